@@ -1,0 +1,12 @@
+"""ORACLE — test infrastructure only.
+
+A plain, slow FP64 CPU implementation of what the nested-mesh volume-potential
+path computes, written from the paper (Groth et al., arXiv 2011.03009).  Only
+the tests, the entry point's smoke check and the benchmark's CPU-baseline leg
+may import it; the HIP library never does, and the two share no code.
+
+Parity status of each function is stated in its docstring; none is
+"parity unpinned" except where noted there.
+"""
+
+from .core import *  # noqa: F401,F403
