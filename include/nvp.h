@@ -1,0 +1,171 @@
+/*
+ * nvp — nested-mesh Helmholtz volume potentials on MI355X (gfx950).
+ *
+ * C ABI of the library that computes the higher harmonics p_2..p_n of the
+ * weakly nonlinear (Westervelt) field of a focused-ultrasound source, each on
+ * its own voxel grid, following Groth et al., "Accelerating frequency-domain
+ * numerical methods for weakly nonlinear focused ultrasound using nested
+ * meshes" (arXiv 2011.03009):
+ *
+ *   harmonic cascade  (Section 2, eq. cascade_2; Section 3, eqs. harm2-harm5)
+ *       p_n = C_n * int_{D_n} G_{k_n}(x, y) f_n(y) dy,
+ *       f_n = sum_{m=1}^{n-1} p_m p_{n-m},  C_n = -beta w^2 n^2 / (2 rho0 c0^4),
+ *       k_n = n w / c0 + i alpha(n w)  (eq. power_law);
+ *   quadrature        (Section 3.1, eq. quad): midpoint rule off the diagonal,
+ *       equal-volume sphere on the self voxel; the Toeplitz operator is applied
+ *       through a circulant embedding and 3-D FFTs;
+ *   nested meshes     (Section 6): harmonic n on its own box and spacing; lower
+ *       harmonics are interpolated onto the new mesh (step 2(a)).
+ *
+ * Conventions for every call:
+ *   - Returns an nvp_status; never throws.  On failure the context's
+ *     nvp_last_error() holds a message.
+ *   - Field buffers are DEVICE pointers owned by the caller, C order [n0][n1][n2]
+ *     (z fastest), complex interleaved re/im: complex64 for NVP_C64,
+ *     complex128 for NVP_C128.
+ *   - execute* calls only enqueue work on the context's stream and return;
+ *     asynchronous faults surface at nvp_ctx_sync().
+ *   - Contexts and plans are owned by the library and released only by their
+ *     _destroy call.  A plan is bound to its context's device and stream.
+ */
+#ifndef NVP_H
+#define NVP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nvp_status;
+#define NVP_OK 0
+#define NVP_E_INVALID 1     /* bad argument: null pointer, h <= 0, n < 1, bad precision, ... */
+#define NVP_E_NOMEM 2       /* device or host allocation failed; no partial state kept */
+#define NVP_E_HIP 3         /* a HIP runtime call or kernel launch failed */
+#define NVP_E_UNSUPPORTED 4 /* valid request outside what this build handles (an axis beyond the compiled circulant lengths) */
+#define NVP_E_STATE 5       /* call out of order (e.g. timing read while disabled) */
+
+typedef enum { NVP_C64 = 0, NVP_C128 = 1 } nvp_prec;
+
+/* Medium (Section 2; medium table of Section 3.2).  alpha0_db is the
+ * attenuation in dB/m at 1 MHz and eta its frequency exponent, so that
+ * alpha(f) = alpha0_db (f / 1 MHz)^eta / (20 log10 e) Np/m. */
+typedef struct {
+    double c0, rho0, beta, alpha0_db, eta;
+} nvp_medium;
+
+/* Uniform voxel grid: centre(i, j, k) = origin + (i, j, k) h. */
+typedef struct {
+    double origin[3];
+    double h;
+    int64_t n[3];
+} nvp_grid;
+
+typedef struct nvp_ctx nvp_ctx;
+typedef struct nvp_plan nvp_plan;
+
+/* ---- status and context ------------------------------------------------ */
+
+const char *nvp_status_str(nvp_status s);
+/* Last error message of a context (empty string if none); ctx may be NULL
+ * for errors of nvp_ctx_create. */
+const char *nvp_last_error(const nvp_ctx *ctx);
+
+/* device: HIP device ordinal; hip_stream: a hipStream_t (NULL = the null
+ * stream) on which all work of this context is enqueued. */
+nvp_status nvp_ctx_create(int device, void *hip_stream, nvp_ctx **out);
+nvp_status nvp_ctx_destroy(nvp_ctx *ctx);
+/* Waits for the context's stream; reports asynchronous HIP errors. */
+nvp_status nvp_ctx_sync(nvp_ctx *ctx);
+
+/* ---- constants and grids (host only) ------------------------------------ */
+
+/* k_n = 2 pi n f0 / c0 + i alpha(n f0)  (Section 2, eq. power_law with n w). */
+nvp_status nvp_wavenumber(const nvp_medium *med, double f0, int n, double *k_re, double *k_im);
+/* C_n = -beta (2 pi f0)^2 n^2 / (2 rho0 c0^4)  (eqs. cascade_2 and harm2-harm5). */
+nvp_status nvp_cascade_constant(const nvp_medium *med, double f0, int n, double *c);
+/* delta x = c0 / (n f0 n_w): n_w voxels per own wavelength (Section 3.3 uses 6). */
+nvp_status nvp_spacing(const nvp_medium *med, double f0, int n, int n_w, double *h);
+/* Grid with n[a] voxels per axis whose voxel i_f[a] is centred on focus[a]. */
+nvp_status nvp_grid_from_counts(const double focus[3], double h, const int64_t n[3],
+                                const int64_t i_f[3], nvp_grid *out);
+/* Grid covering the cuboid [lo, hi] at spacing h with the focus on a voxel
+ * centre: n = max(1, floor((hi - lo)/h + 1/2)), i_f = floor((focus - lo)/h + 1/2).
+ * i_f_out may be NULL. */
+nvp_status nvp_grid_from_box(const double focus[3], const double lo[3], const double hi[3],
+                             double h, nvp_grid *out, int64_t i_f_out[3]);
+/* Box D_n of the paper's rule of thumb (Section 5): D_2 = [l - L, l + d] x [-R, R]^2
+ * with L = sqrt(l^2 - R^2) - eps (eq. domain); for n > 2 the pre-focal length
+ * and the width are scaled by lambda_n / lambda_2 = 2 / n, d is kept. */
+nvp_status nvp_rule_of_thumb_box(int n, double l, double R, double d, double eps,
+                                 double lo[3], double hi[3]);
+/* Transfer table of one axis (Section 6, step 2(a)): for target centres
+ * dst_origin + i dst_h, i < dst_n, the first source index base[i] and the
+ * order + 1 weights w[i*(order+1) + j] of source nodes base[i] + j, for a
+ * source axis src_origin + j src_h, j < src_n.  Targets are clamped into the
+ * source hull; order 1: linear (the paper's choice), order 3: four-point
+ * Lagrange with the stencil shifted inward at the edges.  Host buffers.
+ * NVP_E_INVALID if src_n < order + 1. */
+nvp_status nvp_transfer_axis(double dst_origin, double dst_h, int64_t dst_n, double src_origin, double src_h,
+                             int64_t src_n, int order, int32_t *base, double *w);
+/* Circulant length used for an axis of n voxels: the smallest supported
+ * M >= 2 n - 1 (the embedding of Section 3.1 is exact for any such M). */
+nvp_status nvp_circulant_size(int64_t n, int64_t *m);
+
+/* ---- the raw operator ---------------------------------------------------- */
+
+/* u = -sum_j K(x_i - x_j) f_j on grid g (eqs. vol_pot_approx and quad), any
+ * complex wavenumber k with Im k >= 0.  f_dev and u_dev are device buffers
+ * of g->n[0]*g->n[1]*g->n[2] complex elements (may not alias).  The context
+ * keeps the kernel spectrum of the last (k, g, prec) for reuse. */
+nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nvp_grid *g,
+                                const void *f_dev, void *u_dev, nvp_prec prec);
+
+/* ---- the nested-mesh cascade (Section 6) ----------------------------------- */
+
+/* Plan harmonics 2..n_harm.  g1: grid of the incident field p_1 (Section 3.2);
+ * gn[0..n_harm-2]: grids of p_2..p_n_harm.  transfer_order: 1 = trilinear
+ * (the paper's choice), 3 = tricubic Lagrange (the higher-order option the
+ * paper recommends); target centres are clamped into the source grid's hull,
+ * and a field on the very grid it is needed on is used as is.  Every axis
+ * of a source grid needs at least transfer_order + 1 voxels, and every axis
+ * a circulant length (nvp_circulant_size; up to 640 voxels in this build). */
+nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int n_harm,
+                            const nvp_grid *g1, const nvp_grid *gn, nvp_prec prec,
+                            int transfer_order, nvp_plan **out);
+/* Device bytes held by the plan (work buffers and kernel spectra). */
+nvp_status nvp_plan_workspace_bytes(const nvp_plan *plan, size_t *bytes);
+/* 1 (default): keep each harmonic's kernel spectrum after its first use;
+ * 0: tabulate and transform the kernel again on every execution. */
+nvp_status nvp_plan_set_kernel_cache(nvp_plan *plan, int enable);
+/* One harmonic: fields[m-1] = p_m on its grid for m = 1..n-1; writes p_n. */
+nvp_status nvp_execute_harmonic(nvp_plan *plan, int n, const void *const *fields, void *pn_dev);
+/* The whole cascade: p1 in, pn_dev[i] = p_{i+2} out, computed in order. */
+nvp_status nvp_execute_cascade(nvp_plan *plan, const void *p1_dev, void *const *pn_dev);
+nvp_status nvp_plan_destroy(nvp_plan *plan);
+
+/* ---- timing of the plan's kernels ---------------------------------------- */
+
+/* Kinds of kernel timed by nvp_plan_get_timing. */
+#define NVP_T_KTAB 0   /* kernel tabulation, FP64 */
+#define NVP_T_KFFT 1   /* kernel spectrum: three FP64 FFT passes and downcast */
+#define NVP_T_XFWD 2   /* transfer + source build fused into the forward x pass */
+#define NVP_T_YFWD 3   /* forward y pass */
+#define NVP_T_ZCONV 4  /* z pass: forward FFT, spectral multiply, inverse FFT */
+#define NVP_T_YINV 5   /* inverse y pass */
+#define NVP_T_XINV 6   /* inverse x pass with the C_n / M scale */
+#define NVP_T_KINDS 7
+
+/* enable != 0: bracket every kernel launch with HIP events on the plan's
+ * stream from now on (adds no device work between kernels). */
+nvp_status nvp_plan_set_timing(nvp_plan *plan, int enable);
+/* Waits for the recorded events; ms[k] = summed kernel time of kind k and
+ * count[k] = launches since the last call (both arrays of n_kinds entries);
+ * then clears the record. */
+nvp_status nvp_plan_get_timing(nvp_plan *plan, double *ms, int64_t *count, int n_kinds);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NVP_H */

@@ -53,6 +53,7 @@ static void kernel_at(int64_t dx, int64_t dy, int64_t dz, double h, double kr, d
 /* Tabulate K for offsets [0,n0) x [0,n1) x [0,n2) (C order, interleaved). */
 int oracle_kernel_table(const int64_t n[3], double h, double kr, double ki, double *tab)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t a = 0; a < n[0]; ++a)
         for (int64_t b = 0; b < n[1]; ++b)
             for (int64_t c = 0; c < n[2]; ++c) {

@@ -1,0 +1,10 @@
+"""nvp: nested-mesh Helmholtz volume potentials on MI355X.
+
+The computation lives in the HIP library lib/libnvp.so (C ABI in
+include/nvp.h); this package is its Python binding.
+"""
+
+from . import nvp  # noqa: F401
+from .nvp import (NVP_C64, NVP_C128, CascadePlan, Context, NvpError, cascade_constant,  # noqa: F401
+                  circulant_size, grid, grid_from_box, grid_from_counts, rule_of_thumb_box, spacing,
+                  volume_potential, wavenumber)

@@ -1,0 +1,280 @@
+// Stockham autosort mixed-radix FFT engine for gfx950 (64-wide wavefronts).
+//
+// One column of length L is transformed by P = L / E threads, each holding E
+// complex values in registers.  Stage s (radix r_s, Ns = r_0 ... r_{s-1})
+// reads butterfly b's inputs at b + q L / r_s, twiddles input q by
+// W^(j q L / (Ns r_s)) with j = b mod Ns and W = exp(-+ 2 pi i / L), does a
+// radix-r_s DFT, and writes output p to (b / Ns) Ns r_s + j + p Ns.  That
+// ordering is self-sorting: the last stage writes natural order, so its
+// outputs go straight to global memory (or to a fused consumer), and the first
+// stage reads straight from global memory (or from a fused producer).  Only
+// the stages in between exchange data through LDS.
+//
+// Forward transforms use sign -1 (X_k = sum x_m e^{-2 pi i k m / L}), inverse
+// +1, unnormalised.  Twiddles come from a table W^e, e in [0, L), computed on
+// the host in extended precision and rounded once to the working precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nvp {
+
+template <typename R> struct cx_sel;
+template <> struct cx_sel<float> { using type = float2; };
+template <> struct cx_sel<double> { using type = double2; };
+template <typename R> using cx = typename cx_sel<R>::type;
+
+template <typename R> __device__ __forceinline__ cx<R> mk(R a, R b) { cx<R> r; r.x = a; r.y = b; return r; }
+template <typename R> __device__ __forceinline__ cx<R> czero() { return mk<R>(R(0), R(0)); }
+template <typename R> __device__ __forceinline__ cx<R> cadd(cx<R> a, cx<R> b) { return mk<R>(a.x + b.x, a.y + b.y); }
+template <typename R> __device__ __forceinline__ cx<R> csub(cx<R> a, cx<R> b) { return mk<R>(a.x - b.x, a.y - b.y); }
+template <typename R> __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+    return mk<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename R> __device__ __forceinline__ cx<R> cscale(cx<R> a, R s) { return mk<R>(a.x * s, a.y * s); }
+// s * i * a for s = +-1
+template <typename R> __device__ __forceinline__ cx<R> crot(cx<R> a, R s) { return mk<R>(-s * a.y, s * a.x); }
+
+// ---------------------------------------------------------------- small DFTs
+// y_p = sum_q v_q exp(s 2 pi i p q / N), in place on v[0..N-1].
+
+template <int N, typename R> struct Dft;
+
+template <typename R> struct Dft<2, R> {
+    static __device__ __forceinline__ void run(cx<R> *v, R) {
+        cx<R> a = v[0], b = v[1];
+        v[0] = cadd<R>(a, b);
+        v[1] = csub<R>(a, b);
+    }
+};
+
+template <typename R> struct Dft<4, R> {
+    static __device__ __forceinline__ void run(cx<R> *v, R s) {
+        cx<R> a = cadd<R>(v[0], v[2]), b = csub<R>(v[0], v[2]);
+        cx<R> c = cadd<R>(v[1], v[3]), d = crot<R>(csub<R>(v[1], v[3]), s);
+        v[0] = cadd<R>(a, c);
+        v[2] = csub<R>(a, c);
+        v[1] = cadd<R>(b, d);
+        v[3] = csub<R>(b, d);
+    }
+};
+
+// Even/odd split: y_p = E_p + W^p O_p, y_{p+N/2} = E_p - W^p O_p.
+template <typename R> struct Dft<8, R> {
+    static __device__ __forceinline__ void run(cx<R> *v, R s) {
+        cx<R> e[4] = {v[0], v[2], v[4], v[6]};
+        cx<R> o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<4, R>::run(e, s);
+        Dft<4, R>::run(o, s);
+        const R c = R(0.707106781186547524400844362105);
+        o[1] = cmul<R>(o[1], mk<R>(c, s * c));
+        o[2] = crot<R>(o[2], s);
+        o[3] = cmul<R>(o[3], mk<R>(-c, s * c));
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            v[p] = cadd<R>(e[p], o[p]);
+            v[p + 4] = csub<R>(e[p], o[p]);
+        }
+    }
+};
+
+template <typename R> struct Dft<16, R> {
+    static __device__ __forceinline__ void run(cx<R> *v, R s) {
+        cx<R> e[8], o[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            e[i] = v[2 * i];
+            o[i] = v[2 * i + 1];
+        }
+        Dft<8, R>::run(e, s);
+        Dft<8, R>::run(o, s);
+        const R c1 = R(0.923879532511286756128183189397);  // cos(pi/8)
+        const R s1 = R(0.382683432365089771728459984030);  // sin(pi/8)
+        const R c2 = R(0.707106781186547524400844362105);
+        o[1] = cmul<R>(o[1], mk<R>(c1, s * s1));
+        o[2] = cmul<R>(o[2], mk<R>(c2, s * c2));
+        o[3] = cmul<R>(o[3], mk<R>(s1, s * c1));
+        o[4] = crot<R>(o[4], s);
+        o[5] = cmul<R>(o[5], mk<R>(-s1, s * c1));
+        o[6] = cmul<R>(o[6], mk<R>(-c2, s * c2));
+        o[7] = cmul<R>(o[7], mk<R>(-c1, s * s1));
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            v[p] = cadd<R>(e[p], o[p]);
+            v[p + 8] = csub<R>(e[p], o[p]);
+        }
+    }
+};
+
+// cos and sin of 2 pi k / N for k = 1..(N-1)/2 (N = 3, 5, 7).
+__host__ __device__ constexpr double odd_cos(int N, int k) {
+    return N == 3 ? -0.5
+         : N == 5 ? (k == 1 ? 0.309016994374947424102293417183 : -0.809016994374947424102293417183)
+         : (k == 1 ? 0.623489801858733530525004884004
+            : k == 2 ? -0.222520933956314404288902564497 : -0.900968867902419126236102319507);
+}
+__host__ __device__ constexpr double odd_sin(int N, int k) {
+    return N == 3 ? 0.866025403784438646763723170753
+         : N == 5 ? (k == 1 ? 0.951056516295153572116439333379 : 0.587785252292473129168705954639)
+         : (k == 1 ? 0.781831482468029808708444526674
+            : k == 2 ? 0.974927912181823607018131682994 : 0.433883739117558120475768332849);
+}
+
+// Odd N: pair v_q with v_{N-q}:  y_p = v_0 + sum_q a_q cos(2 pi p q / N) +- s i sum_q b_q sin(...).
+template <int N, typename R> struct DftOdd {
+    static __device__ __forceinline__ void run(cx<R> *v, R s) {
+        constexpr int H = (N - 1) / 2;
+        cx<R> a[H], b[H];
+        cx<R> y0 = v[0];
+#pragma unroll
+        for (int q = 1; q <= H; ++q) {
+            a[q - 1] = cadd<R>(v[q], v[N - q]);
+            b[q - 1] = csub<R>(v[q], v[N - q]);
+            y0 = cadd<R>(y0, a[q - 1]);
+        }
+        cx<R> out[N];
+#pragma unroll
+        for (int p = 1; p <= H; ++p) {
+            cx<R> A = v[0], B = czero<R>();
+#pragma unroll
+            for (int q = 1; q <= H; ++q) {
+                const int idx = (p * q) % N;
+                const R cv = R(idx <= H ? odd_cos(N, idx) : odd_cos(N, N - idx));
+                const R sv = R(idx <= H ? odd_sin(N, idx) : -odd_sin(N, N - idx));
+                A = cadd<R>(A, cscale<R>(a[q - 1], cv));
+                B = cadd<R>(B, cscale<R>(b[q - 1], sv));
+            }
+            cx<R> iB = crot<R>(B, s);
+            out[p] = cadd<R>(A, iB);
+            out[N - p] = csub<R>(A, iB);
+        }
+        v[0] = y0;
+#pragma unroll
+        for (int p = 1; p < N; ++p) v[p] = out[p];
+    }
+};
+template <typename R> struct Dft<3, R> : DftOdd<3, R> {};
+template <typename R> struct Dft<5, R> : DftOdd<5, R> {};
+template <typename R> struct Dft<7, R> : DftOdd<7, R> {};
+
+// ---------------------------------------------------------------- plans
+
+struct PlanDesc {
+    int S;      // number of stages
+    int r[6];   // radix of each stage
+    int E;      // complex values per thread (a multiple of every radix)
+};
+
+// Radix plans of the supported lengths.  The first stage reads global memory
+// directly and the last writes it, so fewer stages mean fewer LDS round trips.
+__host__ __device__ constexpr PlanDesc plan_for(int L) {
+    switch (L) {
+    case 16: return PlanDesc{1, {16, 0, 0, 0, 0, 0}, 16};
+    case 32: return PlanDesc{2, {2, 16, 0, 0, 0, 0}, 16};
+    case 48: return PlanDesc{3, {3, 4, 4, 0, 0, 0}, 12};
+    case 64: return PlanDesc{2, {4, 16, 0, 0, 0, 0}, 16};
+    case 96: return PlanDesc{3, {3, 4, 8, 0, 0, 0}, 24};
+    case 128: return PlanDesc{2, {8, 16, 0, 0, 0, 0}, 16};
+    case 160: return PlanDesc{3, {5, 4, 8, 0, 0, 0}, 40};
+    case 192: return PlanDesc{3, {3, 8, 8, 0, 0, 0}, 24};
+    case 256: return PlanDesc{2, {16, 16, 0, 0, 0, 0}, 16};
+    case 320: return PlanDesc{3, {5, 8, 8, 0, 0, 0}, 40};
+    case 384: return PlanDesc{4, {3, 8, 4, 4, 0, 0}, 24};
+    case 448: return PlanDesc{4, {7, 4, 4, 4, 0, 0}, 28};
+    case 512: return PlanDesc{3, {8, 8, 8, 0, 0, 0}, 16};
+    case 640: return PlanDesc{4, {5, 8, 4, 4, 0, 0}, 40};
+    case 768: return PlanDesc{4, {3, 4, 8, 8, 0, 0}, 24};
+    case 896: return PlanDesc{5, {7, 4, 4, 4, 2, 0}, 28};
+    case 1024: return PlanDesc{3, {16, 8, 8, 0, 0, 0}, 32};
+    case 1280: return PlanDesc{4, {5, 8, 8, 4, 0, 0}, 40};
+    default: return PlanDesc{0, {0, 0, 0, 0, 0, 0}, 0};
+    }
+}
+
+__host__ __device__ constexpr int plan_threads(int L) { return plan_for(L).E ? L / plan_for(L).E : 0; }
+
+// ---------------------------------------------------------------- engine
+
+template <typename R, int L> struct Fft {
+    static constexpr PlanDesc D = plan_for(L);
+    static constexpr int S = D.S;
+    static constexpr int E = D.E;
+    static constexpr int P = L / E;  // threads per column
+    static_assert(S > 0, "unsupported FFT length");
+
+    template <int s> static constexpr int ns() {
+        int n = 1;
+        for (int i = 0; i < s; ++i) n *= D.r[i];
+        return n;
+    }
+
+    template <int r> static __device__ __forceinline__ void bflies(cx<R> *v, R sgn) {
+#pragma unroll
+        for (int i = 0; i < E / r; ++i) Dft<r, R>::run(v + i * r, sgn);
+    }
+
+    // Transform this thread's share of one column.
+    //   ld(m)     -> input element m (first stage)
+    //   st(m, x)  <- output element m (last stage, natural order)
+    //   lds(m)    -> reference to element m of this column's LDS slot
+    // LDS_IN: ld reads the same LDS slot, so wait before overwriting it.
+    template <bool LDS_IN, class Ld, class St, class Lds>
+    static __device__ __forceinline__ void run(int t, const cx<R> *__restrict__ tw, R sgn, Ld ld, St st, Lds lds) {
+        cx<R> v[E];
+        constexpr int r0 = D.r[0];
+#pragma unroll
+        for (int i = 0; i < E / r0; ++i) {
+            const int b = t + i * P;
+#pragma unroll
+            for (int q = 0; q < r0; ++q) v[i * r0 + q] = ld(b + q * (L / r0));
+        }
+        if constexpr (LDS_IN) __syncthreads();
+        bflies<r0>(v, sgn);
+        next<0>(v, t, tw, sgn, st, lds);
+    }
+
+    template <int s, class St, class Lds>
+    static __device__ __forceinline__ void next(cx<R> *v, int t, const cx<R> *__restrict__ tw, R sgn, St st,
+                                                Lds lds) {
+        constexpr int r = D.r[s];
+        constexpr int Ns = ns<s>();
+        if constexpr (s == S - 1) {
+#pragma unroll
+            for (int i = 0; i < E / r; ++i) {
+                const int b = t + i * P;
+#pragma unroll
+                for (int p = 0; p < r; ++p) st(b + p * (L / r), v[i * r + p]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < E / r; ++i) {
+                const int b = t + i * P;
+                const int base = (b / Ns) * Ns * r + (b % Ns);
+#pragma unroll
+                for (int p = 0; p < r; ++p) lds(base + p * Ns) = v[i * r + p];
+            }
+            __syncthreads();
+            constexpr int r1 = D.r[s + 1];
+            constexpr int Ns1 = Ns * r;
+            constexpr int tstep = L / (Ns1 * r1);
+#pragma unroll
+            for (int i = 0; i < E / r1; ++i) {
+                const int b = t + i * P;
+                const int j = b % Ns1;
+                v[i * r1] = lds(b);
+#pragma unroll
+                for (int q = 1; q < r1; ++q) {
+                    cx<R> w = tw[j * q * tstep];
+                    if (sgn > R(0)) w.y = -w.y;
+                    v[i * r1 + q] = cmul<R>(lds(b + q * (L / r1)), w);
+                }
+            }
+            __syncthreads();
+            bflies<r1>(v, sgn);
+            next<s + 1>(v, t, tw, sgn, st, lds);
+        }
+    }
+};
+
+}  // namespace nvp

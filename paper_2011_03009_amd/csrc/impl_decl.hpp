@@ -1,0 +1,16 @@
+// Declarations of the per-length launcher templates.  Each length's
+// instantiations live in their own translation unit (inst.hip compiled with
+// -DNVP_L=<length>), so the kernels build in parallel.
+#pragma once
+
+#include "launch.hpp"
+
+namespace nvp {
+
+template <typename R, typename Rout, int L> hipError_t strided_impl(const StridedArgs &, const void *, hipStream_t);
+template <typename R, int L> hipError_t contig_impl(const StridedArgs &, const void *, hipStream_t);
+template <typename R, int L> hipError_t xsrc_impl(const SourceArgs &, const void *, hipStream_t);
+template <typename R, int L>
+hipError_t zconv_impl(void *, const void *, int64_t, int64_t, int, const void *, hipStream_t);
+
+}  // namespace nvp

@@ -1,0 +1,227 @@
+// Pass kernels of the pruned 3-D circulant convolution.
+//
+// Array layout: C order [x][y][z], z fastest.  For harmonic grid N = (Nx, Ny, Nz)
+// and circulant M = (Mx, My, Mz) the five passes are
+//   x fwd : source [Nx][Ny][Nz] (built on the fly)     -> A [Mx][Ny][Nz]
+//   y fwd : A                                           -> B [Mx][My][Nz]
+//   z     : B, per (kx, ky) pencil: FFT_z, times K^, IFFT_z, in place
+//   y inv : B                                           -> A [Mx][Ny][Nz]
+//   x inv : A, times C_n / (Mx My Mz)                    -> p_n [Nx][Ny][Nz]
+// Only the first N inputs of a forward transform are nonzero and only the
+// first N outputs of an inverse transform are kept, so neither the zero half
+// of the padded source nor the discarded half of the result touches memory.
+#pragma once
+
+#include "fft_core.hpp"
+#include "launch.hpp"
+
+namespace nvp {
+
+// ---------------------------------------------------------------- loaders
+
+// Element m of column (o, col) at p[o*os + m*ms + col].  Pruned: zero for
+// m >= n.  Mirrored: the column holds entries 0..L/2 of an even sequence of
+// length L, and entry m > L/2 equals entry L - m.
+template <typename R, int L> struct LdPlain {
+    const cx<R> *__restrict__ p;
+    int64_t os, ms;
+    int n;
+    int mirror;
+    __device__ __forceinline__ cx<R> operator()(int64_t o, int64_t col, int m) const {
+        if (mirror) {
+            const int mm = m <= L / 2 ? m : L - m;
+            return p[o * os + (int64_t)mm * ms + col];
+        }
+        return m < n ? p[o * os + (int64_t)m * ms + col] : czero<R>();
+    }
+};
+
+template <typename R, typename Rout> __device__ __forceinline__ cx<Rout> cvt(cx<R> v);
+template <> __device__ __forceinline__ float2 cvt<float, float>(float2 v) { return v; }
+template <> __device__ __forceinline__ double2 cvt<double, double>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 cvt<double, float>(double2 v) {
+    return make_float2((float)v.x, (float)v.y);
+}
+
+// Stores element m < n of column (o, col) times a real scale.
+template <typename R, typename Rout> struct StPlain {
+    cx<Rout> *__restrict__ p;
+    int64_t os, ms;
+    int n;
+    R scale;
+    __device__ __forceinline__ void operator()(int64_t o, int64_t col, int m, cx<R> v) const {
+        if (m < n) p[o * os + (int64_t)m * ms + col] = cvt<R, Rout>(cscale<R>(v, scale));
+    }
+};
+
+// Source term of harmonic n fused into the forward x pass:
+//   f_n(x) = sum_{m=1}^{n-1} T_m[p_m](x) T_{n-m}[p_{n-m}](x),
+// where T_m interpolates p_m from its own grid with separable K-point weights
+// (K = 2 linear, K = 4 cubic Lagrange) from per-axis tables, or reads it
+// directly when p_m lives on the target grid.
+template <typename R> struct FieldDev {
+    const cx<R> *__restrict__ p;
+    int64_t s0, s1;                      // strides of the field's own grid
+    const int *__restrict__ b[3];        // base source index per target index, per axis
+    const R *__restrict__ w[3];          // K weights per target index, per axis
+    int identity;
+};
+
+template <typename R, int K> struct LdSource {
+    FieldDev<R> f[NVP_MAX_FIELDS];
+    int nf;     // n - 1 fields
+    int Nx, Nz; // target grid (Ny implied by the column count)
+
+    __device__ __forceinline__ cx<R> interp(const FieldDev<R> &g, int ix, int iy, int iz) const {
+        if (g.identity) return g.p[ix * g.s0 + (int64_t)iy * g.s1 + iz];
+        const int bx = g.b[0][ix], by = g.b[1][iy], bz = g.b[2][iz];
+        R wx[K], wy[K], wz[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            wx[a] = g.w[0][ix * K + a];
+            wy[a] = g.w[1][iy * K + a];
+            wz[a] = g.w[2][iz * K + a];
+        }
+        cx<R> acc = czero<R>();
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            cx<R> ay = czero<R>();
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                const cx<R> *row = g.p + (int64_t)(bx + a) * g.s0 + (int64_t)(by + c) * g.s1 + bz;
+                cx<R> az = czero<R>();
+#pragma unroll
+                for (int d = 0; d < K; ++d) az = cadd<R>(az, cscale<R>(row[d], wz[d]));
+                ay = cadd<R>(ay, cscale<R>(az, wy[c]));
+            }
+            acc = cadd<R>(acc, cscale<R>(ay, wx[a]));
+        }
+        return acc;
+    }
+
+    // f_n at target voxel (ix, iy, iz)
+    __device__ __forceinline__ cx<R> value(int ix, int iy, int iz) const {
+        cx<R> v[NVP_MAX_FIELDS];
+#pragma unroll
+        for (int i = 0; i < NVP_MAX_FIELDS; ++i) v[i] = i < nf ? interp(f[i], ix, iy, iz) : czero<R>();
+        cx<R> s = czero<R>();
+#pragma unroll
+        for (int a = 0; a < NVP_MAX_FIELDS; ++a)
+#pragma unroll
+            for (int b = 0; b < NVP_MAX_FIELDS; ++b)
+                if (a + b == nf - 1) s = cadd<R>(s, cmul<R>(v[a], v[b]));
+        return s;
+    }
+};
+
+// ---------------------------------------------------------------- kernels
+
+extern __shared__ __align__(16) unsigned char nvp_smem[];
+
+// Columns strided by `ms` with T consecutive columns (contiguous in memory)
+// per workgroup: lanes run over columns first, so every row access of a wave
+// reads T * sizeof(complex) contiguous bytes.  grid = (ceil(inner / T), outer).
+template <typename R, int L, int T, class Ld, class St>
+__global__ void __launch_bounds__(T *plan_threads(L))
+k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, R sgn, int64_t inner) {
+    using F = Fft<R, L>;
+    cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
+    const int tid = threadIdx.x, c = tid % T, t = tid / T;
+    const int64_t col = (int64_t)blockIdx.x * T + c;
+    const int64_t o = blockIdx.y;
+    const bool act = col < inner;
+    F::template run<false>(
+        t, tw, sgn, [&](int m) { return act ? ld(o, col, m) : czero<R>(); },
+        [&](int m, cx<R> v) {
+            if (act) st(o, col, m, v);
+        },
+        [&](int m) -> cx<R> & { return lds[m * T + c]; });
+}
+
+// Forward x pass with the source build fused in front: each thread first
+// writes f_n for its share of the column's Nx voxels into the column's LDS
+// slot (a rolled loop, so the interpolation code exists once), then the FFT
+// reads its first stage from there.  Column col = iy * Nz + iz.
+template <typename R, int L, int T, int K, class St>
+__global__ void __launch_bounds__(T *plan_threads(L))
+k_xsrc(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t inner) {
+    using F = Fft<R, L>;
+    cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
+    const int tid = threadIdx.x, c = tid % T, t = tid / T;
+    const int64_t col = (int64_t)blockIdx.x * T + c;
+    const bool act = col < inner;
+    const int iy = act ? (int)(col / src.Nz) : 0, iz = act ? (int)(col % src.Nz) : 0;
+    const int Nx = src.Nx;
+#pragma unroll 1
+    for (int m = t; m < Nx; m += F::P) lds[m * T + c] = act ? src.value(m, iy, iz) : czero<R>();
+    __syncthreads();
+    F::template run<true>(
+        t, tw, R(-1), [&](int m) { return m < Nx ? lds[m * T + c] : czero<R>(); },
+        [&](int m, cx<R> v) {
+            if (act) st(0, col, m, v);
+        },
+        [&](int m) -> cx<R> & { return lds[m * T + c]; });
+}
+
+// Contiguous columns (pencils of stride 1), PW pencils per workgroup; lanes
+// run along the pencil.  Column `col` starts at col * pitch.
+template <typename R, int L, int PW, class Ld, class St>
+__global__ void __launch_bounds__(PW *plan_threads(L))
+k_contig(Ld ld, St st, const cx<R> *__restrict__ tw, R sgn, int64_t n_cols) {
+    using F = Fft<R, L>;
+    constexpr int PAD = 1;
+    cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
+    const int tid = threadIdx.x, t = tid % F::P, c = tid / F::P;
+    const int64_t col = (int64_t)blockIdx.x * PW + c;
+    const bool act = col < n_cols;
+    cx<R> *my = lds + c * (L + PAD);
+    F::template run<false>(
+        t, tw, sgn, [&](int m) { return act ? ld(0, col, m) : czero<R>(); },
+        [&](int m, cx<R> v) {
+            if (act) st(0, col, m, v);
+        },
+        [&](int m) -> cx<R> & { return my[m]; });
+}
+
+// The z pass of the convolution.  Workgroup = the up-to-four pencils
+// (kx, ky), (Mx-kx, ky), (kx, My-ky), (Mx-kx, My-ky) that share one row of the
+// kernel spectrum's octant (the embedded kernel is even on every axis, so
+// K^(k) = K^(M - k)).  Each pencil: Nz inputs -> forward FFT of length Mz ->
+// times K^ -> inverse FFT -> first Nz outputs written back in place.
+template <typename R, int L>
+__global__ void __launch_bounds__(4 * plan_threads(L))
+k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int64_t My, int Nz, int64_t Hy,
+        const cx<R> *__restrict__ tw) {
+    using F = Fft<R, L>;
+    constexpr int PAD = 1;
+    constexpr int HZ = L / 2 + 1;
+    cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
+    const int tid = threadIdx.x, t = tid % F::P, j = tid / F::P;
+    const int64_t quad = blockIdx.x;
+    const int64_t kx = quad / Hy, ky = quad % Hy;
+    const int64_t px = (j & 1) ? (Mx - kx) % Mx : kx;
+    const int64_t py = (j & 2) ? (My - ky) % My : ky;
+    const bool act = !(((j & 1) && px == kx) || ((j & 2) && py == ky));
+    cx<R> *pen = buf + (px * My + py) * (int64_t)Nz;
+    const cx<R> *krow = khat + (kx * Hy + ky) * (int64_t)HZ;
+    cx<R> *my = lds + j * (L + PAD);
+    auto slot = [&](int m) -> cx<R> & { return my[m]; };
+    F::template run<false>(
+        t, tw, R(-1), [&](int m) { return (act && m < Nz) ? pen[m] : czero<R>(); },
+        [&](int k, cx<R> v) { my[k] = cmul<R>(v, krow[k <= L / 2 ? k : L - k]); }, slot);
+    __syncthreads();
+    F::template run<true>(
+        t, tw, R(1), [&](int m) { return my[m]; },
+        [&](int m, cx<R> v) {
+            if (act && m < Nz) pen[m] = v;
+        },
+        slot);
+}
+
+// Octant [Hx][Hy][Hz] of the embedded kernel in FP64: K at offset (i, j, k) for
+// i < Nx, j < Ny, k < Nz (equation "quad": h^3 G_k(|d| h), self voxel given),
+// zero beyond (the embedding is exact for M >= 2N - 1).
+__global__ void k_ktab(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Hz, int64_t Nx, int64_t Ny,
+                       int64_t Nz, double h, double kr, double ki, double2 self);
+
+}  // namespace nvp

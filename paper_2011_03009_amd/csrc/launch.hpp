@@ -1,0 +1,74 @@
+// Host-side launchers of the pass kernels (defined in the *.hip files).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define NVP_MAX_FIELDS 7  // harmonics up to 8
+
+// Transform lengths with a compiled radix plan.
+#define NVP_FOR_EACH_LENGTH(X) \
+    X(16) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(448) X(512) X(640) X(768) X(896) \
+    X(1024) X(1280)
+
+namespace nvp {
+
+bool length_supported(int L);
+int threads_per_column(int L);
+
+// Generic strided pass: element m of column (o, col) is read at
+// in[o*in_os + m*in_ms + col] and written to out[o*out_os + m*out_ms + col],
+// col in [0, inner), o in [0, outer).  Inputs: the first n_in (zero beyond),
+// or, with mirror, entries 0..L/2 of an even sequence.  Outputs: the first
+// n_out, times `scale`.  sign = -1 forward, +1 inverse.
+struct StridedArgs {
+    const void *in;
+    int64_t in_os, in_ms;
+    int n_in;
+    int mirror;
+    void *out;
+    int64_t out_os, out_ms;
+    int n_out;
+    double scale;
+    int64_t inner, outer;
+    int sign;
+};
+
+// Field of the fused source build (see LdSource).
+struct FieldArgs {
+    const void *p;
+    int64_t s0, s1;
+    const int *b[3];
+    const void *w[3];  // weights in the working precision
+    int identity;
+};
+
+struct SourceArgs {
+    FieldArgs f[NVP_MAX_FIELDS];
+    int nf;
+    int order;  // 1 or 3
+    int Nx, Nz;
+    void *out;  // A [Mx][Ny][Nz]
+    int64_t out_ms;  // Ny * Nz
+    int64_t inner;   // Ny * Nz
+};
+
+hipError_t launch_strided_c64(int L, const StridedArgs &a, const void *tw, hipStream_t s);
+hipError_t launch_strided_c128(int L, const StridedArgs &a, const void *tw, hipStream_t s);
+// FP64 in, complex64 out (the downcast of the kernel spectrum).
+hipError_t launch_strided_f64_c64(int L, const StridedArgs &a, const void *tw, hipStream_t s);
+// Contiguous pencils (ms = 1, pencil `col` at col * os), FP64.
+hipError_t launch_contig_c128(int L, const StridedArgs &a, const void *tw, hipStream_t s);
+
+hipError_t launch_xsrc_c64(int L, const SourceArgs &a, const void *tw, hipStream_t s);
+hipError_t launch_xsrc_c128(int L, const SourceArgs &a, const void *tw, hipStream_t s);
+
+hipError_t launch_zconv_c64(int L, void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw,
+                            hipStream_t s);
+hipError_t launch_zconv_c128(int L, void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw,
+                             hipStream_t s);
+
+hipError_t launch_ktab(double2 *out, const int64_t H[3], const int64_t N[3], double h, double kr, double ki,
+                       double self_re, double self_im, hipStream_t s);
+
+}  // namespace nvp

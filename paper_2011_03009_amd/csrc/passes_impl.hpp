@@ -1,0 +1,125 @@
+// Launcher templates shared by the per-precision translation units.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace nvp {
+
+// Columns per workgroup of the strided kernels: at least 128 contiguous bytes
+// per row access, about 256 threads per workgroup.
+template <typename R> constexpr int strided_cols(int L) {
+    const int lo = sizeof(R) == 4 ? 16 : 8, hi = sizeof(R) == 4 ? 64 : 32;
+    const int t = 256 / plan_threads(L);
+    return t < lo ? lo : (t > hi ? hi : t);
+}
+
+// Pencils per workgroup of the contiguous kernel: about 256 threads, LDS <= 128 KiB.
+template <typename R> constexpr int contig_pencils(int L) {
+    const int by_threads = 256 / plan_threads(L) > 0 ? 256 / plan_threads(L) : 1;
+    const int by_lds = (int)(131072 / ((L + 1) * (int)sizeof(cx<R>)));
+    const int p = by_threads < by_lds ? by_threads : by_lds;
+    return p > 0 ? p : 1;
+}
+
+template <class K> inline hipError_t allow_lds(K kern, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+template <typename R, typename Rout, int L>
+hipError_t strided_impl(const StridedArgs &a, const void *tw, hipStream_t s) {
+    constexpr int T = strided_cols<R>(L);
+    using Ld = LdPlain<R, L>;
+    using St = StPlain<R, Rout>;
+    Ld ld{static_cast<const cx<R> *>(a.in), a.in_os, a.in_ms, a.n_in, a.mirror};
+    St st{static_cast<cx<Rout> *>(a.out), a.out_os, a.out_ms, a.n_out, (R)a.scale};
+    auto kern = k_strided<R, L, T, Ld, St>;
+    const size_t lds = (size_t)T * L * sizeof(cx<R>);
+    static const hipError_t attr = allow_lds(kern, lds);
+    if (attr != hipSuccess) return attr;
+    dim3 grid((unsigned)((a.inner + T - 1) / T), (unsigned)a.outer);
+    hipLaunchKernelGGL(kern, grid, dim3(T * plan_threads(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
+                       (R)a.sign, a.inner);
+    return hipGetLastError();
+}
+
+template <typename R, int L> hipError_t contig_impl(const StridedArgs &a, const void *tw, hipStream_t s) {
+    constexpr int PW = contig_pencils<R>(L);
+    using Ld = LdPlain<R, L>;
+    using St = StPlain<R, R>;
+    // pencil `col` starts at col * os: map (o = 0, col, m) -> col * os + m
+    Ld ld{static_cast<const cx<R> *>(a.in), 0, 1, a.n_in, a.mirror};
+    St st{static_cast<cx<R> *>(a.out), 0, 1, a.n_out, (R)a.scale};
+    struct LdP {
+        Ld b;
+        int64_t pitch;
+        __device__ cx<R> operator()(int64_t, int64_t col, int m) const { return b(0, col * pitch, m); }
+    };
+    struct StP {
+        St b;
+        int64_t pitch;
+        __device__ void operator()(int64_t, int64_t col, int m, cx<R> v) const { b(0, col * pitch, m, v); }
+    };
+    LdP lp{ld, a.in_os};
+    StP sp{st, a.out_os};
+    auto kern = k_contig<R, L, PW, LdP, StP>;
+    const size_t lds = (size_t)PW * (L + 1) * sizeof(cx<R>);
+    static const hipError_t attr = allow_lds(kern, lds);
+    if (attr != hipSuccess) return attr;
+    dim3 grid((unsigned)((a.inner + PW - 1) / PW));
+    hipLaunchKernelGGL(kern, grid, dim3(PW * plan_threads(L)), lds, s, lp, sp, static_cast<const cx<R> *>(tw),
+                       (R)a.sign, a.inner);
+    return hipGetLastError();
+}
+
+template <typename R, int L, int K> hipError_t xsrc_impl_k(const SourceArgs &a, const void *tw, hipStream_t s) {
+    constexpr int T = strided_cols<R>(L);
+    using Ld = LdSource<R, K>;
+    using St = StPlain<R, R>;
+    Ld ld;
+    for (int i = 0; i < NVP_MAX_FIELDS; ++i) {
+        const FieldArgs &f = a.f[i < a.nf ? i : 0];
+        ld.f[i].p = static_cast<const cx<R> *>(f.p);
+        ld.f[i].s0 = f.s0;
+        ld.f[i].s1 = f.s1;
+        for (int ax = 0; ax < 3; ++ax) {
+            ld.f[i].b[ax] = f.b[ax];
+            ld.f[i].w[ax] = static_cast<const R *>(f.w[ax]);
+        }
+        ld.f[i].identity = f.identity;
+    }
+    ld.nf = a.nf;
+    ld.Nx = a.Nx;
+    ld.Nz = a.Nz;
+    St st{static_cast<cx<R> *>(a.out), 0, a.out_ms, L, R(1)};
+    auto kern = k_xsrc<R, L, T, K, St>;
+    const size_t lds = (size_t)T * L * sizeof(cx<R>);
+    static const hipError_t attr = allow_lds(kern, lds);
+    if (attr != hipSuccess) return attr;
+    dim3 grid((unsigned)((a.inner + T - 1) / T), 1);
+    hipLaunchKernelGGL(kern, grid, dim3(T * plan_threads(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
+                       a.inner);
+    return hipGetLastError();
+}
+
+template <typename R, int L> hipError_t xsrc_impl(const SourceArgs &a, const void *tw, hipStream_t s) {
+    if (a.order == 1) return xsrc_impl_k<R, L, 2>(a, tw, s);
+    if (a.order == 3) return xsrc_impl_k<R, L, 4>(a, tw, s);
+    return hipErrorInvalidValue;
+}
+
+template <typename R, int L>
+hipError_t zconv_impl(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, hipStream_t s) {
+    auto kern = k_zconv<R, L>;
+    const size_t lds = (size_t)4 * (L + 1) * sizeof(cx<R>);
+    static const hipError_t attr = allow_lds(kern, lds);
+    if (attr != hipSuccess) return attr;
+    const int64_t Hx = Mx / 2 + 1, Hy = My / 2 + 1;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(Hx * Hy)), dim3(4 * plan_threads(L)), lds, s,
+                       static_cast<cx<R> *>(buf), static_cast<const cx<R> *>(khat), Mx, My, Nz, Hy,
+                       static_cast<const cx<R> *>(tw));
+    return hipGetLastError();
+}
+
+}  // namespace nvp

@@ -1,0 +1,785 @@
+// Host runtime behind the C ABI of include/nvp.h: contexts, plans, grids,
+// transfer tables, kernel spectra and the launch sequence of each harmonic.
+//
+// Built with -ffp-contract=off: the transfer tables decide integer stencil
+// positions from floating-point coordinates, and that decision is made with
+// plain IEEE double operations in the order written here.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nvp.h"
+#include "launch.hpp"
+
+using nvp::FieldArgs;
+using nvp::SourceArgs;
+using nvp::StridedArgs;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct Twiddle {
+    int L;
+    int dbl;
+    void *dev;
+};
+
+struct VpCache {
+    bool valid = false;
+    double kr = 0, ki = 0;
+    nvp_grid g{};
+    int prec = -1;
+    int64_t M[3]{};
+    void *khat = nullptr, *A = nullptr, *B = nullptr;
+};
+
+}  // namespace
+
+struct nvp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::vector<Twiddle> tw;
+    VpCache vp;
+    size_t max_lds = 0;
+};
+
+namespace {
+
+struct HarmField {
+    int identity = 0;
+    size_t off_b[3]{}, off_w[3]{};  // byte offsets in the plan's table blob
+};
+
+struct Harm {
+    int n = 0;
+    nvp_grid g{};
+    int64_t M[3]{};
+    double kr = 0, ki = 0, Cn = 0;
+    void *khat = nullptr;
+    bool khat_ok = false;
+    HarmField f[NVP_MAX_FIELDS];
+};
+
+struct TimedEvent {
+    int kind;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct nvp_plan {
+    nvp_ctx *ctx = nullptr;
+    nvp_prec prec = NVP_C64;
+    int order = 1;
+    nvp_medium med{};
+    double f0 = 0;
+    int n_harm = 0;
+    nvp_grid g1{};
+    std::vector<Harm> h;
+    void *A = nullptr, *B = nullptr, *tables = nullptr;
+    size_t bytes_A = 0, bytes_B = 0, bytes_tables = 0, bytes_khat = 0;
+    bool cache = true;
+    bool timing = false;
+    std::vector<TimedEvent> events;
+    std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+const char *g_create_err = "";
+std::string g_create_err_buf;
+
+nvp_status fail(nvp_ctx *ctx, nvp_status s, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    else {
+        g_create_err_buf = msg;
+        g_create_err = g_create_err_buf.c_str();
+    }
+    return s;
+}
+
+nvp_status hip_fail(nvp_ctx *ctx, const char *what, hipError_t e) {
+    return fail(ctx, e == hipErrorOutOfMemory ? NVP_E_NOMEM : NVP_E_HIP,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define NVP_HIP(ctx, call)                                       \
+    do {                                                         \
+        hipError_t _e = (call);                                  \
+        if (_e != hipSuccess) return hip_fail((ctx), #call, _e); \
+    } while (0)
+
+size_t csize(nvp_prec p) { return p == NVP_C64 ? 8 : 16; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+bool grid_ok(const nvp_grid *g) {
+    if (!g || !finite_pos(g->h)) return false;
+    for (int a = 0; a < 3; ++a)
+        if (g->n[a] < 1 || !std::isfinite(g->origin[a])) return false;
+    return true;
+}
+
+bool medium_ok(const nvp_medium *m) {
+    return m && finite_pos(m->c0) && finite_pos(m->rho0) && std::isfinite(m->beta) && std::isfinite(m->alpha0_db) &&
+           m->alpha0_db >= 0 && std::isfinite(m->eta);
+}
+
+int64_t nint(double x) { return (int64_t)std::floor(x + 0.5); }
+
+const int kLengths[] = {
+#define X(n) n,
+    NVP_FOR_EACH_LENGTH(X)
+#undef X
+};
+
+int64_t circulant_len(int64_t n) {
+    for (int L : kLengths)
+        if (L >= 2 * n - 1) return L;
+    return -1;
+}
+
+// exp(-2 pi i e / L), e in [0, L), in extended precision, rounded once.
+nvp_status twiddles(nvp_ctx *ctx, int L, bool dbl, const void **out) {
+    for (auto &t : ctx->tw)
+        if (t.L == L && t.dbl == (int)dbl) {
+            *out = t.dev;
+            return NVP_OK;
+        }
+    std::vector<double> hd(2 * (size_t)L);
+    for (int e = 0; e < L; ++e) {
+        long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)e / (long double)L;
+        hd[2 * e] = (double)cosl(ang);
+        hd[2 * e + 1] = (double)-sinl(ang);
+    }
+    void *dev = nullptr;
+    size_t bytes = (size_t)L * (dbl ? 16 : 8);
+    NVP_HIP(ctx, hipMalloc(&dev, bytes));
+    hipError_t e;
+    if (dbl) {
+        e = hipMemcpy(dev, hd.data(), bytes, hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> hf(2 * (size_t)L);
+        for (size_t i = 0; i < hf.size(); ++i) hf[i] = (float)hd[i];
+        e = hipMemcpy(dev, hf.data(), bytes, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return hip_fail(ctx, "twiddle upload", e);
+    }
+    ctx->tw.push_back({L, (int)dbl, dev});
+    *out = dev;
+    return NVP_OK;
+}
+
+void self_cell(double kr, double ki, double h, double *re, double *im) {
+    // (e^{ika} (1 - ika) - 1) / k^2 with a = (3 / (4 pi))^(1/3) h
+    const double a = std::cbrt(3.0 / (4.0 * kPi)) * h;
+    const double ar = kr * a, ai = ki * a;
+    const double mag = std::exp(-ai);
+    const double er = mag * std::cos(ar), ei = mag * std::sin(ar);
+    const double br = 1.0 + ai, bi = -ar;
+    const double nr = er * br - ei * bi - 1.0, ni = er * bi + ei * br;
+    const double k2r = kr * kr - ki * ki, k2i = 2.0 * kr * ki;
+    const double den = k2r * k2r + k2i * k2i;
+    *re = (nr * k2r + ni * k2i) / den;
+    *im = (ni * k2r - nr * k2i) / den;
+}
+
+nvp_status check_grid_lengths(nvp_ctx *ctx, const nvp_grid *g, int64_t M[3]) {
+    for (int a = 0; a < 3; ++a) {
+        M[a] = circulant_len(g->n[a]);
+        if (M[a] < 0)
+            return fail(ctx, NVP_E_UNSUPPORTED,
+                        "axis of " + std::to_string(g->n[a]) + " voxels exceeds the largest compiled circulant length");
+    }
+    return NVP_OK;
+}
+
+// ------------------------------------------------------------------ timing
+
+struct Timer {
+    nvp_plan *p;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer(nvp_plan *plan, int k) : p(plan), kind(k) {
+        if (!p || !p->timing) return;
+        a = take();
+        b = take();
+        if (a && b) (void)hipEventRecord(a, p->ctx->stream);
+    }
+    hipEvent_t take() {
+        if (!p->pool.empty()) {
+            hipEvent_t e = p->pool.back();
+            p->pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    ~Timer() {
+        if (!p || !p->timing || !a || !b) return;
+        (void)hipEventRecord(b, p->ctx->stream);
+        p->events.push_back({kind, a, b});
+    }
+};
+
+// ------------------------------------------------------------------ kernel spectrum
+
+// Octant of the FP64 DFT of the circulant-embedded kernel, stored as
+// [Mx/2+1][My/2+1][Mz/2+1] in the plan precision at `khat`.  `scratch` holds
+// the FP64 octant during the three passes.
+nvp_status kernel_spectrum(nvp_ctx *ctx, nvp_plan *timed, double kr, double ki, const nvp_grid *g,
+                           const int64_t M[3], nvp_prec prec, void *khat, void *scratch) {
+    const int64_t H[3] = {M[0] / 2 + 1, M[1] / 2 + 1, M[2] / 2 + 1};
+    double sr, si;
+    self_cell(kr, ki, g->h, &sr, &si);
+    {
+        Timer t(timed, NVP_T_KTAB);
+        NVP_HIP(ctx, nvp::launch_ktab(static_cast<double2 *>(scratch), H, g->n, g->h, kr, ki, sr, si, ctx->stream));
+    }
+    Timer t(timed, NVP_T_KFFT);
+    const void *tw;
+    nvp_status st;
+    // z: contiguous rows of Hz entries of an even sequence of length Mz
+    if ((st = twiddles(ctx, (int)M[2], true, &tw))) return st;
+    StridedArgs a{};
+    a.in = scratch; a.in_os = H[2]; a.in_ms = 1; a.n_in = 0; a.mirror = 1;
+    a.out = scratch; a.out_os = H[2]; a.out_ms = 1; a.n_out = (int)H[2];
+    a.scale = 1.0; a.inner = H[0] * H[1]; a.outer = 1; a.sign = -1;
+    NVP_HIP(ctx, nvp::launch_contig_c128((int)M[2], a, tw, ctx->stream));
+    // y
+    if ((st = twiddles(ctx, (int)M[1], true, &tw))) return st;
+    a = StridedArgs{};
+    a.in = scratch; a.in_os = H[1] * H[2]; a.in_ms = H[2]; a.mirror = 1;
+    a.out = scratch; a.out_os = H[1] * H[2]; a.out_ms = H[2]; a.n_out = (int)H[1];
+    a.scale = 1.0; a.inner = H[2]; a.outer = H[0]; a.sign = -1;
+    NVP_HIP(ctx, nvp::launch_strided_c128((int)M[1], a, tw, ctx->stream));
+    // x, written in the plan precision
+    if ((st = twiddles(ctx, (int)M[0], true, &tw))) return st;
+    a = StridedArgs{};
+    a.in = scratch; a.in_os = 0; a.in_ms = H[1] * H[2]; a.mirror = 1;
+    a.out = khat; a.out_os = 0; a.out_ms = H[1] * H[2]; a.n_out = (int)H[0];
+    a.scale = 1.0; a.inner = H[1] * H[2]; a.outer = 1; a.sign = -1;
+    if (prec == NVP_C64) NVP_HIP(ctx, nvp::launch_strided_f64_c64((int)M[0], a, tw, ctx->stream));
+    else NVP_HIP(ctx, nvp::launch_strided_c128((int)M[0], a, tw, ctx->stream));
+    return NVP_OK;
+}
+
+size_t khat_bytes(const int64_t M[3], nvp_prec prec) {
+    return (size_t)(M[0] / 2 + 1) * (M[1] / 2 + 1) * (M[2] / 2 + 1) * csize(prec);
+}
+size_t kscratch_bytes(const int64_t M[3]) { return (size_t)(M[0] / 2 + 1) * (M[1] / 2 + 1) * (M[2] / 2 + 1) * 16; }
+
+// ------------------------------------------------------------------ the five passes
+
+// x fwd (either from `f` directly or from the fused source), y fwd, z conv,
+// y inv, x inv with `scale` into u.
+nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid *g, const int64_t M[3],
+                    const void *khat, void *A, void *B, const void *f, const SourceArgs *src, void *u,
+                    double scale) {
+    const int64_t Nx = g->n[0], Ny = g->n[1], Nz = g->n[2];
+    const int64_t Mx = M[0], My = M[1], Mz = M[2];
+    const bool dbl = prec == NVP_C128;
+    const void *twx, *twy, *twz;
+    nvp_status st;
+    if ((st = twiddles(ctx, (int)Mx, dbl, &twx))) return st;
+    if ((st = twiddles(ctx, (int)My, dbl, &twy))) return st;
+    if ((st = twiddles(ctx, (int)Mz, dbl, &twz))) return st;
+    auto strided = dbl ? nvp::launch_strided_c128 : nvp::launch_strided_c64;
+    {
+        Timer t(timed, NVP_T_XFWD);
+        if (src) {
+            SourceArgs s = *src;
+            s.out = A;
+            s.out_ms = Ny * Nz;
+            s.inner = Ny * Nz;
+            NVP_HIP(ctx, (dbl ? nvp::launch_xsrc_c128 : nvp::launch_xsrc_c64)((int)Mx, s, twx, ctx->stream));
+        } else {
+            StridedArgs a{};
+            a.in = f; a.in_os = 0; a.in_ms = Ny * Nz; a.n_in = (int)Nx;
+            a.out = A; a.out_os = 0; a.out_ms = Ny * Nz; a.n_out = (int)Mx;
+            a.scale = 1.0; a.inner = Ny * Nz; a.outer = 1; a.sign = -1;
+            NVP_HIP(ctx, strided((int)Mx, a, twx, ctx->stream));
+        }
+    }
+    {
+        Timer t(timed, NVP_T_YFWD);
+        StridedArgs a{};
+        a.in = A; a.in_os = Ny * Nz; a.in_ms = Nz; a.n_in = (int)Ny;
+        a.out = B; a.out_os = My * Nz; a.out_ms = Nz; a.n_out = (int)My;
+        a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = -1;
+        NVP_HIP(ctx, strided((int)My, a, twy, ctx->stream));
+    }
+    {
+        Timer t(timed, NVP_T_ZCONV);
+        NVP_HIP(ctx, (dbl ? nvp::launch_zconv_c128 : nvp::launch_zconv_c64)((int)Mz, B, khat, Mx, My, (int)Nz, twz,
+                                                                          ctx->stream));
+    }
+    {
+        Timer t(timed, NVP_T_YINV);
+        StridedArgs a{};
+        a.in = B; a.in_os = My * Nz; a.in_ms = Nz; a.n_in = (int)My;
+        a.out = A; a.out_os = Ny * Nz; a.out_ms = Nz; a.n_out = (int)Ny;
+        a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = 1;
+        NVP_HIP(ctx, strided((int)My, a, twy, ctx->stream));
+    }
+    {
+        Timer t(timed, NVP_T_XINV);
+        StridedArgs a{};
+        a.in = A; a.in_os = 0; a.in_ms = Ny * Nz; a.n_in = (int)Mx;
+        a.out = u; a.out_os = 0; a.out_ms = Ny * Nz; a.n_out = (int)Nx;
+        a.scale = scale; a.inner = Ny * Nz; a.outer = 1; a.sign = 1;
+        NVP_HIP(ctx, strided((int)Mx, a, twx, ctx->stream));
+    }
+    return NVP_OK;
+}
+
+size_t bytesA(const nvp_grid *g, const int64_t M[3], nvp_prec p) { return (size_t)M[0] * g->n[1] * g->n[2] * csize(p); }
+size_t bytesB(const nvp_grid *g, const int64_t M[3], nvp_prec p) {
+    size_t b = (size_t)M[0] * M[1] * g->n[2] * csize(p);
+    size_t k = kscratch_bytes(M);
+    return b > k ? b : k;
+}
+
+bool same_grid(const nvp_grid &a, const nvp_grid &b) {
+    return std::memcmp(a.origin, b.origin, sizeof a.origin) == 0 && a.h == b.h &&
+           std::memcmp(a.n, b.n, sizeof a.n) == 0;
+}
+
+// 1-D interpolation of a source axis at the target centres (clamped into the
+// source hull): order 1 linear, order 3 four-point Lagrange with the stencil
+// shifted inward at the edges.
+void axis_table(double dst_o, double dst_h, int64_t dst_n, double src_o, double src_h, int64_t src_n, int order,
+                int *base, double *w) {
+    const int K = order + 1;
+    for (int64_t i = 0; i < dst_n; ++i) {
+        const double x = dst_o + (double)i * dst_h;
+        double s = (x - src_o) / src_h;
+        s = std::fmin(std::fmax(s, 0.0), (double)(src_n - 1));
+        const double i0 = std::fmin(std::floor(s), (double)(src_n - 2));
+        if (order == 1) {
+            const double t = s - i0;
+            base[i] = (int)i0;
+            w[i * K] = 1.0 - t;
+            w[i * K + 1] = t;
+        } else {
+            const double b = std::fmin(std::fmax(i0 - 1.0, 0.0), (double)(src_n - 4));
+            const double u = s - b;
+            base[i] = (int)b;
+            w[i * K] = -(u - 1.0) * (u - 2.0) * (u - 3.0) / 6.0;
+            w[i * K + 1] = u * (u - 2.0) * (u - 3.0) / 2.0;
+            w[i * K + 2] = -u * (u - 1.0) * (u - 3.0) / 2.0;
+            w[i * K + 3] = u * (u - 1.0) * (u - 2.0) / 6.0;
+        }
+    }
+}
+
+void free_plan_memory(nvp_plan *p) {
+    for (auto &h : p->h)
+        if (h.khat) (void)hipFree(h.khat), h.khat = nullptr;
+    if (p->A) (void)hipFree(p->A);
+    if (p->B) (void)hipFree(p->B);
+    if (p->tables) (void)hipFree(p->tables);
+    p->A = p->B = p->tables = nullptr;
+    for (auto &e : p->events) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    p->events.clear();
+    for (auto e : p->pool) (void)hipEventDestroy(e);
+    p->pool.clear();
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+const char *nvp_status_str(nvp_status s) {
+    switch (s) {
+    case NVP_OK: return "ok";
+    case NVP_E_INVALID: return "invalid argument";
+    case NVP_E_NOMEM: return "out of memory";
+    case NVP_E_HIP: return "HIP error";
+    case NVP_E_UNSUPPORTED: return "unsupported";
+    case NVP_E_STATE: return "bad state";
+    default: return "unknown status";
+    }
+}
+
+const char *nvp_last_error(const nvp_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_err; }
+
+nvp_status nvp_ctx_create(int device, void *hip_stream, nvp_ctx **out) {
+    if (!out) return fail(nullptr, NVP_E_INVALID, "out is null");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(nullptr, "hipGetDeviceCount", e);
+    if (device < 0 || device >= count) return fail(nullptr, NVP_E_INVALID, "no such device");
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(nullptr, "hipSetDevice", e);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(nullptr, "hipGetDeviceProperties", e);
+    nvp_ctx *c = new (std::nothrow) nvp_ctx;
+    if (!c) return fail(nullptr, NVP_E_NOMEM, "context allocation");
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->max_lds = prop.sharedMemPerBlock;
+    *out = c;
+    return NVP_OK;
+}
+
+nvp_status nvp_ctx_destroy(nvp_ctx *ctx) {
+    if (!ctx) return NVP_E_INVALID;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &t : ctx->tw) (void)hipFree(t.dev);
+    if (ctx->vp.khat) (void)hipFree(ctx->vp.khat);
+    if (ctx->vp.A) (void)hipFree(ctx->vp.A);
+    if (ctx->vp.B) (void)hipFree(ctx->vp.B);
+    delete ctx;
+    return NVP_OK;
+}
+
+nvp_status nvp_ctx_sync(nvp_ctx *ctx) {
+    if (!ctx) return NVP_E_INVALID;
+    NVP_HIP(ctx, hipSetDevice(ctx->device));
+    NVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    NVP_HIP(ctx, hipGetLastError());
+    return NVP_OK;
+}
+
+nvp_status nvp_wavenumber(const nvp_medium *med, double f0, int n, double *k_re, double *k_im) {
+    if (!medium_ok(med) || !finite_pos(f0) || n < 1 || !k_re || !k_im) return NVP_E_INVALID;
+    const double f = n * f0;
+    *k_re = 2.0 * kPi * f / med->c0;
+    // alpha0 in dB/m at 1 MHz, eta the frequency exponent; dB -> Np: / (20 log10 e)
+    *k_im = med->alpha0_db * std::pow(f / 1.0e6, med->eta) / (20.0 * std::log10(std::exp(1.0)));
+    return NVP_OK;
+}
+
+nvp_status nvp_cascade_constant(const nvp_medium *med, double f0, int n, double *c) {
+    if (!medium_ok(med) || !finite_pos(f0) || n < 1 || !c) return NVP_E_INVALID;
+    const double w = 2.0 * kPi * f0;
+    const double c2 = med->c0 * med->c0;
+    *c = -med->beta * w * w * (double)n * (double)n / (2.0 * med->rho0 * c2 * c2);
+    return NVP_OK;
+}
+
+nvp_status nvp_spacing(const nvp_medium *med, double f0, int n, int n_w, double *h) {
+    if (!medium_ok(med) || !finite_pos(f0) || n < 1 || n_w < 1 || !h) return NVP_E_INVALID;
+    *h = med->c0 / (n * f0) / n_w;
+    return NVP_OK;
+}
+
+nvp_status nvp_grid_from_counts(const double focus[3], double h, const int64_t n[3], const int64_t i_f[3],
+                                nvp_grid *out) {
+    if (!focus || !n || !i_f || !out || !finite_pos(h)) return NVP_E_INVALID;
+    for (int a = 0; a < 3; ++a) {
+        if (n[a] < 1 || !std::isfinite(focus[a])) return NVP_E_INVALID;
+        out->origin[a] = focus[a] - (double)i_f[a] * h;
+        out->n[a] = n[a];
+    }
+    out->h = h;
+    return NVP_OK;
+}
+
+nvp_status nvp_grid_from_box(const double focus[3], const double lo[3], const double hi[3], double h, nvp_grid *out,
+                             int64_t i_f_out[3]) {
+    if (!focus || !lo || !hi || !out || !finite_pos(h)) return NVP_E_INVALID;
+    int64_t n[3], i_f[3];
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(lo[a]) || !std::isfinite(hi[a]) || !(hi[a] >= lo[a])) return NVP_E_INVALID;
+        const int64_t c = nint((hi[a] - lo[a]) / h);
+        n[a] = c > 1 ? c : 1;
+        i_f[a] = nint((focus[a] - lo[a]) / h);
+        if (i_f_out) i_f_out[a] = i_f[a];
+    }
+    return nvp_grid_from_counts(focus, h, n, i_f, out);
+}
+
+nvp_status nvp_rule_of_thumb_box(int n, double l, double R, double d, double eps, double lo[3], double hi[3]) {
+    if (n < 2 || !finite_pos(l) || !finite_pos(R) || !(R < l) || !(d >= 0) || !(eps >= 0) || !lo || !hi)
+        return NVP_E_INVALID;
+    const double L = std::sqrt(l * l - R * R) - eps;
+    const double s = 2.0 / n;  // lambda_n / lambda_2
+    lo[0] = l - s * L;
+    lo[1] = -s * R;
+    lo[2] = -s * R;
+    hi[0] = l + d;
+    hi[1] = s * R;
+    hi[2] = s * R;
+    return NVP_OK;
+}
+
+nvp_status nvp_transfer_axis(double dst_origin, double dst_h, int64_t dst_n, double src_origin, double src_h,
+                             int64_t src_n, int order, int32_t *base, double *w) {
+    if ((order != 1 && order != 3) || dst_n < 1 || src_n < order + 1 || !base || !w || !finite_pos(dst_h) ||
+        !finite_pos(src_h) || !std::isfinite(dst_origin) || !std::isfinite(src_origin))
+        return NVP_E_INVALID;
+    std::vector<int> b((size_t)dst_n);
+    axis_table(dst_origin, dst_h, dst_n, src_origin, src_h, src_n, order, b.data(), w);
+    for (int64_t i = 0; i < dst_n; ++i) base[i] = b[i];
+    return NVP_OK;
+}
+
+nvp_status nvp_circulant_size(int64_t n, int64_t *m) {
+    if (n < 1 || !m) return NVP_E_INVALID;
+    *m = circulant_len(n);
+    return *m < 0 ? NVP_E_UNSUPPORTED : NVP_OK;
+}
+
+nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nvp_grid *g, const void *f_dev,
+                                void *u_dev, nvp_prec prec) {
+    if (!ctx) return NVP_E_INVALID;
+    if (!grid_ok(g) || !f_dev || !u_dev || f_dev == u_dev || (prec != NVP_C64 && prec != NVP_C128) ||
+        !std::isfinite(k_re) || !std::isfinite(k_im) || k_im < 0 || (k_re == 0 && k_im == 0))
+        return fail(ctx, NVP_E_INVALID, "nvp_volume_potential: bad argument");
+    NVP_HIP(ctx, hipSetDevice(ctx->device));
+    int64_t M[3];
+    nvp_status st = check_grid_lengths(ctx, g, M);
+    if (st) return st;
+    VpCache &c = ctx->vp;
+    const bool hit = c.valid && c.kr == k_re && c.ki == k_im && c.prec == (int)prec && same_grid(c.g, *g);
+    if (!hit) {
+        NVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (c.khat) (void)hipFree(c.khat);
+        if (c.A) (void)hipFree(c.A);
+        if (c.B) (void)hipFree(c.B);
+        c = VpCache{};
+        hipError_t e1 = hipMalloc(&c.khat, khat_bytes(M, prec));
+        hipError_t e2 = hipMalloc(&c.A, bytesA(g, M, prec));
+        hipError_t e3 = hipMalloc(&c.B, bytesB(g, M, prec));
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+            if (c.khat) (void)hipFree(c.khat);
+            if (c.A) (void)hipFree(c.A);
+            if (c.B) (void)hipFree(c.B);
+            c = VpCache{};
+            return fail(ctx, NVP_E_NOMEM, "nvp_volume_potential: device allocation failed");
+        }
+        if ((st = kernel_spectrum(ctx, nullptr, k_re, k_im, g, M, prec, c.khat, c.B))) return st;
+        c.valid = true;
+        c.kr = k_re;
+        c.ki = k_im;
+        c.g = *g;
+        c.prec = (int)prec;
+        std::memcpy(c.M, M, sizeof M);
+    }
+    const double scale = -1.0 / ((double)M[0] * (double)M[1] * (double)M[2]);
+    return convolve(ctx, nullptr, prec, g, M, c.khat, c.A, c.B, f_dev, nullptr, u_dev, scale);
+}
+
+nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int n_harm, const nvp_grid *g1,
+                            const nvp_grid *gn, nvp_prec prec, int transfer_order, nvp_plan **out) {
+    if (!ctx) return NVP_E_INVALID;
+    if (!out) return fail(ctx, NVP_E_INVALID, "out is null");
+    *out = nullptr;
+    if (!medium_ok(med) || !finite_pos(f0) || !grid_ok(g1) || !gn || (prec != NVP_C64 && prec != NVP_C128))
+        return fail(ctx, NVP_E_INVALID, "nvp_plan_cascade: bad argument");
+    if (n_harm < 2 || n_harm > NVP_MAX_FIELDS + 1)
+        return fail(ctx, n_harm < 2 ? NVP_E_INVALID : NVP_E_UNSUPPORTED, "nvp_plan_cascade: n_harm out of range");
+    if (transfer_order != 1 && transfer_order != 3)
+        return fail(ctx, NVP_E_UNSUPPORTED, "nvp_plan_cascade: transfer order must be 1 or 3");
+    for (int i = 0; i < n_harm - 1; ++i)
+        if (!grid_ok(&gn[i])) return fail(ctx, NVP_E_INVALID, "nvp_plan_cascade: bad harmonic grid");
+    NVP_HIP(ctx, hipSetDevice(ctx->device));
+
+    nvp_plan *p = new (std::nothrow) nvp_plan;
+    if (!p) return fail(ctx, NVP_E_NOMEM, "plan allocation");
+    p->ctx = ctx;
+    p->prec = prec;
+    p->order = transfer_order;
+    p->med = *med;
+    p->f0 = f0;
+    p->n_harm = n_harm;
+    p->g1 = *g1;
+    p->h.resize(n_harm - 1);
+    const int K = transfer_order + 1;
+    const size_t rs = prec == NVP_C64 ? 4 : 8;
+    size_t maxA = 0, maxB = 0, tbytes = 0;
+    auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    for (int i = 0; i < n_harm - 1; ++i) {
+        Harm &h = p->h[i];
+        h.n = i + 2;
+        h.g = gn[i];
+        nvp_status st = check_grid_lengths(ctx, &h.g, h.M);
+        if (st) {
+            delete p;
+            return st;
+        }
+        nvp_wavenumber(med, f0, h.n, &h.kr, &h.ki);
+        nvp_cascade_constant(med, f0, h.n, &h.Cn);
+        size_t a = bytesA(&h.g, h.M, prec), b = bytesB(&h.g, h.M, prec);
+        maxA = a > maxA ? a : maxA;
+        maxB = b > maxB ? b : maxB;
+        for (int m = 1; m < h.n; ++m) {
+            const nvp_grid &src = m == 1 ? *g1 : gn[m - 2];
+            HarmField &f = h.f[m - 1];
+            f.identity = same_grid(src, h.g) ? 1 : 0;
+            if (f.identity) continue;
+            for (int ax = 0; ax < 3; ++ax) {
+                if (src.n[ax] < K) {
+                    delete p;
+                    return fail(ctx, NVP_E_INVALID, "a source grid axis is shorter than the transfer stencil");
+                }
+                f.off_b[ax] = tbytes;
+                tbytes = align(tbytes + (size_t)h.g.n[ax] * sizeof(int));
+                f.off_w[ax] = tbytes;
+                tbytes = align(tbytes + (size_t)h.g.n[ax] * K * rs);
+            }
+        }
+    }
+    // tables on the host, then one upload
+    std::vector<unsigned char> host(tbytes ? tbytes : 1);
+    for (auto &h : p->h) {
+        for (int m = 1; m < h.n; ++m) {
+            const nvp_grid &src = m == 1 ? *g1 : gn[m - 2];
+            HarmField &f = h.f[m - 1];
+            if (f.identity) continue;
+            for (int ax = 0; ax < 3; ++ax) {
+                std::vector<double> w((size_t)h.g.n[ax] * K);
+                int *base = reinterpret_cast<int *>(host.data() + f.off_b[ax]);
+                axis_table(h.g.origin[ax], h.g.h, h.g.n[ax], src.origin[ax], src.h, src.n[ax], transfer_order, base,
+                           w.data());
+                if (rs == 8) std::memcpy(host.data() + f.off_w[ax], w.data(), w.size() * 8);
+                else {
+                    float *wf = reinterpret_cast<float *>(host.data() + f.off_w[ax]);
+                    for (size_t j = 0; j < w.size(); ++j) wf[j] = (float)w[j];
+                }
+            }
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (tbytes) e = hipMalloc(&p->tables, tbytes);
+    if (e == hipSuccess) e = hipMalloc(&p->A, maxA);
+    if (e == hipSuccess) e = hipMalloc(&p->B, maxB);
+    for (auto &h : p->h) {
+        if (e != hipSuccess) break;
+        e = hipMalloc(&h.khat, khat_bytes(h.M, prec));
+        p->bytes_khat += khat_bytes(h.M, prec);
+    }
+    if (e == hipSuccess && tbytes) e = hipMemcpy(p->tables, host.data(), tbytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_plan_memory(p);
+        delete p;
+        return hip_fail(ctx, "nvp_plan_cascade: allocation", e);
+    }
+    p->bytes_A = maxA;
+    p->bytes_B = maxB;
+    p->bytes_tables = tbytes;
+    *out = p;
+    return NVP_OK;
+}
+
+nvp_status nvp_plan_workspace_bytes(const nvp_plan *plan, size_t *bytes) {
+    if (!plan || !bytes) return NVP_E_INVALID;
+    *bytes = plan->bytes_A + plan->bytes_B + plan->bytes_tables + plan->bytes_khat;
+    return NVP_OK;
+}
+
+nvp_status nvp_plan_set_kernel_cache(nvp_plan *plan, int enable) {
+    if (!plan) return NVP_E_INVALID;
+    plan->cache = enable != 0;
+    return NVP_OK;
+}
+
+nvp_status nvp_execute_harmonic(nvp_plan *plan, int n, const void *const *fields, void *pn_dev) {
+    if (!plan) return NVP_E_INVALID;
+    nvp_ctx *ctx = plan->ctx;
+    if (n < 2 || n > plan->n_harm || !fields || !pn_dev)
+        return fail(ctx, NVP_E_INVALID, "nvp_execute_harmonic: bad argument");
+    for (int m = 1; m < n; ++m)
+        if (!fields[m - 1] || fields[m - 1] == pn_dev)
+            return fail(ctx, NVP_E_INVALID, "nvp_execute_harmonic: null or aliased field");
+    NVP_HIP(ctx, hipSetDevice(ctx->device));
+    Harm &h = plan->h[n - 2];
+    nvp_status st;
+    if (!h.khat_ok || !plan->cache) {
+        if ((st = kernel_spectrum(ctx, plan, h.kr, h.ki, &h.g, h.M, plan->prec, h.khat, plan->B))) return st;
+        h.khat_ok = true;
+    }
+    SourceArgs src{};
+    src.nf = n - 1;
+    src.order = plan->order;
+    src.Nx = (int)h.g.n[0];
+    src.Nz = (int)h.g.n[2];
+    const unsigned char *tb = static_cast<const unsigned char *>(plan->tables);
+    for (int m = 1; m < n; ++m) {
+        const nvp_grid &sg = m == 1 ? plan->g1 : plan->h[m - 2].g;
+        FieldArgs &fa = src.f[m - 1];
+        const HarmField &hf = h.f[m - 1];
+        fa.p = fields[m - 1];
+        fa.s0 = sg.n[1] * sg.n[2];
+        fa.s1 = sg.n[2];
+        fa.identity = hf.identity;
+        for (int ax = 0; ax < 3; ++ax) {
+            fa.b[ax] = hf.identity ? nullptr : reinterpret_cast<const int *>(tb + hf.off_b[ax]);
+            fa.w[ax] = hf.identity ? nullptr : static_cast<const void *>(tb + hf.off_w[ax]);
+        }
+    }
+    const double scale = h.Cn / ((double)h.M[0] * (double)h.M[1] * (double)h.M[2]);
+    return convolve(ctx, plan, plan->prec, &h.g, h.M, h.khat, plan->A, plan->B, nullptr, &src, pn_dev, scale);
+}
+
+nvp_status nvp_execute_cascade(nvp_plan *plan, const void *p1_dev, void *const *pn_dev) {
+    if (!plan) return NVP_E_INVALID;
+    if (!p1_dev || !pn_dev) return fail(plan->ctx, NVP_E_INVALID, "nvp_execute_cascade: null buffer");
+    std::vector<const void *> fields(plan->n_harm);
+    fields[0] = p1_dev;
+    for (int n = 2; n <= plan->n_harm; ++n) {
+        if (!pn_dev[n - 2]) return fail(plan->ctx, NVP_E_INVALID, "nvp_execute_cascade: null output");
+        nvp_status st = nvp_execute_harmonic(plan, n, fields.data(), pn_dev[n - 2]);
+        if (st) return st;
+        fields[n - 1] = pn_dev[n - 2];
+    }
+    return NVP_OK;
+}
+
+nvp_status nvp_plan_destroy(nvp_plan *plan) {
+    if (!plan) return NVP_E_INVALID;
+    (void)hipSetDevice(plan->ctx->device);
+    (void)hipStreamSynchronize(plan->ctx->stream);
+    free_plan_memory(plan);
+    delete plan;
+    return NVP_OK;
+}
+
+nvp_status nvp_plan_set_timing(nvp_plan *plan, int enable) {
+    if (!plan) return NVP_E_INVALID;
+    plan->timing = enable != 0;
+    return NVP_OK;
+}
+
+nvp_status nvp_plan_get_timing(nvp_plan *plan, double *ms, int64_t *count, int n_kinds) {
+    if (!plan || !ms || !count || n_kinds < 1) return NVP_E_INVALID;
+    nvp_ctx *ctx = plan->ctx;
+    for (int k = 0; k < n_kinds; ++k) {
+        ms[k] = 0;
+        count[k] = 0;
+    }
+    for (auto &e : plan->events) {
+        NVP_HIP(ctx, hipEventSynchronize(e.b));
+        float t = 0;
+        NVP_HIP(ctx, hipEventElapsedTime(&t, e.a, e.b));
+        if (e.kind < n_kinds) {
+            ms[e.kind] += t;
+            count[e.kind] += 1;
+        }
+        plan->pool.push_back(e.a);
+        plan->pool.push_back(e.b);
+    }
+    plan->events.clear();
+    return NVP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,265 @@
+"""Python binding of the nvp C ABI.
+
+Every function here only marshals arguments: torch tensors provide device
+memory (their data pointers) and the current HIP stream; all computation runs
+in the library's HIP kernels.  There is no CPU fallback: without the built
+library every call raises.
+"""
+
+import ctypes
+
+import torch
+
+from . import _native
+from ._native import Grid, Medium
+
+NVP_C64, NVP_C128 = 0, 1
+TIMING_KINDS = ("ktab", "kfft", "xfwd", "yfwd", "zconv", "yinv", "xinv")
+_DT = {NVP_C64: torch.complex64, NVP_C128: torch.complex128}
+
+
+class NvpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("nvp status %d (%s): %s" % (status, _native.lib().nvp_status_str(status).decode(), msg))
+        self.status = status
+
+
+def _check(st, ctx=None):
+    if st != 0:
+        L = _native.lib()
+        raise NvpError(st, (L.nvp_last_error(ctx) or b"").decode())
+
+
+def prec_of(dtype):
+    if dtype == torch.complex64:
+        return NVP_C64
+    if dtype == torch.complex128:
+        return NVP_C128
+    raise ValueError("fields must be complex64 or complex128")
+
+
+def medium(m):
+    """Medium from a mapping with c0, rho0, beta, alpha0_db, eta."""
+    if isinstance(m, Medium):
+        return m
+    return Medium(m["c0"], m["rho0"], m["beta"], m["alpha0_db"], m["eta"])
+
+
+def grid(g):
+    """Grid from an nvp Grid, or any object/mapping with origin, h, n."""
+    if isinstance(g, Grid):
+        return g
+    if isinstance(g, dict):
+        o, h, n = g["origin"], g["h"], g["n"]
+    else:
+        o, h, n = g.origin, g.h, g.n
+    return Grid((ctypes.c_double * 3)(*[float(v) for v in o]), float(h), (ctypes.c_int64 * 3)(*[int(v) for v in n]))
+
+
+def grid_tuple(g):
+    return tuple(g.origin), g.h, tuple(g.n)
+
+
+# ------------------------------------------------------------- host constants and grids
+
+def wavenumber(med, f0, n):
+    kr, ki = ctypes.c_double(), ctypes.c_double()
+    _check(_native.lib().nvp_wavenumber(ctypes.byref(medium(med)), f0, n, ctypes.byref(kr), ctypes.byref(ki)))
+    return complex(kr.value, ki.value)
+
+
+def cascade_constant(med, f0, n):
+    c = ctypes.c_double()
+    _check(_native.lib().nvp_cascade_constant(ctypes.byref(medium(med)), f0, n, ctypes.byref(c)))
+    return c.value
+
+
+def spacing(med, f0, n, n_w=6):
+    h = ctypes.c_double()
+    _check(_native.lib().nvp_spacing(ctypes.byref(medium(med)), f0, n, n_w, ctypes.byref(h)))
+    return h.value
+
+
+def _d3(v):
+    return (ctypes.c_double * 3)(*[float(x) for x in v])
+
+
+def _i3(v):
+    return (ctypes.c_int64 * 3)(*[int(x) for x in v])
+
+
+def grid_from_counts(focus, h, n, i_f):
+    g = Grid()
+    _check(_native.lib().nvp_grid_from_counts(_d3(focus), h, _i3(n), _i3(i_f), ctypes.byref(g)))
+    return g
+
+
+def grid_from_box(focus, lo, hi, h):
+    g = Grid()
+    i_f = (ctypes.c_int64 * 3)()
+    _check(_native.lib().nvp_grid_from_box(_d3(focus), _d3(lo), _d3(hi), h, ctypes.byref(g), i_f))
+    return g, tuple(i_f)
+
+
+def rule_of_thumb_box(n, l, R, d, eps=1e-4):
+    lo, hi = (ctypes.c_double * 3)(), (ctypes.c_double * 3)()
+    _check(_native.lib().nvp_rule_of_thumb_box(n, l, R, d, eps, lo, hi))
+    return tuple(lo), tuple(hi)
+
+
+def transfer_axis(dst_origin, dst_h, dst_n, src_origin, src_h, src_n, order):
+    """(base int32[dst_n], weights float64[dst_n, order + 1]) of one axis, computed by the library."""
+    import numpy as np
+    base = np.empty(dst_n, dtype=np.int32)
+    w = np.empty((dst_n, order + 1), dtype=np.float64)
+    _check(_native.lib().nvp_transfer_axis(dst_origin, dst_h, dst_n, src_origin, src_h, src_n, order,
+                                           base.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                           w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return base, w
+
+
+def circulant_size(n):
+    m = ctypes.c_int64()
+    _check(_native.lib().nvp_circulant_size(n, ctypes.byref(m)))
+    return m.value
+
+
+# ------------------------------------------------------------- context
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, numel, what):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError("%s must be a CUDA (HIP) tensor" % what)
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError("%s must be contiguous %s with %d elements" % (what, dtype, numel))
+
+
+class Context:
+    """nvp_ctx bound to a device and a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, device=0, stream=None):
+        dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.device = dev
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(_native.lib().nvp_ctx_create(dev.index or 0, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    def sync(self):
+        _check(_native.lib().nvp_ctx_sync(self.handle), self.handle)
+
+    def close(self):
+        if self.handle:
+            _native.lib().nvp_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def volume_potential(ctx, k, g, f, out=None):
+    """u = -sum_j K(x_i - x_j) f_j on grid g (complex64 or complex128 f of shape g.n)."""
+    g = grid(g)
+    n = tuple(g.n)
+    prec = prec_of(f.dtype)
+    _need(f, f.dtype, n[0] * n[1] * n[2], "f")
+    if out is None:
+        out = torch.empty(n, dtype=f.dtype, device=f.device)
+    _need(out, f.dtype, n[0] * n[1] * n[2], "out")
+    k = complex(k)
+    _check(_native.lib().nvp_volume_potential(ctx.handle, k.real, k.imag, ctypes.byref(g), _ptr(f), _ptr(out), prec),
+           ctx.handle)
+    return out
+
+
+class CascadePlan:
+    """nvp_plan of harmonics 2..n_harm on their own grids."""
+
+    def __init__(self, ctx, med, f0, g1, grids, prec=NVP_C64, order=1):
+        self.ctx = ctx
+        self.g1 = grid(g1)
+        self.grids = [grid(g) for g in grids]
+        self.n_harm = len(self.grids) + 1
+        self.prec = prec
+        self.dtype = _DT[prec]
+        arr = (Grid * len(self.grids))(*self.grids)
+        h = ctypes.c_void_p()
+        _check(_native.lib().nvp_plan_cascade(ctx.handle, ctypes.byref(medium(med)), f0, self.n_harm,
+                                              ctypes.byref(self.g1), arr, prec, order, ctypes.byref(h)), ctx.handle)
+        self.handle = h
+
+    def shape(self, n):
+        g = self.g1 if n == 1 else self.grids[n - 2]
+        return tuple(g.n)
+
+    def workspace_bytes(self):
+        b = ctypes.c_size_t()
+        _check(_native.lib().nvp_plan_workspace_bytes(self.handle, ctypes.byref(b)))
+        return b.value
+
+    def set_kernel_cache(self, enable):
+        _check(_native.lib().nvp_plan_set_kernel_cache(self.handle, int(bool(enable))))
+
+    def set_timing(self, enable):
+        _check(_native.lib().nvp_plan_set_timing(self.handle, int(bool(enable))))
+
+    def get_timing(self):
+        k = len(TIMING_KINDS)
+        ms = (ctypes.c_double * k)()
+        cnt = (ctypes.c_int64 * k)()
+        _check(_native.lib().nvp_plan_get_timing(self.handle, ms, cnt, k), self.ctx.handle)
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(TIMING_KINDS)}
+
+    def _sz(self, n):
+        s = self.shape(n)
+        return s[0] * s[1] * s[2]
+
+    def execute_harmonic(self, n, fields, out=None):
+        """fields[m-1] = p_m on its grid, m = 1..n-1; returns p_n."""
+        if len(fields) != n - 1:
+            raise ValueError("harmonic %d needs %d fields" % (n, n - 1))
+        for m, f in enumerate(fields, start=1):
+            _need(f, self.dtype, self._sz(m), "p_%d" % m)
+        if out is None:
+            out = torch.empty(self.shape(n), dtype=self.dtype, device=fields[0].device)
+        _need(out, self.dtype, self._sz(n), "out")
+        arr = (ctypes.c_void_p * len(fields))(*[f.data_ptr() for f in fields])
+        _check(_native.lib().nvp_execute_harmonic(self.handle, n, arr, _ptr(out)), self.ctx.handle)
+        return out
+
+    def execute(self, p1, outs=None):
+        """p1 on g1 -> [p_2, ..., p_n_harm]."""
+        _need(p1, self.dtype, self._sz(1), "p1")
+        if outs is None:
+            outs = [torch.empty(self.shape(n), dtype=self.dtype, device=p1.device)
+                    for n in range(2, self.n_harm + 1)]
+        for n, o in zip(range(2, self.n_harm + 1), outs):
+            _need(o, self.dtype, self._sz(n), "p_%d" % n)
+        arr = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        _check(_native.lib().nvp_execute_cascade(self.handle, _ptr(p1), arr), self.ctx.handle)
+        return outs
+
+    def close(self):
+        if self.handle:
+            _native.lib().nvp_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
