@@ -1,0 +1,232 @@
+"""Benchmark of the nested-mesh volume-potential cascade on one MI355X.
+
+Workload (paper-scale homogeneous run): bowl R = 7.5 cm, l = 15 cm, 1.1 MHz,
+water, focal pressure 3.5 MPa, 4096 surface points; p1 on 128^3 at lambda_1/6;
+harmonics 2..5 on nested grids (64 (n+2), 256, 256) at lambda_n/6 (circulants
+(128 (n+2), 512, 512)), complex64, tricubic transfer.  One step = the whole
+cascade p1 -> p2..p5: for each harmonic the FP64 kernel tabulation and kernel
+spectrum, the transfer + source build, and the pruned circulant convolution.
+
+Prints one JSON line.  `value` = voxels of p2..p5 per second of step time.
+Also measured: the same cascade on the uniform 640^3 baseline grid (circulant
+1280^3) and the focal-pressure difference between the two, per-kernel HIP
+event times (roofline of the dominant kernel), and the FP64 oracle on a
+bounded sample of the same workload.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "volume-potential voxels/s + % peak HBM; nested vs uniform time @1% focal err"
+PEAK_HBM_GBS = 8000.0
+ELEM = 8  # complex64 bytes
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_inputs(P, torch, cfg, device):
+    from workload import bowl
+    W = cfg["medium"]
+    f0 = cfg["f0"]
+    focus = (cfg["l"], 0.0, 0.0)
+    g1 = P.grid_from_counts(focus, P.spacing(W, f0, 1), cfg["p1_grid"]["n"], cfg["p1_grid"]["i_f"])
+    gn = [P.grid_from_counts(focus, P.spacing(W, f0, n), cfg["grids"][n]["n"], cfg["grids"][n]["i_f"])
+          for n in range(2, cfg["n_harm"] + 1)]
+    gu = [P.grid_from_counts(focus, P.spacing(W, f0, 5), cfg["uniform_grids"][n]["n"],
+                             cfg["uniform_grids"][n]["i_f"]) for n in range(2, cfg["n_harm"] + 1)]
+    k1 = P.wavenumber(W, f0, 1)
+    import numpy as np
+    ax = [g1.origin[a] + np.arange(g1.n[a]) * g1.h for a in range(3)]
+    pts = bowl.bowl_points(cfg["R"], cfg["l"], cfg["n_points"], cfg["seed"])
+    p1 = bowl.incident_field(pts, cfg["R"], cfg["l"], k1, cfg["p0"], ax[0], ax[1], ax[2], device=device,
+                             chunk=8192).to(torch.complex64).contiguous()
+    return g1, gn, gu, p1
+
+
+def nsz(g):
+    return int(g.n[0]) * int(g.n[1]) * int(g.n[2])
+
+
+def alg_bytes(P, g1, gn, order_fields):
+    """Algorithmic HBM bytes per launch kind for one cascade (complex64 passes, FP64 kernel)."""
+    b = {k: 0.0 for k in P.nvp.TIMING_KINDS}
+    grids = [g1] + list(gn)
+    for i, g in enumerate(gn):
+        n = i + 2
+        N = [int(v) for v in g.n]
+        M = [P.circulant_size(v) for v in N]
+        H = [m // 2 + 1 for m in M]
+        Ho = H[0] * H[1] * H[2]
+        b["ktab"] += 16.0 * Ho
+        b["kfft"] += 16.0 * Ho * 2 * 3 - 16.0 * Ho + 8.0 * Ho  # three FP64 passes; last writes complex64
+        src = sum(nsz(grids[m - 1]) for m in range(1, n))
+        b["xfwd"] += ELEM * (src + M[0] * N[1] * N[2])
+        b["yfwd"] += ELEM * (M[0] * N[1] * N[2] + M[0] * M[1] * N[2])
+        b["zconv"] += ELEM * (2 * M[0] * M[1] * N[2] + Ho)
+        b["yinv"] += ELEM * (M[0] * M[1] * N[2] + M[0] * N[1] * N[2])
+        b["xinv"] += ELEM * (M[0] * N[1] * N[2] + N[0] * N[1] * N[2])
+    return b
+
+
+def time_steps(torch, plan, p1, outs, steps, warmup, stream):
+    for _ in range(warmup):
+        plan.execute(p1, outs)
+    torch.cuda.synchronize()
+    plan.get_timing()  # drop warmup events
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.execute(p1, outs)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cpu_baseline(cfg, g1_p, gn_p, p1_dev, budget_s):
+    """The FP64 oracle on a bounded sample: p2 at a set of voxels of its 256^3 grid."""
+    import numpy as np
+    import oracle
+    W = cfg["medium"]
+    g1 = oracle.Grid(tuple(g1_p.origin), g1_p.h, tuple(g1_p.n))
+    g2 = oracle.Grid(tuple(gn_p[0].origin), gn_p[0].h, tuple(gn_p[0].n))
+    p1 = p1_dev.to("cpu").numpy().astype(np.complex128)
+    rng = np.random.default_rng(11)
+    n_t = 16
+    t = rng.integers(0, g2.size(), n_t)
+    t0 = time.perf_counter()
+    oracle.harmonic(2, {1: (p1, g1)}, g2, cfg["f0"], W, 3, method="direct", targets=t)
+    dt = time.perf_counter() - t0
+    # grow the sample to about budget_s of work (per-target cost dominates)
+    if dt < budget_s / 3:
+        n_t = int(min(4096, max(16, n_t * budget_s / max(dt, 1e-3) * 0.8)))
+        t = rng.integers(0, g2.size(), n_t)
+        t0 = time.perf_counter()
+        oracle.harmonic(2, {1: (p1, g1)}, g2, cfg["f0"], W, 3, method="direct", targets=t)
+        dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n_t / dt, "unit": "voxels/s", "cores": cores, "kind": "oracle",
+            "sample": "p2 at %d random voxels of the 256^3 grid: FP64 direct midpoint sum over all 16.8M "
+                      "source voxels, tricubic transfer of p1 included (%.1f s)" % (n_t, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--order", type=int, default=3, choices=[1, 3])
+    ap.add_argument("--pf", type=float, default=3.5e6, help="focal pressure (Pa)")
+    ap.add_argument("--no-uniform", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; every configuration fits one MI355X "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2011_03009_amd as P
+    from workload import configs
+
+    cfg = configs.paper_scale(P_f=a.pf)
+    W = cfg["medium"]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    log("bench: building inputs")
+    g1, gn, gu, p1 = build_inputs(P, torch, cfg, dev)
+    ctx = P.Context(0, stream)
+    voxels = sum(nsz(g) for g in gn)
+
+    # nested cascade, full step (kernel spectra recomputed every step)
+    plan = P.CascadePlan(ctx, W, cfg["f0"], g1, gn, prec=P.NVP_C64, order=a.order)
+    plan.set_kernel_cache(False)
+    outs = [torch.empty(tuple(g.n), dtype=torch.complex64, device=dev) for g in gn]
+    log("bench: nested cascade, %d warmup + %d steps" % (a.warmup, a.steps))
+    plan.set_timing(True)
+    ms = time_steps(torch, plan, p1, outs, a.steps, a.warmup, stream)
+    timing = plan.get_timing()
+    plan.set_timing(False)
+    # conv-only rate: kernel spectra cached
+    plan.set_kernel_cache(True)
+    ms_conv = time_steps(torch, plan, p1, outs, a.steps, 1, stream)
+    ctx.sync()
+    nested = [o.clone() for o in outs]
+
+    # roofline of the dominant kernel kind
+    ab = alg_bytes(P, g1, gn, a.order)
+    per_kind = {}
+    for k, (t_ms, cnt) in timing.items():
+        if cnt:
+            per_kind[k] = {"ms_per_step": t_ms / a.steps, "launches_per_step": cnt / a.steps,
+                           "alg_GBs": ab[k] * a.steps / (t_ms * 1e-3) / 1e9}
+    dom = max(per_kind, key=lambda k: per_kind[k]["ms_per_step"])
+    achieved = per_kind[dom]["alg_GBs"]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+            "alg_bytes_per_launch": ab[dom] / max(1.0, per_kind[dom]["launches_per_step"]),
+            "avg_launch_ms": per_kind[dom]["ms_per_step"] / max(1.0, per_kind[dom]["launches_per_step"])}
+    conv_kinds = ("xfwd", "yfwd", "zconv", "yinv", "xinv")
+    conv_ms = sum(per_kind[k]["ms_per_step"] for k in conv_kinds)
+    conv_gbs = sum(ab[k] for k in conv_kinds) / (conv_ms * 1e-3) / 1e9
+
+    result = {
+        "metric": METRIC, "value": voxels / (ms * 1e-3), "unit": "voxels/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64", "data": "synthetic",
+        "config": {"workload": "paper-scale nested cascade: bowl R 7.5 cm, l 15 cm, 1.1 MHz, water, P_f %.2g MPa, "
+                               "4096 points; p1 128^3; p2..p5 on (64(n+2),256,256) at lambda_n/6; complex64; "
+                               "transfer order %d; kernel spectra recomputed every step" % (a.pf / 1e6, a.order),
+                   "voxels_per_step": voxels, "grids": [list(map(int, g.n)) for g in gn],
+                   "circulants": [[P.circulant_size(int(v)) for v in g.n] for g in gn]},
+        "roofline": roof,
+        "conv_only": {"ms_per_step": ms_conv, "voxels_per_s": voxels / (ms_conv * 1e-3),
+                      "five_pass_alg_GBs": conv_gbs, "five_pass_frac": conv_gbs / PEAK_HBM_GBS},
+        "per_kernel": per_kind,
+    }
+    del plan
+
+    if not a.no_uniform:
+        log("bench: uniform 640^3 cascade")
+        plan_u = P.CascadePlan(ctx, W, cfg["f0"], g1, gu, prec=P.NVP_C64, order=a.order)
+        plan_u.set_kernel_cache(False)
+        outs_u = [torch.empty(tuple(g.n), dtype=torch.complex64, device=dev) for g in gu]
+        ms_u = time_steps(torch, plan_u, p1, outs_u, 3, 1, stream)
+        plan_u.set_kernel_cache(True)
+        ms_u_conv = time_steps(torch, plan_u, p1, outs_u, 3, 1, stream)
+        ctx.sync()
+        i1 = cfg["p1_grid"]["i_f"]
+        p1f = abs(complex(p1[i1].item()))
+        errs = {}
+        for i in range(len(gn)):
+            a_n = complex(nested[i][tuple(cfg["grids"][i + 2]["i_f"])].item())
+            b_n = complex(outs_u[i][tuple(cfg["uniform_grids"][i + 2]["i_f"])].item())
+            errs[str(i + 2)] = {"e_n": abs(a_n - b_n) / p1f, "nested": abs(a_n), "uniform": abs(b_n)}
+        result["nested_vs_uniform"] = {
+            "t_nested_ms": ms, "t_uniform_ms": ms_u, "ratio": ms_u / ms,
+            "conv_only_ratio": ms_u_conv / ms_conv, "t_uniform_conv_ms": ms_u_conv,
+            "uniform_voxels": sum(nsz(g) for g in gu), "focal_err": errs,
+            "max_focal_err": max(e["e_n"] for e in errs.values()), "gate": 0.01,
+            "p1_focal_Pa": p1f}
+        del plan_u, outs_u
+        torch.cuda.empty_cache()
+
+    if not a.no_cpu:
+        log("bench: oracle CPU baseline")
+        result["cpu_baseline"] = cpu_baseline(cfg, g1, gn, p1, a.cpu_budget)
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -163,6 +163,101 @@ k_xsrc(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t inner) {
         [&](int m) -> cx<R> & { return lds[m * T + c]; });
 }
 
+// The same pass with the transfer split by axis.  Per chunk of target x
+// indices [ix0, ix1): (A) for every field that needs interpolating, the y-z
+// interpolation of the source x-rows the chunk touches is staged, per column,
+// in the upper part of the column's LDS slot (rows Nx .. L-1, which the
+// zero-padded transform never reads); (B) each target voxel then needs only
+// K x-taps per field from LDS before the products of the source term are
+// written to rows 0 .. Nx-1.  The host picks `chunk` so that the staged rows
+// of all fields fit in L - Nx rows.
+template <typename R, int L, int T, int K, class St>
+__global__ void __launch_bounds__(T *plan_threads(L))
+k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t inner, int chunk) {
+    using F = Fft<R, L>;
+    constexpr int P = F::P;
+    cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
+    const int tid = threadIdx.x, c = tid % T, t = tid / T;
+    const int64_t col = (int64_t)blockIdx.x * T + c;
+    const bool act = col < inner;
+    const int iy = act ? (int)(col / src.Nz) : 0, iz = act ? (int)(col % src.Nz) : 0;
+    const int Nx = src.Nx;
+    cx<R> *stage = lds + (int64_t)Nx * T;
+#pragma unroll 1
+    for (int ix0 = 0; ix0 < Nx; ix0 += chunk) {
+        const int ix1 = ix0 + chunk < Nx ? ix0 + chunk : Nx;
+        int lo[NVP_MAX_FIELDS], off[NVP_MAX_FIELDS];
+        int rows = 0;
+#pragma unroll
+        for (int i = 0; i < NVP_MAX_FIELDS; ++i) {
+            lo[i] = 0;
+            off[i] = rows;
+            if (i < src.nf && !src.f[i].identity) {
+                const FieldDev<R> &g = src.f[i];
+                const int r0 = g.b[0][ix0], r1 = g.b[0][ix1 - 1] + K;
+                lo[i] = r0;
+                const int by = g.b[1][iy], bz = g.b[2][iz];
+                R wy[K], wz[K];
+#pragma unroll
+                for (int a = 0; a < K; ++a) {
+                    wy[a] = g.w[1][iy * K + a];
+                    wz[a] = g.w[2][iz * K + a];
+                }
+#pragma unroll 1
+                for (int r = t; r < r1 - r0; r += P) {
+                    cx<R> acc = czero<R>();
+                    if (act) {
+                        const cx<R> *base = g.p + (int64_t)(r0 + r) * g.s0 + (int64_t)by * g.s1 + bz;
+#pragma unroll
+                        for (int b = 0; b < K; ++b) {
+                            cx<R> az = czero<R>();
+#pragma unroll
+                            for (int d = 0; d < K; ++d) az = cadd<R>(az, cscale<R>(base[b * g.s1 + d], wz[d]));
+                            acc = cadd<R>(acc, cscale<R>(az, wy[b]));
+                        }
+                    }
+                    stage[(rows + r) * T + c] = acc;
+                }
+                rows += r1 - r0;
+            }
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int ix = ix0 + t; ix < ix1; ix += P) {
+            cx<R> v[NVP_MAX_FIELDS];
+#pragma unroll
+            for (int i = 0; i < NVP_MAX_FIELDS; ++i) {
+                v[i] = czero<R>();
+                if (i < src.nf) {
+                    const FieldDev<R> &g = src.f[i];
+                    if (g.identity) {
+                        if (act) v[i] = g.p[ix * g.s0 + (int64_t)iy * g.s1 + iz];
+                    } else {
+                        const int r = off[i] + g.b[0][ix] - lo[i];
+#pragma unroll
+                        for (int a = 0; a < K; ++a)
+                            v[i] = cadd<R>(v[i], cscale<R>(stage[(r + a) * T + c], g.w[0][ix * K + a]));
+                    }
+                }
+            }
+            cx<R> s = czero<R>();
+#pragma unroll
+            for (int a = 0; a < NVP_MAX_FIELDS; ++a)
+#pragma unroll
+                for (int b = 0; b < NVP_MAX_FIELDS; ++b)
+                    if (a + b == src.nf - 1) s = cadd<R>(s, cmul<R>(v[a], v[b]));
+            lds[ix * T + c] = s;
+        }
+        __syncthreads();
+    }
+    F::template run<true>(
+        t, tw, R(-1), [&](int m) { return m < Nx ? lds[m * T + c] : czero<R>(); },
+        [&](int m, cx<R> v) {
+            if (act) st(0, col, m, v);
+        },
+        [&](int m) -> cx<R> & { return lds[m * T + c]; });
+}
+
 // Contiguous columns (pencils of stride 1), PW pencils per workgroup; lanes
 // run along the pencil.  Column `col` starts at col * pitch.
 template <typename R, int L, int PW, class Ld, class St>
@@ -183,39 +278,41 @@ k_contig(Ld ld, St st, const cx<R> *__restrict__ tw, R sgn, int64_t n_cols) {
         [&](int m) -> cx<R> & { return my[m]; });
 }
 
-// The z pass of the convolution.  Workgroup = the up-to-four pencils
+// The z pass of the convolution.  A quad = the up-to-four pencils
 // (kx, ky), (Mx-kx, ky), (kx, My-ky), (Mx-kx, My-ky) that share one row of the
 // kernel spectrum's octant (the embedded kernel is even on every axis, so
-// K^(k) = K^(M - k)).  Each pencil: Nz inputs -> forward FFT of length Mz ->
-// times K^ -> inverse FFT -> first Nz outputs written back in place.
-template <typename R, int L>
-__global__ void __launch_bounds__(4 * plan_threads(L))
+// K^(k) = K^(M - k)); QW quads per workgroup.  Each pencil: Nz inputs ->
+// forward FFT of length Mz -> times K^ -> inverse FFT -> first Nz outputs
+// written back in place.
+template <typename R, int L, int QW>
+__global__ void __launch_bounds__(4 * QW * plan_threads(L))
 k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int64_t My, int Nz, int64_t Hy,
-        const cx<R> *__restrict__ tw) {
+        int64_t n_quads, const cx<R> *__restrict__ tw) {
     using F = Fft<R, L>;
     constexpr int PAD = 1;
     constexpr int HZ = L / 2 + 1;
     cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
-    const int tid = threadIdx.x, t = tid % F::P, j = tid / F::P;
-    const int64_t quad = blockIdx.x;
-    const int64_t kx = quad / Hy, ky = quad % Hy;
+    const int tid = threadIdx.x, t = tid % F::P, slot = tid / F::P, j = slot & 3;
+    const int64_t quad = (int64_t)blockIdx.x * QW + (slot >> 2);
+    const bool valid = quad < n_quads;
+    const int64_t kx = valid ? quad / Hy : 0, ky = valid ? quad % Hy : 0;
     const int64_t px = (j & 1) ? (Mx - kx) % Mx : kx;
     const int64_t py = (j & 2) ? (My - ky) % My : ky;
-    const bool act = !(((j & 1) && px == kx) || ((j & 2) && py == ky));
+    const bool act = valid && !(((j & 1) && px == kx) || ((j & 2) && py == ky));
     cx<R> *pen = buf + (px * My + py) * (int64_t)Nz;
     const cx<R> *krow = khat + (kx * Hy + ky) * (int64_t)HZ;
-    cx<R> *my = lds + j * (L + PAD);
-    auto slot = [&](int m) -> cx<R> & { return my[m]; };
+    cx<R> *my = lds + slot * (L + PAD);
+    auto ref = [&](int m) -> cx<R> & { return my[m]; };
     F::template run<false>(
         t, tw, R(-1), [&](int m) { return (act && m < Nz) ? pen[m] : czero<R>(); },
-        [&](int k, cx<R> v) { my[k] = cmul<R>(v, krow[k <= L / 2 ? k : L - k]); }, slot);
+        [&](int k, cx<R> v) { my[k] = valid ? cmul<R>(v, krow[k <= L / 2 ? k : L - k]) : czero<R>(); }, ref);
     __syncthreads();
     F::template run<true>(
         t, tw, R(1), [&](int m) { return my[m]; },
         [&](int m, cx<R> v) {
             if (act && m < Nz) pen[m] = v;
         },
-        slot);
+        ref);
 }
 
 // Octant [Hx][Hy][Hz] of the embedded kernel in FP64: K at offset (i, j, k) for

@@ -1,5 +1,6 @@
 // FP64 kernel tabulation and the FP64 passes of the kernel spectrum.
 #include <math.h>
+#include <stdlib.h>
 
 #include "kernels.hpp"
 
@@ -35,6 +36,14 @@ hipError_t launch_ktab(double2 *out, const int64_t H[3], const int64_t N[3], dou
 }
 
 bool length_supported(int L) { return plan_for(L).S > 0; }
+
+int zconv_quads_override() {
+    static const int v = [] {
+        const char *e = getenv("NVP_ZCONV_QUADS");
+        return e ? atoi(e) : 0;
+    }();
+    return v;
+}
 int threads_per_column(int L) { return plan_threads(L); }
 
 }  // namespace nvp

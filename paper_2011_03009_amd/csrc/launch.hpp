@@ -14,6 +14,9 @@
 namespace nvp {
 
 bool length_supported(int L);
+// Tuning switch read once from the environment (NVP_ZCONV_QUADS): 1 forces one
+// pencil quad per z-pass workgroup; anything else keeps the default.
+int zconv_quads_override();
 int threads_per_column(int L);
 
 // Generic strided pass: element m of column (o, col) is read at
@@ -51,6 +54,7 @@ struct SourceArgs {
     void *out;  // A [Mx][Ny][Nz]
     int64_t out_ms;  // Ny * Nz
     int64_t inner;   // Ny * Nz
+    int chunk;       // > 0: staged separable transfer with this x-chunk; 0: direct gathers
 };
 
 hipError_t launch_strided_c64(int L, const StridedArgs &a, const void *tw, hipStream_t s);

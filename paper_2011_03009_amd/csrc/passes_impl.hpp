@@ -93,13 +93,21 @@ template <typename R, int L, int K> hipError_t xsrc_impl_k(const SourceArgs &a, 
     ld.Nx = a.Nx;
     ld.Nz = a.Nz;
     St st{static_cast<cx<R> *>(a.out), 0, a.out_ms, L, R(1)};
-    auto kern = k_xsrc<R, L, T, K, St>;
     const size_t lds = (size_t)T * L * sizeof(cx<R>);
-    static const hipError_t attr = allow_lds(kern, lds);
-    if (attr != hipSuccess) return attr;
     dim3 grid((unsigned)((a.inner + T - 1) / T), 1);
-    hipLaunchKernelGGL(kern, grid, dim3(T * plan_threads(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
-                       a.inner);
+    if (a.chunk > 0) {
+        auto kern = k_xsrc_staged<R, L, T, K, St>;
+        static const hipError_t attr = allow_lds(kern, lds);
+        if (attr != hipSuccess) return attr;
+        hipLaunchKernelGGL(kern, grid, dim3(T * plan_threads(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
+                           a.inner, a.chunk);
+    } else {
+        auto kern = k_xsrc<R, L, T, K, St>;
+        static const hipError_t attr = allow_lds(kern, lds);
+        if (attr != hipSuccess) return attr;
+        hipLaunchKernelGGL(kern, grid, dim3(T * plan_threads(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
+                           a.inner);
+    }
     return hipGetLastError();
 }
 
@@ -109,17 +117,25 @@ template <typename R, int L> hipError_t xsrc_impl(const SourceArgs &a, const voi
     return hipErrorInvalidValue;
 }
 
-template <typename R, int L>
-hipError_t zconv_impl(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, hipStream_t s) {
-    auto kern = k_zconv<R, L>;
-    const size_t lds = (size_t)4 * (L + 1) * sizeof(cx<R>);
+template <typename R, int L, int QW>
+hipError_t zconv_qw(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, hipStream_t s) {
+    auto kern = k_zconv<R, L, QW>;
+    const size_t lds = (size_t)4 * QW * (L + 1) * sizeof(cx<R>);
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
-    const int64_t Hx = Mx / 2 + 1, Hy = My / 2 + 1;
-    hipLaunchKernelGGL(kern, dim3((unsigned)(Hx * Hy)), dim3(4 * plan_threads(L)), lds, s,
-                       static_cast<cx<R> *>(buf), static_cast<const cx<R> *>(khat), Mx, My, Nz, Hy,
+    const int64_t Hx = Mx / 2 + 1, Hy = My / 2 + 1, nq = Hx * Hy;
+    hipLaunchKernelGGL(kern, dim3((unsigned)((nq + QW - 1) / QW)), dim3(4 * QW * plan_threads(L)), lds, s,
+                       static_cast<cx<R> *>(buf), static_cast<const cx<R> *>(khat), Mx, My, Nz, Hy, nq,
                        static_cast<const cx<R> *>(tw));
     return hipGetLastError();
+}
+
+template <typename R, int L>
+hipError_t zconv_impl(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, hipStream_t s) {
+    // quads per workgroup: up to 256 threads and 80 KiB of LDS
+    constexpr int QW = (4 * plan_threads(L) <= 128 && 8 * (L + 1) * (int)sizeof(cx<R>) <= 81920) ? 2 : 1;
+    if (zconv_quads_override() == 1) return zconv_qw<R, L, 1>(buf, khat, Mx, My, Nz, tw, s);
+    return zconv_qw<R, L, QW>(buf, khat, Mx, My, Nz, tw, s);
 }
 
 }  // namespace nvp

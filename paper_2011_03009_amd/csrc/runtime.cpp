@@ -63,6 +63,7 @@ struct Harm {
     double kr = 0, ki = 0, Cn = 0;
     void *khat = nullptr;
     bool khat_ok = false;
+    int chunk = 0;  // x-chunk of the staged source build (0: direct gathers)
     HarmField f[NVP_MAX_FIELDS];
 };
 
@@ -659,6 +660,30 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
             }
         }
     }
+    // Chunk of the staged source build: the largest x-chunk whose source rows
+    // (K-point stencils of every interpolated field) fit in the Mx - Nx rows
+    // of the x pass's LDS slot that the zero-padded transform leaves unused.
+    for (auto &h : p->h) {
+        const int64_t Nx = h.g.n[0], cap = h.M[0] - Nx;
+        std::vector<const int *> bx;
+        for (int m = 1; m < h.n; ++m)
+            if (!h.f[m - 1].identity) bx.push_back(reinterpret_cast<const int *>(host.data() + h.f[m - 1].off_b[0]));
+        h.chunk = 0;
+        if (bx.empty()) {
+            h.chunk = (int)Nx;
+            continue;
+        }
+        for (int64_t c = Nx; c >= 1 && !h.chunk; --c) {
+            bool ok = true;
+            for (int64_t i0 = 0; i0 < Nx && ok; i0 += c) {
+                const int64_t i1 = i0 + c < Nx ? i0 + c : Nx;
+                int64_t rows = 0;
+                for (const int *b : bx) rows += b[i1 - 1] + K - b[i0];
+                ok = rows <= cap;
+            }
+            if (ok) h.chunk = (int)c;
+        }
+    }
     hipError_t e = hipSuccess;
     if (tbytes) e = hipMalloc(&p->tables, tbytes);
     if (e == hipSuccess) e = hipMalloc(&p->A, maxA);
@@ -713,6 +738,7 @@ nvp_status nvp_execute_harmonic(nvp_plan *plan, int n, const void *const *fields
     src.order = plan->order;
     src.Nx = (int)h.g.n[0];
     src.Nz = (int)h.g.n[2];
+    src.chunk = h.chunk;
     const unsigned char *tb = static_cast<const unsigned char *>(plan->tables);
     for (int m = 1; m < n; ++m) {
         const nvp_grid &sg = m == 1 ? plan->g1 : plan->h[m - 2].g;

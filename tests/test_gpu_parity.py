@@ -131,20 +131,24 @@ def test_tiny_config_p2_matches_direct_sum(ctx, prec):
     plan.close()
 
 
-def nested_grids(scale=1):
+def nested_grids(short_x=False):
+    """Tiny nested grids.  short_x: x axes of 8 voxels (circulant 16), too short to stage four
+    cubic stencils in the x pass, so the source build takes its direct-gather path."""
     focus = (15e-3, 0.0, 0.0)
     c0 = WATER["c0"]
     g1 = oracle.grid_from_counts(focus, oracle.spacing(1, F0, c0), (10, 9, 8), (5, 4, 4))
-    gn = {n: oracle.grid_from_counts(focus, oracle.spacing(n, F0, c0), (8 + 2 * n, 11, 10), (6, 5, 4))
+    gn = {n: oracle.grid_from_counts(focus, oracle.spacing(n, F0, c0), (8 if short_x else 8 + 2 * n, 11, 10),
+                                     (4 if short_x else 6, 5, 4))
           for n in range(2, 6)}
     return focus, g1, gn
 
 
+@pytest.mark.parametrize("short_x", [False, True])
 @pytest.mark.parametrize("prec", [P.NVP_C128, P.NVP_C64])
 @pytest.mark.parametrize("order", [1, 3])
-def test_tiny_nested_cascade_matches_oracle(ctx, order, prec):
-    focus, g1, gn = nested_grids()
-    say("case nested-cascade order=%d prec=%d" % (order, prec))
+def test_tiny_nested_cascade_matches_oracle(ctx, order, prec, short_x):
+    focus, g1, gn = nested_grids(short_x)
+    say("case nested-cascade order=%d prec=%d short_x=%d" % (order, prec, short_x))
     k1 = oracle.wavenumber(1, F0, WATER)
     pts = bowl.bowl_points(7.5e-3, 15e-3, 128, 1)
     p1 = bowl.incident_field(pts, 7.5e-3, 15e-3, k1, 1e6, g1.coords(0), g1.coords(1), g1.coords(2)).numpy()

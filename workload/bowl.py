@@ -73,7 +73,11 @@ def incident_field(points, R, l, k1, p0, xs, ys, zs, device="cpu", chunk=4096):
     kr, ki = k1.real, k1.imag
     for s in range(0, tgt.shape[0], chunk):
         t = tgt[s:s + chunk]
-        r = torch.cdist(t, P, compute_mode="donot_use_mm_for_euclid_dist")
+        dx = t[:, 0:1] - P[None, :, 0]
+        dy = t[:, 1:2] - P[None, :, 1]
+        dz = t[:, 2:3] - P[None, :, 2]
+        r = torch.sqrt(dx * dx + dy * dy + dz * dz)
+        del dx, dy, dz
         amp = torch.exp(-ki * r) / r
         ph = kr * r
         re = (amp * torch.cos(ph)).sum(dim=1)
