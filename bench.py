@@ -65,8 +65,8 @@ def alg_bytes(P, g1, gn, order_fields):
         M = [P.circulant_size(v) for v in N]
         H = [m // 2 + 1 for m in M]
         Ho = H[0] * H[1] * H[2]
-        b["ktab"] += 16.0 * Ho
-        b["kfft"] += 16.0 * Ho * 2 * 3 - 16.0 * Ho + 8.0 * Ho  # three FP64 passes; last writes complex64
+        b["ktab"] += 16.0 * Ho  # tabulation fused into the z pass: FP64 octant written once
+        b["kfft"] += 16.0 * Ho * 2 + 16.0 * Ho + 8.0 * Ho  # y pass r+w FP64; x pass reads FP64, writes complex64
         src = sum(nsz(grids[m - 1]) for m in range(1, n))
         b["xfwd"] += ELEM * (src + M[0] * N[1] * N[2])
         b["yfwd"] += ELEM * (M[0] * N[1] * N[2] + M[0] * M[1] * N[2])
@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--no-uniform", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--calib", action="store_true",
+                    help="only copy 1 GiB device-to-device 3 times (a known-size reference for HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; every configuration fits one MI355X "
@@ -137,6 +139,15 @@ def main():
     import torch
     import paper_2011_03009_amd as P
     from workload import configs
+
+    if a.calib:
+        src = torch.ones(1 << 27, dtype=torch.complex64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": src.numel() * 8, "copies": 3}))
+        return
 
     cfg = configs.paper_scale(P_f=a.pf)
     W = cfg["medium"]

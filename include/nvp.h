@@ -148,8 +148,8 @@ nvp_status nvp_plan_destroy(nvp_plan *plan);
 /* ---- timing of the plan's kernels ---------------------------------------- */
 
 /* Kinds of kernel timed by nvp_plan_get_timing. */
-#define NVP_T_KTAB 0   /* kernel tabulation, FP64 */
-#define NVP_T_KFFT 1   /* kernel spectrum: three FP64 FFT passes and downcast */
+#define NVP_T_KTAB 0   /* kernel tabulation fused with the first (z) FP64 FFT pass */
+#define NVP_T_KFFT 1   /* kernel spectrum: the y and x FP64 FFT passes and the downcast */
 #define NVP_T_XFWD 2   /* transfer + source build fused into the forward x pass */
 #define NVP_T_YFWD 3   /* forward y pass */
 #define NVP_T_ZCONV 4  /* z pass: forward FFT, spectral multiply, inverse FFT */

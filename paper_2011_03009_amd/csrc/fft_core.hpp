@@ -196,17 +196,28 @@ __host__ __device__ constexpr int plan_threads(int L) { return plan_for(L).E ? L
 
 // ---------------------------------------------------------------- engine
 
-template <typename R, int L> struct Fft {
+// REV = true runs the stages in reverse radix order.  Its first stage then has
+// the radix of the forward plan's last stage, so a forward transform's
+// outputs, as left in registers by compute_keep(), are exactly the inputs the
+// reversed transform's first stage expects in the same thread and slot.
+template <typename R, int L, bool REV = false> struct Fft {
     static constexpr PlanDesc D = plan_for(L);
     static constexpr int S = D.S;
     static constexpr int E = D.E;
     static constexpr int P = L / E;  // threads per column
     static_assert(S > 0, "unsupported FFT length");
 
-    template <int s> static constexpr int ns() {
+    static constexpr int rad(int s) { return REV ? D.r[S - 1 - s] : D.r[s]; }
+    static constexpr int ns(int s) {
         int n = 1;
-        for (int i = 0; i < s; ++i) n *= D.r[i];
+        for (int i = 0; i < s; ++i) n *= rad(i);
         return n;
+    }
+
+    // Output index held in register `slot` after the last stage.
+    static __device__ __forceinline__ int out_index(int t, int slot) {
+        constexpr int r = rad(S - 1);
+        return t + (slot / r) * P + (slot % r) * (L / r);
     }
 
     template <int r> static __device__ __forceinline__ void bflies(cx<R> *v, R sgn) {
@@ -214,37 +225,57 @@ template <typename R, int L> struct Fft {
         for (int i = 0; i < E / r; ++i) Dft<r, R>::run(v + i * r, sgn);
     }
 
-    // Transform this thread's share of one column.
-    //   ld(m)     -> input element m (first stage)
-    //   st(m, x)  <- output element m (last stage, natural order)
-    //   lds(m)    -> reference to element m of this column's LDS slot
-    // LDS_IN: ld reads the same LDS slot, so wait before overwriting it.
-    template <bool LDS_IN, class Ld, class St, class Lds>
-    static __device__ __forceinline__ void run(int t, const cx<R> *__restrict__ tw, R sgn, Ld ld, St st, Lds lds) {
-        cx<R> v[E];
-        constexpr int r0 = D.r[0];
+    // First-stage inputs: v[i r0 + q] = x[t + i P + q L / r0].
+    template <class Ld> static __device__ __forceinline__ void load0(cx<R> *v, int t, Ld ld) {
+        constexpr int r0 = rad(0);
 #pragma unroll
         for (int i = 0; i < E / r0; ++i) {
             const int b = t + i * P;
 #pragma unroll
             for (int q = 0; q < r0; ++q) v[i * r0 + q] = ld(b + q * (L / r0));
         }
-        if constexpr (LDS_IN) __syncthreads();
-        bflies<r0>(v, sgn);
-        next<0>(v, t, tw, sgn, st, lds);
     }
 
-    template <int s, class St, class Lds>
-    static __device__ __forceinline__ void next(cx<R> *v, int t, const cx<R> *__restrict__ tw, R sgn, St st,
-                                                Lds lds) {
-        constexpr int r = D.r[s];
-        constexpr int Ns = ns<s>();
+    // All stages on v (loaded by load0); st(m, x) receives the outputs.
+    template <class Tw, class St, class Lds>
+    static __device__ __forceinline__ void compute(cx<R> *v, int t, Tw tw, R sgn, St st, Lds lds) {
+        bflies<rad(0)>(v, sgn);
+        next<0, true>(v, t, tw, sgn, st, lds);
+    }
+
+    // All stages on v; the outputs stay in v (see out_index).
+    template <class Tw, class Lds>
+    static __device__ __forceinline__ void compute_keep(cx<R> *v, int t, Tw tw, R sgn, Lds lds) {
+        bflies<rad(0)>(v, sgn);
+        next<0, false>(v, t, tw, sgn, [](int, cx<R>) {}, lds);
+    }
+
+    // Transform this thread's share of one column.
+    //   ld(m)     -> input element m (first stage)
+    //   st(m, x)  <- output element m (last stage, natural order)
+    //   lds(m)    -> reference to element m of this column's LDS slot
+    // LDS_IN: ld reads the same LDS slot, so wait before overwriting it.
+    // tw(e) -> W^e, W = exp(-2 pi i / L) (a global or LDS table).
+    template <bool LDS_IN, class Tw, class Ld, class St, class Lds>
+    static __device__ __forceinline__ void run(int t, Tw tw, R sgn, Ld ld, St st, Lds lds) {
+        cx<R> v[E];
+        load0(v, t, ld);
+        if constexpr (LDS_IN) __syncthreads();
+        compute(v, t, tw, sgn, st, lds);
+    }
+
+    template <int s, bool STORE, class Tw, class St, class Lds>
+    static __device__ __forceinline__ void next(cx<R> *v, int t, Tw tw, R sgn, St st, Lds lds) {
+        constexpr int r = rad(s);
+        constexpr int Ns = ns(s);
         if constexpr (s == S - 1) {
+            if constexpr (STORE) {
 #pragma unroll
-            for (int i = 0; i < E / r; ++i) {
-                const int b = t + i * P;
+                for (int i = 0; i < E / r; ++i) {
+                    const int b = t + i * P;
 #pragma unroll
-                for (int p = 0; p < r; ++p) st(b + p * (L / r), v[i * r + p]);
+                    for (int p = 0; p < r; ++p) st(b + p * (L / r), v[i * r + p]);
+                }
             }
         } else {
 #pragma unroll
@@ -255,7 +286,7 @@ template <typename R, int L> struct Fft {
                 for (int p = 0; p < r; ++p) lds(base + p * Ns) = v[i * r + p];
             }
             __syncthreads();
-            constexpr int r1 = D.r[s + 1];
+            constexpr int r1 = rad(s + 1);
             constexpr int Ns1 = Ns * r;
             constexpr int tstep = L / (Ns1 * r1);
 #pragma unroll
@@ -265,14 +296,14 @@ template <typename R, int L> struct Fft {
                 v[i * r1] = lds(b);
 #pragma unroll
                 for (int q = 1; q < r1; ++q) {
-                    cx<R> w = tw[j * q * tstep];
+                    cx<R> w = tw(j * q * tstep);
                     if (sgn > R(0)) w.y = -w.y;
                     v[i * r1 + q] = cmul<R>(lds(b + q * (L / r1)), w);
                 }
             }
             __syncthreads();
             bflies<r1>(v, sgn);
-            next<s + 1>(v, t, tw, sgn, st, lds);
+            next<s + 1, STORE>(v, t, tw, sgn, st, lds);
         }
     }
 };

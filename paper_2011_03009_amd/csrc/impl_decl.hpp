@@ -13,4 +13,8 @@ template <typename R, int L> hipError_t xsrc_impl(const SourceArgs &, const void
 template <typename R, int L>
 hipError_t zconv_impl(void *, const void *, int64_t, int64_t, int, const void *, hipStream_t);
 
+template <int L>
+hipError_t kz_impl(double2 *, const int64_t[3], const int64_t[3], double, double, double, double, double, const void *,
+                   hipStream_t);
+
 }  // namespace nvp

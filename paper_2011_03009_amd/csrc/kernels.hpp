@@ -118,24 +118,67 @@ template <typename R, int K> struct LdSource {
 
 extern __shared__ __align__(16) unsigned char nvp_smem[];
 
+// LDS slot of a contiguous pencil: one pad element per 16 spreads the strided
+// writes of the early Stockham stages over the banks.
+__host__ __device__ constexpr int padded(int m) { return m + (m >> 4); }
+__host__ __device__ constexpr int slot_len(int L) { return padded(L) + 1; }
+
+// Twiddle table W^e, e < L: copied into LDS behind the workgroup's data when
+// it fits (every later stage reads it with low latency), else read from the
+// global table through the caches.
+template <typename R, int L> __device__ __forceinline__ void stage_twiddles(cx<R> *dst, const cx<R> *src) {
+    for (int e = threadIdx.x; e < L; e += blockDim.x) dst[e] = src[e];
+}
+// Staged only when it costs no occupancy: as many workgroups fit per CU
+// (160 KiB of LDS) with the table as without it.
+template <typename R, int L> constexpr bool tw_fits(size_t data_elems) {
+    const size_t d = data_elems * sizeof(cx<R>), w = (data_elems + L) * sizeof(cx<R>);
+    return w <= 163840 && 163840 / w == 163840 / d;
+}
+
 // Columns strided by `ms` with T consecutive columns (contiguous in memory)
 // per workgroup: lanes run over columns first, so every row access of a wave
 // reads T * sizeof(complex) contiguous bytes.  grid = (ceil(inner / T), outer).
-template <typename R, int L, int T, class Ld, class St>
+// MIRROR: the columns hold entries 0..L/2 of even sequences; they are read
+// once into LDS and the transform takes its first stage from there.
+template <typename R, int L, int T, bool MIRROR, class Ld, class St>
 __global__ void __launch_bounds__(T *plan_threads(L))
 k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, R sgn, int64_t inner) {
     using F = Fft<R, L>;
+    constexpr bool TWL = tw_fits<R, L>((size_t)T * L);
     cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
+    cx<R> *twl = lds + T * L;
+    auto twf = [&](int e) { return TWL ? twl[e] : tw[e]; };
     const int tid = threadIdx.x, c = tid % T, t = tid / T;
     const int64_t col = (int64_t)blockIdx.x * T + c;
     const int64_t o = blockIdx.y;
     const bool act = col < inner;
-    F::template run<false>(
-        t, tw, sgn, [&](int m) { return act ? ld(o, col, m) : czero<R>(); },
-        [&](int m, cx<R> v) {
-            if (act) st(o, col, m, v);
-        },
-        [&](int m) -> cx<R> & { return lds[m * T + c]; });
+    auto ref = [&](int m) -> cx<R> & { return lds[m * T + c]; };
+    auto store = [&](int m, cx<R> v) {
+        if (act) st(o, col, m, v);
+    };
+    if constexpr (MIRROR) {
+        constexpr int NH = (L / 2 + F::P) / F::P;  // entries 0..L/2 per thread, all loads issued first
+        cx<R> h[NH];
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+            const int m = t + i * F::P;
+            h[i] = (act && m <= L / 2) ? ld(o, col, m) : czero<R>();
+        }
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+            const int m = t + i * F::P;
+            if (m <= L / 2) lds[m * T + c] = h[i];
+        }
+        if constexpr (TWL) stage_twiddles<R, L>(twl, tw);
+        __syncthreads();
+        F::template run<true>(t, twf, sgn, [&](int m) { return lds[(m <= L / 2 ? m : L - m) * T + c]; }, store, ref);
+    } else {
+        cx<R> v[F::E];
+        F::load0(v, t, [&](int m) { return act ? ld(o, col, m) : czero<R>(); });
+        if constexpr (TWL) stage_twiddles<R, L>(twl, tw);
+        F::compute(v, t, twf, sgn, store, ref);
+    }
 }
 
 // Forward x pass with the source build fused in front: each thread first
@@ -152,11 +195,15 @@ k_xsrc(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t inner) {
     const bool act = col < inner;
     const int iy = act ? (int)(col / src.Nz) : 0, iz = act ? (int)(col % src.Nz) : 0;
     const int Nx = src.Nx;
+    constexpr bool TWL = tw_fits<R, L>((size_t)T * L);
+    cx<R> *twl = lds + T * L;
+    if constexpr (TWL) stage_twiddles<R, L>(twl, tw);
+    auto twf = [&](int e) { return TWL ? twl[e] : tw[e]; };
 #pragma unroll 1
     for (int m = t; m < Nx; m += F::P) lds[m * T + c] = act ? src.value(m, iy, iz) : czero<R>();
     __syncthreads();
     F::template run<true>(
-        t, tw, R(-1), [&](int m) { return m < Nx ? lds[m * T + c] : czero<R>(); },
+        t, twf, R(-1), [&](int m) { return m < Nx ? lds[m * T + c] : czero<R>(); },
         [&](int m, cx<R> v) {
             if (act) st(0, col, m, v);
         },
@@ -183,6 +230,10 @@ k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t i
     const int iy = act ? (int)(col / src.Nz) : 0, iz = act ? (int)(col % src.Nz) : 0;
     const int Nx = src.Nx;
     cx<R> *stage = lds + (int64_t)Nx * T;
+    constexpr bool TWL = tw_fits<R, L>((size_t)T * L);
+    cx<R> *twl = lds + T * L;
+    if constexpr (TWL) stage_twiddles<R, L>(twl, tw);
+    auto twf = [&](int e) { return TWL ? twl[e] : tw[e]; };
 #pragma unroll 1
     for (int ix0 = 0; ix0 < Nx; ix0 += chunk) {
         const int ix1 = ix0 + chunk < Nx ? ix0 + chunk : Nx;
@@ -203,7 +254,7 @@ k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t i
                     wy[a] = g.w[1][iy * K + a];
                     wz[a] = g.w[2][iz * K + a];
                 }
-#pragma unroll 1
+#pragma unroll 4
                 for (int r = t; r < r1 - r0; r += P) {
                     cx<R> acc = czero<R>();
                     if (act) {
@@ -222,7 +273,7 @@ k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t i
             }
         }
         __syncthreads();
-#pragma unroll 1
+#pragma unroll 2
         for (int ix = ix0 + t; ix < ix1; ix += P) {
             cx<R> v[NVP_MAX_FIELDS];
 #pragma unroll
@@ -251,7 +302,7 @@ k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t i
         __syncthreads();
     }
     F::template run<true>(
-        t, tw, R(-1), [&](int m) { return m < Nx ? lds[m * T + c] : czero<R>(); },
+        t, twf, R(-1), [&](int m) { return m < Nx ? lds[m * T + c] : czero<R>(); },
         [&](int m, cx<R> v) {
             if (act) st(0, col, m, v);
         },
@@ -264,18 +315,20 @@ template <typename R, int L, int PW, class Ld, class St>
 __global__ void __launch_bounds__(PW *plan_threads(L))
 k_contig(Ld ld, St st, const cx<R> *__restrict__ tw, R sgn, int64_t n_cols) {
     using F = Fft<R, L>;
-    constexpr int PAD = 1;
     cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
     const int tid = threadIdx.x, t = tid % F::P, c = tid / F::P;
     const int64_t col = (int64_t)blockIdx.x * PW + c;
     const bool act = col < n_cols;
-    cx<R> *my = lds + c * (L + PAD);
+    cx<R> *my = lds + c * slot_len(L);
+    cx<R> *twl = lds + PW * slot_len(L);
+    stage_twiddles<R, L>(twl, tw);
+    auto twf = [&](int e) { return twl[e]; };
     F::template run<false>(
-        t, tw, sgn, [&](int m) { return act ? ld(0, col, m) : czero<R>(); },
+        t, twf, sgn, [&](int m) { return act ? ld(0, col, m) : czero<R>(); },
         [&](int m, cx<R> v) {
             if (act) st(0, col, m, v);
         },
-        [&](int m) -> cx<R> & { return my[m]; });
+        [&](int m) -> cx<R> & { return my[padded(m)]; });
 }
 
 // The z pass of the convolution.  A quad = the up-to-four pencils
@@ -283,13 +336,16 @@ k_contig(Ld ld, St st, const cx<R> *__restrict__ tw, R sgn, int64_t n_cols) {
 // kernel spectrum's octant (the embedded kernel is even on every axis, so
 // K^(k) = K^(M - k)); QW quads per workgroup.  Each pencil: Nz inputs ->
 // forward FFT of length Mz -> times K^ -> inverse FFT -> first Nz outputs
-// written back in place.
+// written back in place.  The inverse runs the radix plan in reverse order,
+// so the forward outputs feed it straight from registers, where the product
+// with K^ is taken.
 template <typename R, int L, int QW>
 __global__ void __launch_bounds__(4 * QW * plan_threads(L))
 k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int64_t My, int Nz, int64_t Hy,
         int64_t n_quads, const cx<R> *__restrict__ tw) {
-    using F = Fft<R, L>;
-    constexpr int PAD = 1;
+    using F = Fft<R, L, false>;
+    using G = Fft<R, L, true>;
+    constexpr int E = F::E;
     constexpr int HZ = L / 2 + 1;
     cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
     const int tid = threadIdx.x, t = tid % F::P, slot = tid / F::P, j = slot & 3;
@@ -301,18 +357,74 @@ k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int
     const bool act = valid && !(((j & 1) && px == kx) || ((j & 2) && py == ky));
     cx<R> *pen = buf + (px * My + py) * (int64_t)Nz;
     const cx<R> *krow = khat + (kx * Hy + ky) * (int64_t)HZ;
-    cx<R> *my = lds + slot * (L + PAD);
-    auto ref = [&](int m) -> cx<R> & { return my[m]; };
-    F::template run<false>(
-        t, tw, R(-1), [&](int m) { return (act && m < Nz) ? pen[m] : czero<R>(); },
-        [&](int k, cx<R> v) { my[k] = valid ? cmul<R>(v, krow[k <= L / 2 ? k : L - k]) : czero<R>(); }, ref);
+    cx<R> *my = lds + slot * slot_len(L);
+    cx<R> *twl = lds + 4 * QW * slot_len(L);
+    cx<R> *kl = twl + L + (slot >> 2) * HZ;  // this quad's K^ row
+    auto ref = [&](int m) -> cx<R> & { return my[padded(m)]; };
+    cx<R> v[E];
+    F::load0(v, t, [&](int m) { return (act && m < Nz) ? pen[m] : czero<R>(); });
+    stage_twiddles<R, L>(twl, tw);
+    if (j == 0)
+        for (int k = t; k < HZ; k += F::P) kl[k] = valid ? krow[k] : czero<R>();
+    auto twf = [&](int e) { return twl[e]; };
+    F::compute_keep(v, t, twf, R(-1), ref);
+    if constexpr (F::S == 1) __syncthreads();  // K^ row staged above; longer plans synchronise inside
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int k = F::out_index(t, i);
+        v[i] = cmul<R>(v[i], kl[k <= L / 2 ? k : L - k]);
+    }
+    G::compute(v, t, twf, R(1),
+               [&](int m, cx<R> x) {
+                   if (act && m < Nz) pen[m] = x;
+               },
+               ref);
+}
+
+// First pass of the kernel spectrum, fused with the kernel's tabulation: one
+// octant row (i, j) per pencil.  The row's Hz = L/2+1 values of K at offsets
+// (i, j, k) -- h^3 G_k(|d| h) of equation "quad", the self value at the
+// origin, zero for k >= Nz or beyond the grid in x or y (the embedding is
+// exact for M >= 2N - 1) -- are computed into LDS in FP64, then the FFT of the
+// even extension to length L is written back as the row's first Hz outputs.
+template <int L, int PW>
+__global__ void __launch_bounds__(PW *plan_threads(L))
+k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, int64_t Nz, double h, double kr,
+     double ki, double2 self, const double2 *__restrict__ tw) {
+    using F = Fft<double, L>;
+    constexpr int HZ = L / 2 + 1;
+    cx<double> *lds = reinterpret_cast<cx<double> *>(nvp_smem);
+    const int tid = threadIdx.x, t = tid % F::P, c = tid / F::P;
+    const int64_t row = (int64_t)blockIdx.x * PW + c;
+    const bool act = row < Hx * Hy;
+    const int64_t i = act ? row / Hy : 0, jj = act ? row % Hy : 0;
+    cx<double> *my = lds + c * slot_len(L);
+    cx<double> *twl = lds + PW * slot_len(L);
+    stage_twiddles<double, L>(twl, tw);
+    auto twf = [&](int e) { return twl[e]; };
+#pragma unroll 1
+    for (int k = t; k < HZ; k += F::P) {
+        double2 v = make_double2(0.0, 0.0);
+        if (act && i < Nx && jj < Ny && k < Nz) {
+            if (i == 0 && jj == 0 && k == 0) {
+                v = self;
+            } else {
+                const double d = h * sqrt((double)(i * i + jj * jj + (int64_t)k * k));
+                const double mag = h * h * h * exp(-ki * d) / (4.0 * M_PI * d);
+                double sn, cs;
+                sincos(kr * d, &sn, &cs);
+                v = make_double2(mag * cs, mag * sn);
+            }
+        }
+        my[padded(k)] = v;
+    }
     __syncthreads();
     F::template run<true>(
-        t, tw, R(1), [&](int m) { return my[m]; },
-        [&](int m, cx<R> v) {
-            if (act && m < Nz) pen[m] = v;
+        t, twf, -1.0, [&](int m) { return my[padded(m <= L / 2 ? m : L - m)]; },
+        [&](int m, cx<double> v) {
+            if (act && m < HZ) out[row * HZ + m] = v;
         },
-        ref);
+        [&](int m) -> cx<double> & { return my[padded(m)]; });
 }
 
 // Octant [Hx][Hy][Hz] of the embedded kernel in FP64: K at offset (i, j, k) for

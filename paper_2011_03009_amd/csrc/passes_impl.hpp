@@ -16,7 +16,7 @@ template <typename R> constexpr int strided_cols(int L) {
 // Pencils per workgroup of the contiguous kernel: about 256 threads, LDS <= 128 KiB.
 template <typename R> constexpr int contig_pencils(int L) {
     const int by_threads = 256 / plan_threads(L) > 0 ? 256 / plan_threads(L) : 1;
-    const int by_lds = (int)(131072 / ((L + 1) * (int)sizeof(cx<R>)));
+    const int by_lds = (int)((131072 - L * (int)sizeof(cx<R>)) / (slot_len(L) * (int)sizeof(cx<R>)));
     const int p = by_threads < by_lds ? by_threads : by_lds;
     return p > 0 ? p : 1;
 }
@@ -34,11 +34,23 @@ hipError_t strided_impl(const StridedArgs &a, const void *tw, hipStream_t s) {
     using St = StPlain<R, Rout>;
     Ld ld{static_cast<const cx<R> *>(a.in), a.in_os, a.in_ms, a.n_in, a.mirror};
     St st{static_cast<cx<Rout> *>(a.out), a.out_os, a.out_ms, a.n_out, (R)a.scale};
-    auto kern = k_strided<R, L, T, Ld, St>;
-    const size_t lds = (size_t)T * L * sizeof(cx<R>);
+    const size_t lds = ((size_t)T * L + (tw_fits<R, L>((size_t)T * L) ? L : 0)) * sizeof(cx<R>);
+    dim3 grid((unsigned)((a.inner + T - 1) / T), (unsigned)a.outer);
+    if constexpr (sizeof(R) == 8) {
+        if (a.mirror) {
+            auto kern = k_strided<R, L, T, true, Ld, St>;
+            static const hipError_t attr = allow_lds(kern, lds);
+            if (attr != hipSuccess) return attr;
+            hipLaunchKernelGGL(kern, grid, dim3(T * plan_threads(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
+                               (R)a.sign, a.inner);
+            return hipGetLastError();
+        }
+    } else if (a.mirror) {
+        return hipErrorInvalidValue;
+    }
+    auto kern = k_strided<R, L, T, false, Ld, St>;
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
-    dim3 grid((unsigned)((a.inner + T - 1) / T), (unsigned)a.outer);
     hipLaunchKernelGGL(kern, grid, dim3(T * plan_threads(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
                        (R)a.sign, a.inner);
     return hipGetLastError();
@@ -64,7 +76,7 @@ template <typename R, int L> hipError_t contig_impl(const StridedArgs &a, const 
     LdP lp{ld, a.in_os};
     StP sp{st, a.out_os};
     auto kern = k_contig<R, L, PW, LdP, StP>;
-    const size_t lds = (size_t)PW * (L + 1) * sizeof(cx<R>);
+    const size_t lds = ((size_t)PW * slot_len(L) + L) * sizeof(cx<R>);
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
     dim3 grid((unsigned)((a.inner + PW - 1) / PW));
@@ -93,7 +105,7 @@ template <typename R, int L, int K> hipError_t xsrc_impl_k(const SourceArgs &a, 
     ld.Nx = a.Nx;
     ld.Nz = a.Nz;
     St st{static_cast<cx<R> *>(a.out), 0, a.out_ms, L, R(1)};
-    const size_t lds = (size_t)T * L * sizeof(cx<R>);
+    const size_t lds = ((size_t)T * L + (tw_fits<R, L>((size_t)T * L) ? L : 0)) * sizeof(cx<R>);
     dim3 grid((unsigned)((a.inner + T - 1) / T), 1);
     if (a.chunk > 0) {
         auto kern = k_xsrc_staged<R, L, T, K, St>;
@@ -120,7 +132,7 @@ template <typename R, int L> hipError_t xsrc_impl(const SourceArgs &a, const voi
 template <typename R, int L, int QW>
 hipError_t zconv_qw(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, hipStream_t s) {
     auto kern = k_zconv<R, L, QW>;
-    const size_t lds = (size_t)4 * QW * (L + 1) * sizeof(cx<R>);
+    const size_t lds = ((size_t)4 * QW * slot_len(L) + L + QW * (L / 2 + 1)) * sizeof(cx<R>);
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
     const int64_t Hx = Mx / 2 + 1, Hy = My / 2 + 1, nq = Hx * Hy;
@@ -133,9 +145,25 @@ hipError_t zconv_qw(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz,
 template <typename R, int L>
 hipError_t zconv_impl(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, hipStream_t s) {
     // quads per workgroup: up to 256 threads and 80 KiB of LDS
-    constexpr int QW = (4 * plan_threads(L) <= 128 && 8 * (L + 1) * (int)sizeof(cx<R>) <= 81920) ? 2 : 1;
+    constexpr int QW = (4 * plan_threads(L) <= 128 && (8 * slot_len(L) + L + L + 2) * (int)sizeof(cx<R>) <= 81920)
+                           ? 2 : 1;
     if (zconv_quads_override() == 1) return zconv_qw<R, L, 1>(buf, khat, Mx, My, Nz, tw, s);
     return zconv_qw<R, L, QW>(buf, khat, Mx, My, Nz, tw, s);
+}
+
+template <int L>
+hipError_t kz_impl(double2 *out, const int64_t H[3], const int64_t N[3], double h, double kr, double ki,
+                   double self_re, double self_im, const void *tw, hipStream_t s) {
+    constexpr int PW = contig_pencils<double>(L);
+    auto kern = k_kz<L, PW>;
+    const size_t lds = ((size_t)PW * slot_len(L) + L) * sizeof(double2);
+    static const hipError_t attr = allow_lds(kern, lds);
+    if (attr != hipSuccess) return attr;
+    const int64_t rows = H[0] * H[1];
+    hipLaunchKernelGGL(kern, dim3((unsigned)((rows + PW - 1) / PW)), dim3(PW * plan_threads(L)), lds, s, out, H[0],
+                       H[1], N[0], N[1], N[2], h, kr, ki, make_double2(self_re, self_im),
+                       static_cast<const double2 *>(tw));
+    return hipGetLastError();
 }
 
 }  // namespace nvp

@@ -242,23 +242,19 @@ nvp_status kernel_spectrum(nvp_ctx *ctx, nvp_plan *timed, double kr, double ki, 
     const int64_t H[3] = {M[0] / 2 + 1, M[1] / 2 + 1, M[2] / 2 + 1};
     double sr, si;
     self_cell(kr, ki, g->h, &sr, &si);
-    {
-        Timer t(timed, NVP_T_KTAB);
-        NVP_HIP(ctx, nvp::launch_ktab(static_cast<double2 *>(scratch), H, g->n, g->h, kr, ki, sr, si, ctx->stream));
-    }
-    Timer t(timed, NVP_T_KFFT);
     const void *tw;
     nvp_status st;
-    // z: contiguous rows of Hz entries of an even sequence of length Mz
+    // z: tabulation fused with the FFT of the even extension of each octant row
     if ((st = twiddles(ctx, (int)M[2], true, &tw))) return st;
+    {
+        Timer t(timed, NVP_T_KTAB);
+        NVP_HIP(ctx, nvp::launch_kz((int)M[2], static_cast<double2 *>(scratch), H, g->n, g->h, kr, ki, sr, si, tw,
+                                    ctx->stream));
+    }
+    Timer t(timed, NVP_T_KFFT);
     StridedArgs a{};
-    a.in = scratch; a.in_os = H[2]; a.in_ms = 1; a.n_in = 0; a.mirror = 1;
-    a.out = scratch; a.out_os = H[2]; a.out_ms = 1; a.n_out = (int)H[2];
-    a.scale = 1.0; a.inner = H[0] * H[1]; a.outer = 1; a.sign = -1;
-    NVP_HIP(ctx, nvp::launch_contig_c128((int)M[2], a, tw, ctx->stream));
     // y
     if ((st = twiddles(ctx, (int)M[1], true, &tw))) return st;
-    a = StridedArgs{};
     a.in = scratch; a.in_os = H[1] * H[2]; a.in_ms = H[2]; a.mirror = 1;
     a.out = scratch; a.out_os = H[1] * H[2]; a.out_ms = H[2]; a.n_out = (int)H[1];
     a.scale = 1.0; a.inner = H[2]; a.outer = H[0]; a.sign = -1;
