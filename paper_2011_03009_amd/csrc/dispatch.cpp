@@ -27,12 +27,6 @@ hipError_t launch_strided_f64_c64(int L, const StridedArgs &a, const void *tw, h
 #undef X
 }
 
-hipError_t launch_contig_c128(int L, const StridedArgs &a, const void *tw, hipStream_t s) {
-#define X(n) case n: return contig_impl<double, n>(a, tw, s);
-    NVP_DISPATCH()
-#undef X
-}
-
 hipError_t launch_xsrc_c64(int L, const SourceArgs &a, const void *tw, hipStream_t s) {
 #define X(n) case n: return xsrc_impl<float, n>(a, tw, s);
     NVP_DISPATCH()

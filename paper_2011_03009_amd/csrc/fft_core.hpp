@@ -196,18 +196,35 @@ __host__ __device__ constexpr int plan_threads(int L) { return plan_for(L).E ? L
 
 // ---------------------------------------------------------------- engine
 
+// Orders LDS traffic between the lanes of one wavefront: a wave's LDS
+// operations complete in issue order, so it only has to stop the compiler
+// from moving accesses across this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // REV = true runs the stages in reverse radix order.  Its first stage then has
 // the radix of the forward plan's last stage, so a forward transform's
 // outputs, as left in registers by compute_keep(), are exactly the inputs the
 // reversed transform's first stage expects in the same thread and slot.
-template <typename R, int L, bool REV = false> struct Fft {
+// WAVE = true: each column's P <= 64 threads lie in one wavefront (and no
+// other wave touches its LDS slot), so stages synchronise per wave instead of
+// per workgroup.
+template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
     static constexpr PlanDesc D = plan_for(L);
     static constexpr int S = D.S;
     static constexpr int E = D.E;
     static constexpr int P = L / E;  // threads per column
     static_assert(S > 0, "unsupported FFT length");
 
+    static_assert(!WAVE || P <= 64, "a wave-local column needs at most 64 threads");
     static constexpr int rad(int s) { return REV ? D.r[S - 1 - s] : D.r[s]; }
+    static __device__ __forceinline__ void sync() {
+        if constexpr (WAVE) wave_sync();
+        else __syncthreads();
+    }
     static constexpr int ns(int s) {
         int n = 1;
         for (int i = 0; i < s; ++i) n *= rad(i);
@@ -260,7 +277,7 @@ template <typename R, int L, bool REV = false> struct Fft {
     static __device__ __forceinline__ void run(int t, Tw tw, R sgn, Ld ld, St st, Lds lds) {
         cx<R> v[E];
         load0(v, t, ld);
-        if constexpr (LDS_IN) __syncthreads();
+        if constexpr (LDS_IN) sync();
         compute(v, t, tw, sgn, st, lds);
     }
 
@@ -285,7 +302,7 @@ template <typename R, int L, bool REV = false> struct Fft {
 #pragma unroll
                 for (int p = 0; p < r; ++p) lds(base + p * Ns) = v[i * r + p];
             }
-            __syncthreads();
+            sync();
             constexpr int r1 = rad(s + 1);
             constexpr int Ns1 = Ns * r;
             constexpr int tstep = L / (Ns1 * r1);
@@ -301,7 +318,7 @@ template <typename R, int L, bool REV = false> struct Fft {
                     v[i * r1 + q] = cmul<R>(lds(b + q * (L / r1)), w);
                 }
             }
-            __syncthreads();
+            sync();
             bflies<r1>(v, sgn);
             next<s + 1, STORE>(v, t, tw, sgn, st, lds);
         }

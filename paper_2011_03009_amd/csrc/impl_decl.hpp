@@ -8,7 +8,6 @@
 namespace nvp {
 
 template <typename R, typename Rout, int L> hipError_t strided_impl(const StridedArgs &, const void *, hipStream_t);
-template <typename R, int L> hipError_t contig_impl(const StridedArgs &, const void *, hipStream_t);
 template <typename R, int L> hipError_t xsrc_impl(const SourceArgs &, const void *, hipStream_t);
 template <typename R, int L>
 hipError_t zconv_impl(void *, const void *, int64_t, int64_t, int, const void *, hipStream_t);

@@ -10,7 +10,6 @@ namespace nvp {
 template hipError_t strided_impl<float, float, NVP_L>(const StridedArgs &, const void *, hipStream_t);
 template hipError_t strided_impl<double, double, NVP_L>(const StridedArgs &, const void *, hipStream_t);
 template hipError_t strided_impl<double, float, NVP_L>(const StridedArgs &, const void *, hipStream_t);
-template hipError_t contig_impl<double, NVP_L>(const StridedArgs &, const void *, hipStream_t);
 template hipError_t xsrc_impl<float, NVP_L>(const SourceArgs &, const void *, hipStream_t);
 template hipError_t xsrc_impl<double, NVP_L>(const SourceArgs &, const void *, hipStream_t);
 template hipError_t zconv_impl<float, NVP_L>(void *, const void *, int64_t, int64_t, int, const void *, hipStream_t);

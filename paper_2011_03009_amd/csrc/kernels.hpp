@@ -309,42 +309,21 @@ k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t i
         [&](int m) -> cx<R> & { return lds[m * T + c]; });
 }
 
-// Contiguous columns (pencils of stride 1), PW pencils per workgroup; lanes
-// run along the pencil.  Column `col` starts at col * pitch.
-template <typename R, int L, int PW, class Ld, class St>
-__global__ void __launch_bounds__(PW *plan_threads(L))
-k_contig(Ld ld, St st, const cx<R> *__restrict__ tw, R sgn, int64_t n_cols) {
-    using F = Fft<R, L>;
-    cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
-    const int tid = threadIdx.x, t = tid % F::P, c = tid / F::P;
-    const int64_t col = (int64_t)blockIdx.x * PW + c;
-    const bool act = col < n_cols;
-    cx<R> *my = lds + c * slot_len(L);
-    cx<R> *twl = lds + PW * slot_len(L);
-    stage_twiddles<R, L>(twl, tw);
-    auto twf = [&](int e) { return twl[e]; };
-    F::template run<false>(
-        t, twf, sgn, [&](int m) { return act ? ld(0, col, m) : czero<R>(); },
-        [&](int m, cx<R> v) {
-            if (act) st(0, col, m, v);
-        },
-        [&](int m) -> cx<R> & { return my[padded(m)]; });
-}
-
 // The z pass of the convolution.  A quad = the up-to-four pencils
 // (kx, ky), (Mx-kx, ky), (kx, My-ky), (Mx-kx, My-ky) that share one row of the
 // kernel spectrum's octant (the embedded kernel is even on every axis, so
 // K^(k) = K^(M - k)); QW quads per workgroup.  Each pencil: Nz inputs ->
 // forward FFT of length Mz -> times K^ -> inverse FFT -> first Nz outputs
-// written back in place.  The inverse runs the radix plan in reverse order,
-// so the forward outputs feed it straight from registers, where the product
-// with K^ is taken.
+// written back in place.  A pencil's threads lie in one wavefront, so after
+// the twiddle table is staged the waves run without workgroup barriers.  The
+// inverse runs the radix plan in reverse order, so the forward outputs feed it
+// straight from registers, where the product with K^ is taken.
 template <typename R, int L, int QW>
 __global__ void __launch_bounds__(4 * QW * plan_threads(L))
 k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int64_t My, int Nz, int64_t Hy,
         int64_t n_quads, const cx<R> *__restrict__ tw) {
-    using F = Fft<R, L, false>;
-    using G = Fft<R, L, true>;
+    using F = Fft<R, L, false, true>;
+    using G = Fft<R, L, true, true>;
     constexpr int E = F::E;
     constexpr int HZ = L / 2 + 1;
     cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
@@ -359,20 +338,17 @@ k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int
     const cx<R> *krow = khat + (kx * Hy + ky) * (int64_t)HZ;
     cx<R> *my = lds + slot * slot_len(L);
     cx<R> *twl = lds + 4 * QW * slot_len(L);
-    cx<R> *kl = twl + L + (slot >> 2) * HZ;  // this quad's K^ row
     auto ref = [&](int m) -> cx<R> & { return my[padded(m)]; };
     cx<R> v[E];
     F::load0(v, t, [&](int m) { return (act && m < Nz) ? pen[m] : czero<R>(); });
     stage_twiddles<R, L>(twl, tw);
-    if (j == 0)
-        for (int k = t; k < HZ; k += F::P) kl[k] = valid ? krow[k] : czero<R>();
+    __syncthreads();
     auto twf = [&](int e) { return twl[e]; };
     F::compute_keep(v, t, twf, R(-1), ref);
-    if constexpr (F::S == 1) __syncthreads();  // K^ row staged above; longer plans synchronise inside
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int k = F::out_index(t, i);
-        v[i] = cmul<R>(v[i], kl[k <= L / 2 ? k : L - k]);
+        v[i] = valid ? cmul<R>(v[i], krow[k <= L / 2 ? k : L - k]) : czero<R>();
     }
     G::compute(v, t, twf, R(1),
                [&](int m, cx<R> x) {
@@ -391,7 +367,7 @@ template <int L, int PW>
 __global__ void __launch_bounds__(PW *plan_threads(L))
 k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, int64_t Nz, double h, double kr,
      double ki, double2 self, const double2 *__restrict__ tw) {
-    using F = Fft<double, L>;
+    using F = Fft<double, L, false, true>;
     constexpr int HZ = L / 2 + 1;
     cx<double> *lds = reinterpret_cast<cx<double> *>(nvp_smem);
     const int tid = threadIdx.x, t = tid % F::P, c = tid / F::P;
@@ -401,6 +377,7 @@ k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, 
     cx<double> *my = lds + c * slot_len(L);
     cx<double> *twl = lds + PW * slot_len(L);
     stage_twiddles<double, L>(twl, tw);
+    __syncthreads();
     auto twf = [&](int e) { return twl[e]; };
 #pragma unroll 1
     for (int k = t; k < HZ; k += F::P) {
@@ -418,7 +395,7 @@ k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, 
         }
         my[padded(k)] = v;
     }
-    __syncthreads();
+    wave_sync();
     F::template run<true>(
         t, twf, -1.0, [&](int m) { return my[padded(m <= L / 2 ? m : L - m)]; },
         [&](int m, cx<double> v) {

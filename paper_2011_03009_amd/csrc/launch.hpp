@@ -35,6 +35,7 @@ struct StridedArgs {
     double scale;
     int64_t inner, outer;
     int sign;
+    int cols;  // columns per workgroup: 0 = default, else a compiled variant (8, 16, 32)
 };
 
 // Field of the fused source build (see LdSource).
@@ -55,14 +56,13 @@ struct SourceArgs {
     int64_t out_ms;  // Ny * Nz
     int64_t inner;   // Ny * Nz
     int chunk;       // > 0: staged separable transfer with this x-chunk; 0: direct gathers
+    int cols;        // columns per workgroup: 0 = default, else a compiled variant (8, 32)
 };
 
 hipError_t launch_strided_c64(int L, const StridedArgs &a, const void *tw, hipStream_t s);
 hipError_t launch_strided_c128(int L, const StridedArgs &a, const void *tw, hipStream_t s);
 // FP64 in, complex64 out (the downcast of the kernel spectrum).
 hipError_t launch_strided_f64_c64(int L, const StridedArgs &a, const void *tw, hipStream_t s);
-// Contiguous pencils (ms = 1, pencil `col` at col * os), FP64.
-hipError_t launch_contig_c128(int L, const StridedArgs &a, const void *tw, hipStream_t s);
 
 hipError_t launch_xsrc_c64(int L, const SourceArgs &a, const void *tw, hipStream_t s);
 hipError_t launch_xsrc_c128(int L, const SourceArgs &a, const void *tw, hipStream_t s);

@@ -27,9 +27,13 @@ template <class K> inline hipError_t allow_lds(K kern, size_t bytes) {
                                (int)bytes);
 }
 
-template <typename R, typename Rout, int L>
-hipError_t strided_impl(const StridedArgs &a, const void *tw, hipStream_t s) {
-    constexpr int T = strided_cols<R>(L);
+// A column count is usable if the workgroup stays within 1024 threads and 160 KiB of LDS.
+template <typename R, int L, int T> constexpr bool cols_ok() {
+    return T * plan_threads(L) <= 1024 && (size_t)T * L * sizeof(cx<R>) <= 163840;
+}
+
+template <typename R, typename Rout, int L, int T>
+hipError_t strided_t(const StridedArgs &a, const void *tw, hipStream_t s) {
     using Ld = LdPlain<R, L>;
     using St = StPlain<R, Rout>;
     Ld ld{static_cast<const cx<R> *>(a.in), a.in_os, a.in_ms, a.n_in, a.mirror};
@@ -56,37 +60,25 @@ hipError_t strided_impl(const StridedArgs &a, const void *tw, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename R, int L> hipError_t contig_impl(const StridedArgs &a, const void *tw, hipStream_t s) {
-    constexpr int PW = contig_pencils<R>(L);
-    using Ld = LdPlain<R, L>;
-    using St = StPlain<R, R>;
-    // pencil `col` starts at col * os: map (o = 0, col, m) -> col * os + m
-    Ld ld{static_cast<const cx<R> *>(a.in), 0, 1, a.n_in, a.mirror};
-    St st{static_cast<cx<R> *>(a.out), 0, 1, a.n_out, (R)a.scale};
-    struct LdP {
-        Ld b;
-        int64_t pitch;
-        __device__ cx<R> operator()(int64_t, int64_t col, int m) const { return b(0, col * pitch, m); }
-    };
-    struct StP {
-        St b;
-        int64_t pitch;
-        __device__ void operator()(int64_t, int64_t col, int m, cx<R> v) const { b(0, col * pitch, m, v); }
-    };
-    LdP lp{ld, a.in_os};
-    StP sp{st, a.out_os};
-    auto kern = k_contig<R, L, PW, LdP, StP>;
-    const size_t lds = ((size_t)PW * slot_len(L) + L) * sizeof(cx<R>);
-    static const hipError_t attr = allow_lds(kern, lds);
-    if (attr != hipSuccess) return attr;
-    dim3 grid((unsigned)((a.inner + PW - 1) / PW));
-    hipLaunchKernelGGL(kern, grid, dim3(PW * plan_threads(L)), lds, s, lp, sp, static_cast<const cx<R> *>(tw),
-                       (R)a.sign, a.inner);
-    return hipGetLastError();
+// Column-count variants (complex64 passes): a.cols = 8, 16 or 32, else the default.
+template <typename R, typename Rout, int L>
+hipError_t strided_impl(const StridedArgs &a, const void *tw, hipStream_t s) {
+    constexpr int T0 = strided_cols<R>(L);
+    if constexpr (sizeof(R) == 4) {
+        if (a.cols == 8 && T0 != 8) {
+            if constexpr (cols_ok<R, L, 8>()) return strided_t<R, Rout, L, 8>(a, tw, s);
+        }
+        if (a.cols == 16 && T0 != 16) {
+            if constexpr (cols_ok<R, L, 16>()) return strided_t<R, Rout, L, 16>(a, tw, s);
+        }
+        if (a.cols == 32 && T0 != 32) {
+            if constexpr (cols_ok<R, L, 32>()) return strided_t<R, Rout, L, 32>(a, tw, s);
+        }
+    }
+    return strided_t<R, Rout, L, T0>(a, tw, s);
 }
 
-template <typename R, int L, int K> hipError_t xsrc_impl_k(const SourceArgs &a, const void *tw, hipStream_t s) {
-    constexpr int T = strided_cols<R>(L);
+template <typename R, int L, int K, int T> hipError_t xsrc_impl_k(const SourceArgs &a, const void *tw, hipStream_t s) {
     using Ld = LdSource<R, K>;
     using St = StPlain<R, R>;
     Ld ld;
@@ -123,16 +115,29 @@ template <typename R, int L, int K> hipError_t xsrc_impl_k(const SourceArgs &a, 
     return hipGetLastError();
 }
 
-template <typename R, int L> hipError_t xsrc_impl(const SourceArgs &a, const void *tw, hipStream_t s) {
-    if (a.order == 1) return xsrc_impl_k<R, L, 2>(a, tw, s);
-    if (a.order == 3) return xsrc_impl_k<R, L, 4>(a, tw, s);
+template <typename R, int L, int T> hipError_t xsrc_impl_t(const SourceArgs &a, const void *tw, hipStream_t s) {
+    if (a.order == 1) return xsrc_impl_k<R, L, 2, T>(a, tw, s);
+    if (a.order == 3) return xsrc_impl_k<R, L, 4, T>(a, tw, s);
     return hipErrorInvalidValue;
+}
+
+template <typename R, int L> hipError_t xsrc_impl(const SourceArgs &a, const void *tw, hipStream_t s) {
+    constexpr int T0 = strided_cols<R>(L);
+    if constexpr (sizeof(R) == 4) {
+        if (a.cols == 8 && T0 != 8) {
+            if constexpr (cols_ok<R, L, 8>()) return xsrc_impl_t<R, L, 8>(a, tw, s);
+        }
+        if (a.cols == 32 && T0 != 32) {
+            if constexpr (cols_ok<R, L, 32>()) return xsrc_impl_t<R, L, 32>(a, tw, s);
+        }
+    }
+    return xsrc_impl_t<R, L, T0>(a, tw, s);
 }
 
 template <typename R, int L, int QW>
 hipError_t zconv_qw(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, hipStream_t s) {
     auto kern = k_zconv<R, L, QW>;
-    const size_t lds = ((size_t)4 * QW * slot_len(L) + L + QW * (L / 2 + 1)) * sizeof(cx<R>);
+    const size_t lds = ((size_t)4 * QW * slot_len(L) + L) * sizeof(cx<R>);
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
     const int64_t Hx = Mx / 2 + 1, Hy = My / 2 + 1, nq = Hx * Hy;
@@ -145,8 +150,7 @@ hipError_t zconv_qw(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz,
 template <typename R, int L>
 hipError_t zconv_impl(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, hipStream_t s) {
     // quads per workgroup: up to 256 threads and 80 KiB of LDS
-    constexpr int QW = (4 * plan_threads(L) <= 128 && (8 * slot_len(L) + L + L + 2) * (int)sizeof(cx<R>) <= 81920)
-                           ? 2 : 1;
+    constexpr int QW = (4 * plan_threads(L) <= 128 && (8 * slot_len(L) + L) * (int)sizeof(cx<R>) <= 81920) ? 2 : 1;
     if (zconv_quads_override() == 1) return zconv_qw<R, L, 1>(buf, khat, Mx, My, Nz, tw, s);
     return zconv_qw<R, L, QW>(buf, khat, Mx, My, Nz, tw, s);
 }

@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -47,6 +48,9 @@ struct nvp_ctx {
     std::vector<Twiddle> tw;
     VpCache vp;
     size_t max_lds = 0;
+    // columns per workgroup of the complex64 x and y passes and the source build
+    // (0 = compiled default); read from NVP_COLS_X / NVP_COLS_Y / NVP_COLS_SRC.
+    int cols_x = 0, cols_y = 0, cols_src = 0;
 };
 
 namespace {
@@ -295,6 +299,7 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
         Timer t(timed, NVP_T_XFWD);
         if (src) {
             SourceArgs s = *src;
+            s.cols = ctx->cols_src;
             s.out = A;
             s.out_ms = Ny * Nz;
             s.inner = Ny * Nz;
@@ -303,7 +308,7 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
             StridedArgs a{};
             a.in = f; a.in_os = 0; a.in_ms = Ny * Nz; a.n_in = (int)Nx;
             a.out = A; a.out_os = 0; a.out_ms = Ny * Nz; a.n_out = (int)Mx;
-            a.scale = 1.0; a.inner = Ny * Nz; a.outer = 1; a.sign = -1;
+            a.scale = 1.0; a.inner = Ny * Nz; a.outer = 1; a.sign = -1; a.cols = ctx->cols_x;
             NVP_HIP(ctx, strided((int)Mx, a, twx, ctx->stream));
         }
     }
@@ -312,7 +317,7 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
         StridedArgs a{};
         a.in = A; a.in_os = Ny * Nz; a.in_ms = Nz; a.n_in = (int)Ny;
         a.out = B; a.out_os = My * Nz; a.out_ms = Nz; a.n_out = (int)My;
-        a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = -1;
+        a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = -1; a.cols = ctx->cols_y;
         NVP_HIP(ctx, strided((int)My, a, twy, ctx->stream));
     }
     {
@@ -325,7 +330,7 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
         StridedArgs a{};
         a.in = B; a.in_os = My * Nz; a.in_ms = Nz; a.n_in = (int)My;
         a.out = A; a.out_os = Ny * Nz; a.out_ms = Nz; a.n_out = (int)Ny;
-        a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = 1;
+        a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = 1; a.cols = ctx->cols_y;
         NVP_HIP(ctx, strided((int)My, a, twy, ctx->stream));
     }
     {
@@ -333,7 +338,7 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
         StridedArgs a{};
         a.in = A; a.in_os = 0; a.in_ms = Ny * Nz; a.n_in = (int)Mx;
         a.out = u; a.out_os = 0; a.out_ms = Ny * Nz; a.n_out = (int)Nx;
-        a.scale = scale; a.inner = Ny * Nz; a.outer = 1; a.sign = 1;
+        a.scale = scale; a.inner = Ny * Nz; a.outer = 1; a.sign = 1; a.cols = ctx->cols_x;
         NVP_HIP(ctx, strided((int)Mx, a, twx, ctx->stream));
     }
     return NVP_OK;
@@ -432,6 +437,13 @@ nvp_status nvp_ctx_create(int device, void *hip_stream, nvp_ctx **out) {
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->max_lds = prop.sharedMemPerBlock;
+    auto env = [](const char *n) {
+        const char *v = getenv(n);
+        return v ? atoi(v) : 0;
+    };
+    c->cols_x = env("NVP_COLS_X");
+    c->cols_y = env("NVP_COLS_Y");
+    c->cols_src = env("NVP_COLS_SRC");
     *out = c;
     return NVP_OK;
 }
