@@ -11,8 +11,11 @@
 // the stages in between exchange data through LDS.
 //
 // Forward transforms use sign -1 (X_k = sum x_m e^{-2 pi i k m / L}), inverse
-// +1, unnormalised.  Twiddles come from a table W^e, e in [0, L), computed on
-// the host in extended precision and rounded once to the working precision.
+// +1, unnormalised; the sign is a compile-time parameter, so rotations by +-i
+// and conjugated twiddles cost no instructions.  Twiddles come from per-stage
+// tables [j][q-1] = exp(-2 pi i j q / (Ns r)) computed on the host in extended
+// precision and rounded once; every access is a per-thread base plus a
+// constant offset.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,16 +36,27 @@ template <typename R> __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
     return mk<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 template <typename R> __device__ __forceinline__ cx<R> cscale(cx<R> a, R s) { return mk<R>(a.x * s, a.y * s); }
-// s * i * a for s = +-1
-template <typename R> __device__ __forceinline__ cx<R> crot(cx<R> a, R s) { return mk<R>(-s * a.y, s * a.x); }
+// a * conj(b)
+template <typename R> __device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b) {
+    return mk<R>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// SG * i * a, SG = +-1 at compile time
+template <int SG, typename R> __device__ __forceinline__ cx<R> crot(cx<R> a) {
+    if constexpr (SG > 0) return mk<R>(-a.y, a.x);
+    else return mk<R>(a.y, -a.x);
+}
+// a * (c + SG i s) for constants c, s
+template <int SG, typename R> __device__ __forceinline__ cx<R> cmulk(cx<R> a, R c, R s) {
+    return SG > 0 ? mk<R>(a.x * c - a.y * s, a.x * s + a.y * c) : mk<R>(a.x * c + a.y * s, a.y * c - a.x * s);
+}
 
 // ---------------------------------------------------------------- small DFTs
-// y_p = sum_q v_q exp(s 2 pi i p q / N), in place on v[0..N-1].
+// y_p = sum_q v_q exp(SG 2 pi i p q / N), in place on v[0..N-1].
 
 template <int N, typename R> struct Dft;
 
 template <typename R> struct Dft<2, R> {
-    static __device__ __forceinline__ void run(cx<R> *v, R) {
+    template <int SG> static __device__ __forceinline__ void run(cx<R> *v) {
         cx<R> a = v[0], b = v[1];
         v[0] = cadd<R>(a, b);
         v[1] = csub<R>(a, b);
@@ -50,9 +64,9 @@ template <typename R> struct Dft<2, R> {
 };
 
 template <typename R> struct Dft<4, R> {
-    static __device__ __forceinline__ void run(cx<R> *v, R s) {
+    template <int SG> static __device__ __forceinline__ void run(cx<R> *v) {
         cx<R> a = cadd<R>(v[0], v[2]), b = csub<R>(v[0], v[2]);
-        cx<R> c = cadd<R>(v[1], v[3]), d = crot<R>(csub<R>(v[1], v[3]), s);
+        cx<R> c = cadd<R>(v[1], v[3]), d = crot<SG, R>(csub<R>(v[1], v[3]));
         v[0] = cadd<R>(a, c);
         v[2] = csub<R>(a, c);
         v[1] = cadd<R>(b, d);
@@ -62,15 +76,18 @@ template <typename R> struct Dft<4, R> {
 
 // Even/odd split: y_p = E_p + W^p O_p, y_{p+N/2} = E_p - W^p O_p.
 template <typename R> struct Dft<8, R> {
-    static __device__ __forceinline__ void run(cx<R> *v, R s) {
+    template <int SG> static __device__ __forceinline__ void run(cx<R> *v) {
         cx<R> e[4] = {v[0], v[2], v[4], v[6]};
         cx<R> o[4] = {v[1], v[3], v[5], v[7]};
-        Dft<4, R>::run(e, s);
-        Dft<4, R>::run(o, s);
+        Dft<4, R>::template run<SG>(e);
+        Dft<4, R>::template run<SG>(o);
         const R c = R(0.707106781186547524400844362105);
-        o[1] = cmul<R>(o[1], mk<R>(c, s * c));
-        o[2] = crot<R>(o[2], s);
-        o[3] = cmul<R>(o[3], mk<R>(-c, s * c));
+        // W^1 = c (1 + SG i), W^3 = c (-1 + SG i)
+        o[1] = SG > 0 ? mk<R>(c * (o[1].x - o[1].y), c * (o[1].x + o[1].y))
+                      : mk<R>(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
+        o[2] = crot<SG, R>(o[2]);
+        o[3] = SG > 0 ? mk<R>(-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y))
+                      : mk<R>(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             v[p] = cadd<R>(e[p], o[p]);
@@ -80,25 +97,27 @@ template <typename R> struct Dft<8, R> {
 };
 
 template <typename R> struct Dft<16, R> {
-    static __device__ __forceinline__ void run(cx<R> *v, R s) {
+    template <int SG> static __device__ __forceinline__ void run(cx<R> *v) {
         cx<R> e[8], o[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             e[i] = v[2 * i];
             o[i] = v[2 * i + 1];
         }
-        Dft<8, R>::run(e, s);
-        Dft<8, R>::run(o, s);
+        Dft<8, R>::template run<SG>(e);
+        Dft<8, R>::template run<SG>(o);
         const R c1 = R(0.923879532511286756128183189397);  // cos(pi/8)
         const R s1 = R(0.382683432365089771728459984030);  // sin(pi/8)
         const R c2 = R(0.707106781186547524400844362105);
-        o[1] = cmul<R>(o[1], mk<R>(c1, s * s1));
-        o[2] = cmul<R>(o[2], mk<R>(c2, s * c2));
-        o[3] = cmul<R>(o[3], mk<R>(s1, s * c1));
-        o[4] = crot<R>(o[4], s);
-        o[5] = cmul<R>(o[5], mk<R>(-s1, s * c1));
-        o[6] = cmul<R>(o[6], mk<R>(-c2, s * c2));
-        o[7] = cmul<R>(o[7], mk<R>(-c1, s * s1));
+        o[1] = cmulk<SG, R>(o[1], c1, s1);
+        o[2] = SG > 0 ? mk<R>(c2 * (o[2].x - o[2].y), c2 * (o[2].x + o[2].y))
+                      : mk<R>(c2 * (o[2].x + o[2].y), c2 * (o[2].y - o[2].x));
+        o[3] = cmulk<SG, R>(o[3], s1, c1);
+        o[4] = crot<SG, R>(o[4]);
+        o[5] = cmulk<SG, R>(o[5], -s1, c1);
+        o[6] = SG > 0 ? mk<R>(-c2 * (o[6].x + o[6].y), c2 * (o[6].x - o[6].y))
+                      : mk<R>(c2 * (o[6].y - o[6].x), -c2 * (o[6].x + o[6].y));
+        o[7] = cmulk<SG, R>(o[7], -c1, s1);
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
             v[p] = cadd<R>(e[p], o[p]);
@@ -121,9 +140,9 @@ __host__ __device__ constexpr double odd_sin(int N, int k) {
             : k == 2 ? 0.974927912181823607018131682994 : 0.433883739117558120475768332849);
 }
 
-// Odd N: pair v_q with v_{N-q}:  y_p = v_0 + sum_q a_q cos(2 pi p q / N) +- s i sum_q b_q sin(...).
+// Odd N: pair v_q with v_{N-q}:  y_p = v_0 + sum_q a_q cos(2 pi p q / N) +- SG i sum_q b_q sin(...).
 template <int N, typename R> struct DftOdd {
-    static __device__ __forceinline__ void run(cx<R> *v, R s) {
+    template <int SG> static __device__ __forceinline__ void run(cx<R> *v) {
         constexpr int H = (N - 1) / 2;
         cx<R> a[H], b[H];
         cx<R> y0 = v[0];
@@ -145,7 +164,7 @@ template <int N, typename R> struct DftOdd {
                 A = cadd<R>(A, cscale<R>(a[q - 1], cv));
                 B = cadd<R>(B, cscale<R>(b[q - 1], sv));
             }
-            cx<R> iB = crot<R>(B, s);
+            cx<R> iB = crot<SG, R>(B);
             out[p] = cadd<R>(A, iB);
             out[N - p] = csub<R>(A, iB);
         }
@@ -183,7 +202,7 @@ __host__ __device__ constexpr PlanDesc plan_for(int L) {
     case 384: return PlanDesc{4, {3, 8, 4, 4, 0, 0}, 24};
     case 448: return PlanDesc{4, {7, 4, 4, 4, 0, 0}, 28};
     case 512: return PlanDesc{3, {8, 8, 8, 0, 0, 0}, 16};
-    case 640: return PlanDesc{4, {5, 8, 4, 4, 0, 0}, 40};
+    case 640: return PlanDesc{4, {8, 4, 4, 5, 0, 0}, 40};  // the order 5,8,4,4 computed wrong FP64 results
     case 768: return PlanDesc{4, {3, 4, 8, 8, 0, 0}, 24};
     case 896: return PlanDesc{5, {7, 4, 4, 4, 2, 0}, 28};
     case 1024: return PlanDesc{3, {16, 8, 8, 0, 0, 0}, 32};
@@ -194,14 +213,38 @@ __host__ __device__ constexpr PlanDesc plan_for(int L) {
 
 __host__ __device__ constexpr int plan_threads(int L) { return plan_for(L).E ? L / plan_for(L).E : 0; }
 
+// Radix of stage s and product of the radices before it, for the plan run
+// forward (rev = false) or in reverse radix order (rev = true).
+__host__ __device__ constexpr int plan_rad(int L, bool rev, int s) {
+    return rev ? plan_for(L).r[plan_for(L).S - 1 - s] : plan_for(L).r[s];
+}
+__host__ __device__ constexpr int plan_ns(int L, bool rev, int s) {
+    int n = 1;
+    for (int i = 0; i < s; ++i) n *= plan_rad(L, rev, i);
+    return n;
+}
+// Offset of stage s's twiddles [j][q-1] (j < Ns, q = 1..r-1) in the table of
+// one direction; stages 1..S-1 have twiddles.
+__host__ __device__ constexpr int plan_tw_off(int L, bool rev, int s) {
+    int o = 0;
+    for (int i = 1; i < s; ++i) o += plan_ns(L, rev, i) * (plan_rad(L, rev, i) - 1);
+    return o;
+}
+__host__ __device__ constexpr int plan_tw_len(int L, bool rev) { return plan_tw_off(L, rev, plan_for(L).S); }
+// The table of length L holds the forward-order stages, then the reversed-order ones.
+__host__ __device__ constexpr int twiddle_table_len(int L) { return plan_tw_len(L, false) + plan_tw_len(L, true); }
+
 // ---------------------------------------------------------------- engine
 
-// Orders LDS traffic between the lanes of one wavefront: a wave's LDS
-// operations complete in issue order, so it only has to stop the compiler
-// from moving accesses across this point.
+// Orders LDS traffic between the lanes of one wavefront.  A thread's own
+// accesses on either side may provably not alias (so the compiler would be
+// free to swap them), but other lanes' do: the memory clobber keeps every LDS
+// access on its side, and the wait makes the writes complete before any lane
+// reads.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
@@ -211,24 +254,22 @@ __device__ __forceinline__ void wave_sync() {
 // reversed transform's first stage expects in the same thread and slot.
 // WAVE = true: each column's P <= 64 threads lie in one wavefront (and no
 // other wave touches its LDS slot), so stages synchronise per wave instead of
-// per workgroup.
+// per workgroup.  Tw: tw(e) -> entry e of this direction's twiddle table.
 template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
     static constexpr PlanDesc D = plan_for(L);
     static constexpr int S = D.S;
     static constexpr int E = D.E;
     static constexpr int P = L / E;  // threads per column
     static_assert(S > 0, "unsupported FFT length");
-
     static_assert(!WAVE || P <= 64, "a wave-local column needs at most 64 threads");
-    static constexpr int rad(int s) { return REV ? D.r[S - 1 - s] : D.r[s]; }
+    static constexpr int TW_BASE = REV ? plan_tw_len(L, false) : 0;  // offset in the two-direction table
+
+    static constexpr int rad(int s) { return plan_rad(L, REV, s); }
+    static constexpr int ns(int s) { return plan_ns(L, REV, s); }
+
     static __device__ __forceinline__ void sync() {
         if constexpr (WAVE) wave_sync();
         else __syncthreads();
-    }
-    static constexpr int ns(int s) {
-        int n = 1;
-        for (int i = 0; i < s; ++i) n *= rad(i);
-        return n;
     }
 
     // Output index held in register `slot` after the last stage.
@@ -237,9 +278,28 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
         return t + (slot / r) * P + (slot % r) * (L / r);
     }
 
-    template <int r> static __device__ __forceinline__ void bflies(cx<R> *v, R sgn) {
+    template <int r, int SG> static __device__ __forceinline__ void bflies(cx<R> *v) {
 #pragma unroll
-        for (int i = 0; i < E / r; ++i) Dft<r, R>::run(v + i * r, sgn);
+        for (int i = 0; i < E / r; ++i) Dft<r, R>::template run<SG>(v + i * r);
+    }
+
+    // Stockham destination of butterfly b = t + i P at stage s, written so
+    // that it is a per-thread base plus a compile-time offset when possible.
+    template <int s> static __device__ __forceinline__ int wr_index(int t, int i) {
+        constexpr int Ns = ns(s), r = rad(s);
+        if constexpr (P % Ns == 0) return (t / Ns) * Ns * r + (t % Ns) + i * P * r;
+        else if constexpr (P * (E / r) <= Ns) return t + i * P;
+        else {
+            const int b = t + i * P;
+            return (b / Ns) * Ns * r + b % Ns;
+        }
+    }
+    // j = b mod Ns for b = t + i P, likewise.
+    template <int s> static __device__ __forceinline__ int tw_j(int t, int i) {
+        constexpr int Ns = ns(s), r = rad(s);
+        if constexpr (P % Ns == 0) return t % Ns;
+        else if constexpr (P * (E / r) <= Ns) return t + i * P;
+        else return (t + i * P) % Ns;
     }
 
     // First-stage inputs: v[i r0 + q] = x[t + i P + q L / r0].
@@ -254,17 +314,17 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
     }
 
     // All stages on v (loaded by load0); st(m, x) receives the outputs.
-    template <class Tw, class St, class Lds>
-    static __device__ __forceinline__ void compute(cx<R> *v, int t, Tw tw, R sgn, St st, Lds lds) {
-        bflies<rad(0)>(v, sgn);
-        next<0, true>(v, t, tw, sgn, st, lds);
+    template <int SG, class Tw, class St, class Lds>
+    static __device__ __forceinline__ void compute(cx<R> *v, int t, Tw tw, St st, Lds lds) {
+        bflies<rad(0), SG>(v);
+        next<0, SG, true>(v, t, tw, st, lds);
     }
 
     // All stages on v; the outputs stay in v (see out_index).
-    template <class Tw, class Lds>
-    static __device__ __forceinline__ void compute_keep(cx<R> *v, int t, Tw tw, R sgn, Lds lds) {
-        bflies<rad(0)>(v, sgn);
-        next<0, false>(v, t, tw, sgn, [](int, cx<R>) {}, lds);
+    template <int SG, class Tw, class Lds>
+    static __device__ __forceinline__ void compute_keep(cx<R> *v, int t, Tw tw, Lds lds) {
+        bflies<rad(0), SG>(v);
+        next<0, SG, false>(v, t, tw, [](int, cx<R>) {}, lds);
     }
 
     // Transform this thread's share of one column.
@@ -272,17 +332,16 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
     //   st(m, x)  <- output element m (last stage, natural order)
     //   lds(m)    -> reference to element m of this column's LDS slot
     // LDS_IN: ld reads the same LDS slot, so wait before overwriting it.
-    // tw(e) -> W^e, W = exp(-2 pi i / L) (a global or LDS table).
-    template <bool LDS_IN, class Tw, class Ld, class St, class Lds>
-    static __device__ __forceinline__ void run(int t, Tw tw, R sgn, Ld ld, St st, Lds lds) {
+    template <int SG, bool LDS_IN, class Tw, class Ld, class St, class Lds>
+    static __device__ __forceinline__ void run(int t, Tw tw, Ld ld, St st, Lds lds) {
         cx<R> v[E];
         load0(v, t, ld);
         if constexpr (LDS_IN) sync();
-        compute(v, t, tw, sgn, st, lds);
+        compute<SG>(v, t, tw, st, lds);
     }
 
-    template <int s, bool STORE, class Tw, class St, class Lds>
-    static __device__ __forceinline__ void next(cx<R> *v, int t, Tw tw, R sgn, St st, Lds lds) {
+    template <int s, int SG, bool STORE, class Tw, class St, class Lds>
+    static __device__ __forceinline__ void next(cx<R> *v, int t, Tw tw, St st, Lds lds) {
         constexpr int r = rad(s);
         constexpr int Ns = ns(s);
         if constexpr (s == S - 1) {
@@ -297,30 +356,27 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
         } else {
 #pragma unroll
             for (int i = 0; i < E / r; ++i) {
-                const int b = t + i * P;
-                const int base = (b / Ns) * Ns * r + (b % Ns);
+                const int w = wr_index<s>(t, i);
 #pragma unroll
-                for (int p = 0; p < r; ++p) lds(base + p * Ns) = v[i * r + p];
+                for (int p = 0; p < r; ++p) lds(w + p * Ns) = v[i * r + p];
             }
             sync();
             constexpr int r1 = rad(s + 1);
-            constexpr int Ns1 = Ns * r;
-            constexpr int tstep = L / (Ns1 * r1);
+            constexpr int off = TW_BASE + plan_tw_off(L, REV, s + 1);
 #pragma unroll
             for (int i = 0; i < E / r1; ++i) {
                 const int b = t + i * P;
-                const int j = b % Ns1;
+                const int jb = off + tw_j<s + 1>(t, i) * (r1 - 1) - 1;
                 v[i * r1] = lds(b);
 #pragma unroll
                 for (int q = 1; q < r1; ++q) {
-                    cx<R> w = tw(j * q * tstep);
-                    if (sgn > R(0)) w.y = -w.y;
-                    v[i * r1 + q] = cmul<R>(lds(b + q * (L / r1)), w);
+                    const cx<R> x = lds(b + q * (L / r1)), w = tw(jb + q);
+                    v[i * r1 + q] = SG < 0 ? cmul<R>(x, w) : cmulc<R>(x, w);
                 }
             }
             sync();
-            bflies<r1>(v, sgn);
-            next<s + 1, STORE>(v, t, tw, sgn, st, lds);
+            bflies<r1, SG>(v);
+            next<s + 1, SG, STORE>(v, t, tw, st, lds);
         }
     }
 };

@@ -17,7 +17,7 @@
 
 namespace nvp {
 
-// ---------------------------------------------------------------- loaders
+// ---------------------------------------------------------------- loaders and storers
 
 // Element m of column (o, col) at p[o*os + m*ms + col].  Pruned: zero for
 // m >= n.  Mirrored: the column holds entries 0..L/2 of an even sequence of
@@ -43,14 +43,14 @@ template <> __device__ __forceinline__ float2 cvt<double, float>(double2 v) {
     return make_float2((float)v.x, (float)v.y);
 }
 
-// Stores element m < n of column (o, col) times a real scale.
-template <typename R, typename Rout> struct StPlain {
+// Stores element m < n of column (o, col), times a real scale when SC.
+template <typename R, typename Rout, bool SC> struct StPlain {
     cx<Rout> *__restrict__ p;
     int64_t os, ms;
     int n;
     R scale;
     __device__ __forceinline__ void operator()(int64_t o, int64_t col, int m, cx<R> v) const {
-        if (m < n) p[o * os + (int64_t)m * ms + col] = cvt<R, Rout>(cscale<R>(v, scale));
+        if (m < n) p[o * os + (int64_t)m * ms + col] = cvt<R, Rout>(SC ? cscale<R>(v, scale) : v);
     }
 };
 
@@ -69,8 +69,8 @@ template <typename R> struct FieldDev {
 
 template <typename R, int K> struct LdSource {
     FieldDev<R> f[NVP_MAX_FIELDS];
-    int nf;     // n - 1 fields
-    int Nx, Nz; // target grid (Ny implied by the column count)
+    int nf;      // n - 1 fields
+    int Nx, Nz;  // target grid (Ny implied by the column count)
 
     __device__ __forceinline__ cx<R> interp(const FieldDev<R> &g, int ix, int iy, int iz) const {
         if (g.identity) return g.p[ix * g.s0 + (int64_t)iy * g.s1 + iz];
@@ -82,13 +82,14 @@ template <typename R, int K> struct LdSource {
             wy[a] = g.w[1][iy * K + a];
             wz[a] = g.w[2][iz * K + a];
         }
+        const cx<R> *base = g.p + (int64_t)bx * g.s0 + (int64_t)by * g.s1 + bz;
         cx<R> acc = czero<R>();
 #pragma unroll
         for (int a = 0; a < K; ++a) {
             cx<R> ay = czero<R>();
 #pragma unroll
             for (int c = 0; c < K; ++c) {
-                const cx<R> *row = g.p + (int64_t)(bx + a) * g.s0 + (int64_t)(by + c) * g.s1 + bz;
+                const cx<R> *row = base + a * g.s0 + c * g.s1;
                 cx<R> az = czero<R>();
 #pragma unroll
                 for (int d = 0; d < K; ++d) az = cadd<R>(az, cscale<R>(row[d], wz[d]));
@@ -99,11 +100,8 @@ template <typename R, int K> struct LdSource {
         return acc;
     }
 
-    // f_n at target voxel (ix, iy, iz)
-    __device__ __forceinline__ cx<R> value(int ix, int iy, int iz) const {
-        cx<R> v[NVP_MAX_FIELDS];
-#pragma unroll
-        for (int i = 0; i < NVP_MAX_FIELDS; ++i) v[i] = i < nf ? interp(f[i], ix, iy, iz) : czero<R>();
+    // sum_{a+b = nf-1} v_a v_b over the transferred fields
+    __device__ __forceinline__ cx<R> products(const cx<R> *v) const {
         cx<R> s = czero<R>();
 #pragma unroll
         for (int a = 0; a < NVP_MAX_FIELDS; ++a)
@@ -112,40 +110,51 @@ template <typename R, int K> struct LdSource {
                 if (a + b == nf - 1) s = cadd<R>(s, cmul<R>(v[a], v[b]));
         return s;
     }
+
+    // f_n at target voxel (ix, iy, iz)
+    __device__ __forceinline__ cx<R> value(int ix, int iy, int iz) const {
+        cx<R> v[NVP_MAX_FIELDS];
+#pragma unroll
+        for (int i = 0; i < NVP_MAX_FIELDS; ++i) v[i] = i < nf ? interp(f[i], ix, iy, iz) : czero<R>();
+        return products(v);
+    }
 };
 
-// ---------------------------------------------------------------- kernels
+// ---------------------------------------------------------------- LDS helpers
 
 extern __shared__ __align__(16) unsigned char nvp_smem[];
 
 // LDS slot of a contiguous pencil: one pad element per 16 spreads the strided
 // writes of the early Stockham stages over the banks.
 __host__ __device__ constexpr int padded(int m) { return m + (m >> 4); }
-__host__ __device__ constexpr int slot_len(int L) { return padded(L) + 1; }
+template <typename R> __host__ __device__ constexpr int slot_len(int L) { return padded(L) + 1; }
 
-// Twiddle table W^e, e < L: copied into LDS behind the workgroup's data when
-// it fits (every later stage reads it with low latency), else read from the
-// global table through the caches.
-template <typename R, int L> __device__ __forceinline__ void stage_twiddles(cx<R> *dst, const cx<R> *src) {
-    for (int e = threadIdx.x; e < L; e += blockDim.x) dst[e] = src[e];
+// Copies n entries of a twiddle table into LDS (all threads of the workgroup).
+template <typename R> __device__ __forceinline__ void stage_table(cx<R> *dst, const cx<R> *src, int n) {
+    for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
 }
-// Staged only when it costs no occupancy: as many workgroups fit per CU
-// (160 KiB of LDS) with the table as without it.
-template <typename R, int L> constexpr bool tw_fits(size_t data_elems) {
-    const size_t d = data_elems * sizeof(cx<R>), w = (data_elems + L) * sizeof(cx<R>);
+
+// A twiddle table is staged in LDS behind the workgroup's data only when it
+// costs no occupancy: as many workgroups fit per CU (160 KiB) with it as without.
+template <typename R> constexpr bool tw_fits(size_t data_elems, size_t tw_elems) {
+    const size_t d = data_elems * sizeof(cx<R>), w = (data_elems + tw_elems) * sizeof(cx<R>);
     return w <= 163840 && 163840 / w == 163840 / d;
 }
+
+// ---------------------------------------------------------------- kernels
 
 // Columns strided by `ms` with T consecutive columns (contiguous in memory)
 // per workgroup: lanes run over columns first, so every row access of a wave
 // reads T * sizeof(complex) contiguous bytes.  grid = (ceil(inner / T), outer).
-// MIRROR: the columns hold entries 0..L/2 of even sequences; they are read
-// once into LDS and the transform takes its first stage from there.
-template <typename R, int L, int T, bool MIRROR, class Ld, class St>
+// SG: -1 forward, +1 inverse.  MIRROR: the columns hold entries 0..L/2 of even
+// sequences; they are read once into LDS and the transform takes its first
+// stage from there.
+template <typename R, int L, int T, int SG, bool MIRROR, class Ld, class St>
 __global__ void __launch_bounds__(T *plan_threads(L))
-k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, R sgn, int64_t inner) {
+k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, int64_t inner) {
     using F = Fft<R, L>;
-    constexpr bool TWL = tw_fits<R, L>((size_t)T * L);
+    constexpr int NT = plan_tw_len(L, false);
+    constexpr bool TWL = tw_fits<R>((size_t)T * L, NT);
     cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
     cx<R> *twl = lds + T * L;
     auto twf = [&](int e) { return TWL ? twl[e] : tw[e]; };
@@ -170,40 +179,42 @@ k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, R sgn, int64_t inner) {
             const int m = t + i * F::P;
             if (m <= L / 2) lds[m * T + c] = h[i];
         }
-        if constexpr (TWL) stage_twiddles<R, L>(twl, tw);
+        if constexpr (TWL) stage_table<R>(twl, tw, NT);
         __syncthreads();
-        F::template run<true>(t, twf, sgn, [&](int m) { return lds[(m <= L / 2 ? m : L - m) * T + c]; }, store, ref);
+        F::template run<SG, true>(t, twf, [&](int m) { return lds[(m <= L / 2 ? m : L - m) * T + c]; }, store,
+                                  ref);
     } else {
         cx<R> v[F::E];
         F::load0(v, t, [&](int m) { return act ? ld(o, col, m) : czero<R>(); });
-        if constexpr (TWL) stage_twiddles<R, L>(twl, tw);
-        F::compute(v, t, twf, sgn, store, ref);
+        if constexpr (TWL) stage_table<R>(twl, tw, NT);
+        F::template compute<SG>(v, t, twf, store, ref);
     }
 }
 
-// Forward x pass with the source build fused in front: each thread first
-// writes f_n for its share of the column's Nx voxels into the column's LDS
-// slot (a rolled loop, so the interpolation code exists once), then the FFT
-// reads its first stage from there.  Column col = iy * Nz + iz.
+// Forward x pass with the source build fused in front, direct form: each
+// thread first writes f_n for its share of the column's Nx voxels into the
+// column's LDS slot (a rolled loop, so the interpolation code exists once),
+// then the FFT reads its first stage from there.  Column col = iy * Nz + iz.
 template <typename R, int L, int T, int K, class St>
 __global__ void __launch_bounds__(T *plan_threads(L))
 k_xsrc(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t inner) {
     using F = Fft<R, L>;
+    constexpr int NT = plan_tw_len(L, false);
+    constexpr bool TWL = tw_fits<R>((size_t)T * L, NT);
     cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
+    cx<R> *twl = lds + T * L;
+    if constexpr (TWL) stage_table<R>(twl, tw, NT);
+    auto twf = [&](int e) { return TWL ? twl[e] : tw[e]; };
     const int tid = threadIdx.x, c = tid % T, t = tid / T;
     const int64_t col = (int64_t)blockIdx.x * T + c;
     const bool act = col < inner;
     const int iy = act ? (int)(col / src.Nz) : 0, iz = act ? (int)(col % src.Nz) : 0;
     const int Nx = src.Nx;
-    constexpr bool TWL = tw_fits<R, L>((size_t)T * L);
-    cx<R> *twl = lds + T * L;
-    if constexpr (TWL) stage_twiddles<R, L>(twl, tw);
-    auto twf = [&](int e) { return TWL ? twl[e] : tw[e]; };
 #pragma unroll 1
     for (int m = t; m < Nx; m += F::P) lds[m * T + c] = act ? src.value(m, iy, iz) : czero<R>();
     __syncthreads();
-    F::template run<true>(
-        t, twf, R(-1), [&](int m) { return m < Nx ? lds[m * T + c] : czero<R>(); },
+    F::template run<-1, true>(
+        t, twf, [&](int m) { return m < Nx ? lds[m * T + c] : czero<R>(); },
         [&](int m, cx<R> v) {
             if (act) st(0, col, m, v);
         },
@@ -223,6 +234,8 @@ __global__ void __launch_bounds__(T *plan_threads(L))
 k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t inner, int chunk) {
     using F = Fft<R, L>;
     constexpr int P = F::P;
+    constexpr int NT = plan_tw_len(L, false);
+    constexpr bool TWL = tw_fits<R>((size_t)T * L, NT);
     cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
     const int tid = threadIdx.x, c = tid % T, t = tid / T;
     const int64_t col = (int64_t)blockIdx.x * T + c;
@@ -230,9 +243,8 @@ k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t i
     const int iy = act ? (int)(col / src.Nz) : 0, iz = act ? (int)(col % src.Nz) : 0;
     const int Nx = src.Nx;
     cx<R> *stage = lds + (int64_t)Nx * T;
-    constexpr bool TWL = tw_fits<R, L>((size_t)T * L);
     cx<R> *twl = lds + T * L;
-    if constexpr (TWL) stage_twiddles<R, L>(twl, tw);
+    if constexpr (TWL) stage_table<R>(twl, tw, NT);
     auto twf = [&](int e) { return TWL ? twl[e] : tw[e]; };
 #pragma unroll 1
     for (int ix0 = 0; ix0 < Nx; ix0 += chunk) {
@@ -247,7 +259,7 @@ k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t i
                 const FieldDev<R> &g = src.f[i];
                 const int r0 = g.b[0][ix0], r1 = g.b[0][ix1 - 1] + K;
                 lo[i] = r0;
-                const int by = g.b[1][iy], bz = g.b[2][iz];
+                const cx<R> *colbase = g.p + (int64_t)r0 * g.s0 + (int64_t)g.b[1][iy] * g.s1 + g.b[2][iz];
                 R wy[K], wz[K];
 #pragma unroll
                 for (int a = 0; a < K; ++a) {
@@ -258,12 +270,12 @@ k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t i
                 for (int r = t; r < r1 - r0; r += P) {
                     cx<R> acc = czero<R>();
                     if (act) {
-                        const cx<R> *base = g.p + (int64_t)(r0 + r) * g.s0 + (int64_t)by * g.s1 + bz;
+                        const cx<R> *rp = colbase + (int64_t)r * g.s0;
 #pragma unroll
                         for (int b = 0; b < K; ++b) {
                             cx<R> az = czero<R>();
 #pragma unroll
-                            for (int d = 0; d < K; ++d) az = cadd<R>(az, cscale<R>(base[b * g.s1 + d], wz[d]));
+                            for (int d = 0; d < K; ++d) az = cadd<R>(az, cscale<R>(rp[b * g.s1 + d], wz[d]));
                             acc = cadd<R>(acc, cscale<R>(az, wy[b]));
                         }
                     }
@@ -291,18 +303,12 @@ k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t i
                     }
                 }
             }
-            cx<R> s = czero<R>();
-#pragma unroll
-            for (int a = 0; a < NVP_MAX_FIELDS; ++a)
-#pragma unroll
-                for (int b = 0; b < NVP_MAX_FIELDS; ++b)
-                    if (a + b == src.nf - 1) s = cadd<R>(s, cmul<R>(v[a], v[b]));
-            lds[ix * T + c] = s;
+            lds[ix * T + c] = src.products(v);
         }
         __syncthreads();
     }
-    F::template run<true>(
-        t, twf, R(-1), [&](int m) { return m < Nx ? lds[m * T + c] : czero<R>(); },
+    F::template run<-1, true>(
+        t, twf, [&](int m) { return m < Nx ? lds[m * T + c] : czero<R>(); },
         [&](int m, cx<R> v) {
             if (act) st(0, col, m, v);
         },
@@ -314,10 +320,11 @@ k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t i
 // kernel spectrum's octant (the embedded kernel is even on every axis, so
 // K^(k) = K^(M - k)); QW quads per workgroup.  Each pencil: Nz inputs ->
 // forward FFT of length Mz -> times K^ -> inverse FFT -> first Nz outputs
-// written back in place.  A pencil's threads lie in one wavefront, so after
-// the twiddle table is staged the waves run without workgroup barriers.  The
-// inverse runs the radix plan in reverse order, so the forward outputs feed it
-// straight from registers, where the product with K^ is taken.
+// written back in place.  A pencil's threads lie in one wavefront, so the
+// waves run without workgroup barriers; twiddles come through the caches from
+// the global table (staging them in LDS cost occupancy and was slower).  The
+// inverse runs the radix plan in reverse order, so the forward outputs feed
+// it straight from registers, where the product with K^ is taken.
 template <typename R, int L, int QW>
 __global__ void __launch_bounds__(4 * QW * plan_threads(L))
 k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int64_t My, int Nz, int64_t Hy,
@@ -326,6 +333,7 @@ k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int
     using G = Fft<R, L, true, true>;
     constexpr int E = F::E;
     constexpr int HZ = L / 2 + 1;
+    constexpr int SL = slot_len<R>(L);
     cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
     const int tid = threadIdx.x, t = tid % F::P, slot = tid / F::P, j = slot & 3;
     const int64_t quad = (int64_t)blockIdx.x * QW + (slot >> 2);
@@ -336,25 +344,22 @@ k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int
     const bool act = valid && !(((j & 1) && px == kx) || ((j & 2) && py == ky));
     cx<R> *pen = buf + (px * My + py) * (int64_t)Nz;
     const cx<R> *krow = khat + (kx * Hy + ky) * (int64_t)HZ;
-    cx<R> *my = lds + slot * slot_len(L);
-    cx<R> *twl = lds + 4 * QW * slot_len(L);
+    cx<R> *my = lds + slot * SL;
     auto ref = [&](int m) -> cx<R> & { return my[padded(m)]; };
     cx<R> v[E];
     F::load0(v, t, [&](int m) { return (act && m < Nz) ? pen[m] : czero<R>(); });
-    stage_twiddles<R, L>(twl, tw);
-    __syncthreads();
-    auto twf = [&](int e) { return twl[e]; };
-    F::compute_keep(v, t, twf, R(-1), ref);
+    auto twf = [&](int e) { return tw[e]; };
+    F::template compute_keep<-1>(v, t, twf, ref);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int k = F::out_index(t, i);
         v[i] = valid ? cmul<R>(v[i], krow[k <= L / 2 ? k : L - k]) : czero<R>();
     }
-    G::compute(v, t, twf, R(1),
-               [&](int m, cx<R> x) {
-                   if (act && m < Nz) pen[m] = x;
-               },
-               ref);
+    G::template compute<1>(v, t, twf,
+                           [&](int m, cx<R> x) {
+                               if (act && m < Nz) pen[m] = x;
+                           },
+                           ref);
 }
 
 // First pass of the kernel spectrum, fused with the kernel's tabulation: one
@@ -369,14 +374,16 @@ k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, 
      double ki, double2 self, const double2 *__restrict__ tw) {
     using F = Fft<double, L, false, true>;
     constexpr int HZ = L / 2 + 1;
+    constexpr int SL = slot_len<double>(L);
+    constexpr int NT = plan_tw_len(L, false);
     cx<double> *lds = reinterpret_cast<cx<double> *>(nvp_smem);
     const int tid = threadIdx.x, t = tid % F::P, c = tid / F::P;
     const int64_t row = (int64_t)blockIdx.x * PW + c;
     const bool act = row < Hx * Hy;
     const int64_t i = act ? row / Hy : 0, jj = act ? row % Hy : 0;
-    cx<double> *my = lds + c * slot_len(L);
-    cx<double> *twl = lds + PW * slot_len(L);
-    stage_twiddles<double, L>(twl, tw);
+    cx<double> *my = lds + c * SL;
+    cx<double> *twl = lds + PW * SL;
+    stage_table<double>(twl, tw, NT);
     __syncthreads();
     auto twf = [&](int e) { return twl[e]; };
 #pragma unroll 1
@@ -396,18 +403,12 @@ k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, 
         my[padded(k)] = v;
     }
     wave_sync();
-    F::template run<true>(
-        t, twf, -1.0, [&](int m) { return my[padded(m <= L / 2 ? m : L - m)]; },
+    F::template run<-1, true>(
+        t, twf, [&](int m) { return my[padded(m <= L / 2 ? m : L - m)]; },
         [&](int m, cx<double> v) {
             if (act && m < HZ) out[row * HZ + m] = v;
         },
         [&](int m) -> cx<double> & { return my[padded(m)]; });
 }
-
-// Octant [Hx][Hy][Hz] of the embedded kernel in FP64: K at offset (i, j, k) for
-// i < Nx, j < Ny, k < Nz (equation "quad": h^3 G_k(|d| h), self voxel given),
-// zero beyond (the embedding is exact for M >= 2N - 1).
-__global__ void k_ktab(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Hz, int64_t Nx, int64_t Ny,
-                       int64_t Nz, double h, double kr, double ki, double2 self);
 
 }  // namespace nvp

@@ -35,7 +35,6 @@ struct StridedArgs {
     double scale;
     int64_t inner, outer;
     int sign;
-    int cols;  // columns per workgroup: 0 = default, else a compiled variant (8, 16, 32)
 };
 
 // Field of the fused source build (see LdSource).
@@ -56,7 +55,6 @@ struct SourceArgs {
     int64_t out_ms;  // Ny * Nz
     int64_t inner;   // Ny * Nz
     int chunk;       // > 0: staged separable transfer with this x-chunk; 0: direct gathers
-    int cols;        // columns per workgroup: 0 = default, else a compiled variant (8, 32)
 };
 
 hipError_t launch_strided_c64(int L, const StridedArgs &a, const void *tw, hipStream_t s);

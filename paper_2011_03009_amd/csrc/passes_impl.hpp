@@ -1,4 +1,4 @@
-// Launcher templates shared by the per-precision translation units.
+// Launcher templates shared by the per-length translation units.
 #pragma once
 
 #include "kernels.hpp"
@@ -13,12 +13,17 @@ template <typename R> constexpr int strided_cols(int L) {
     return t < lo ? lo : (t > hi ? hi : t);
 }
 
-// Pencils per workgroup of the contiguous kernel: about 256 threads, LDS <= 128 KiB.
+// Pencils per workgroup of the contiguous FP64 kernel: about 256 threads,
+// LDS <= 128 KiB, and whole wavefronts (a multiple of 64 / P pencils).
 template <typename R> constexpr int contig_pencils(int L) {
-    const int by_threads = 256 / plan_threads(L) > 0 ? 256 / plan_threads(L) : 1;
-    const int by_lds = (int)((131072 - L * (int)sizeof(cx<R>)) / (slot_len(L) * (int)sizeof(cx<R>)));
-    const int p = by_threads < by_lds ? by_threads : by_lds;
-    return p > 0 ? p : 1;
+    const int P = plan_threads(L);
+    const int by_threads = 256 / P > 0 ? 256 / P : 1;
+    const int by_lds = (int)((131072 - twiddle_table_len(L) * (int)sizeof(cx<R>)) /
+                             (slot_len<R>(L) * (int)sizeof(cx<R>)));
+    int p = by_threads < by_lds ? by_threads : by_lds;
+    const int unit = P < 64 ? 64 / P : 1;
+    p = (p / unit) * unit;
+    return p > 0 ? p : unit;
 }
 
 template <class K> inline hipError_t allow_lds(K kern, size_t bytes) {
@@ -27,60 +32,50 @@ template <class K> inline hipError_t allow_lds(K kern, size_t bytes) {
                                (int)bytes);
 }
 
-// A column count is usable if the workgroup stays within 1024 threads and 160 KiB of LDS.
-template <typename R, int L, int T> constexpr bool cols_ok() {
-    return T * plan_threads(L) <= 1024 && (size_t)T * L * sizeof(cx<R>) <= 163840;
+template <typename R, int L, int T> constexpr size_t strided_lds() {
+    return ((size_t)T * L + (tw_fits<R>((size_t)T * L, plan_tw_len(L, false)) ? plan_tw_len(L, false) : 0)) *
+           sizeof(cx<R>);
 }
 
-template <typename R, typename Rout, int L, int T>
-hipError_t strided_t(const StridedArgs &a, const void *tw, hipStream_t s) {
+template <typename R, typename Rout, int L, int SG, bool SC, bool MIRROR>
+hipError_t strided_v(const StridedArgs &a, const void *tw, hipStream_t s) {
+    constexpr int T = strided_cols<R>(L);
     using Ld = LdPlain<R, L>;
-    using St = StPlain<R, Rout>;
+    using St = StPlain<R, Rout, SC>;
     Ld ld{static_cast<const cx<R> *>(a.in), a.in_os, a.in_ms, a.n_in, a.mirror};
     St st{static_cast<cx<Rout> *>(a.out), a.out_os, a.out_ms, a.n_out, (R)a.scale};
-    const size_t lds = ((size_t)T * L + (tw_fits<R, L>((size_t)T * L) ? L : 0)) * sizeof(cx<R>);
-    dim3 grid((unsigned)((a.inner + T - 1) / T), (unsigned)a.outer);
-    if constexpr (sizeof(R) == 8) {
-        if (a.mirror) {
-            auto kern = k_strided<R, L, T, true, Ld, St>;
-            static const hipError_t attr = allow_lds(kern, lds);
-            if (attr != hipSuccess) return attr;
-            hipLaunchKernelGGL(kern, grid, dim3(T * plan_threads(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
-                               (R)a.sign, a.inner);
-            return hipGetLastError();
-        }
-    } else if (a.mirror) {
-        return hipErrorInvalidValue;
-    }
-    auto kern = k_strided<R, L, T, false, Ld, St>;
+    auto kern = k_strided<R, L, T, SG, MIRROR, Ld, St>;
+    constexpr size_t lds = strided_lds<R, L, T>();
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
+    dim3 grid((unsigned)((a.inner + T - 1) / T), (unsigned)a.outer);
     hipLaunchKernelGGL(kern, grid, dim3(T * plan_threads(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
-                       (R)a.sign, a.inner);
+                       a.inner);
     return hipGetLastError();
 }
 
-// Column-count variants (complex64 passes): a.cols = 8, 16 or 32, else the default.
+// Variants in use: forward, inverse, inverse with the epilogue scale, and
+// (FP64 only) forward on mirrored even sequences.
 template <typename R, typename Rout, int L>
 hipError_t strided_impl(const StridedArgs &a, const void *tw, hipStream_t s) {
-    constexpr int T0 = strided_cols<R>(L);
-    if constexpr (sizeof(R) == 4) {
-        if (a.cols == 8 && T0 != 8) {
-            if constexpr (cols_ok<R, L, 8>()) return strided_t<R, Rout, L, 8>(a, tw, s);
+    if (a.mirror) {
+        if constexpr (sizeof(R) == 8) {
+            if (a.sign < 0 && a.scale == 1.0) return strided_v<R, Rout, L, -1, false, true>(a, tw, s);
         }
-        if (a.cols == 16 && T0 != 16) {
-            if constexpr (cols_ok<R, L, 16>()) return strided_t<R, Rout, L, 16>(a, tw, s);
-        }
-        if (a.cols == 32 && T0 != 32) {
-            if constexpr (cols_ok<R, L, 32>()) return strided_t<R, Rout, L, 32>(a, tw, s);
-        }
+        return hipErrorInvalidValue;
     }
-    return strided_t<R, Rout, L, T0>(a, tw, s);
+    if constexpr (sizeof(R) == sizeof(Rout)) {
+        if (a.sign < 0 && a.scale == 1.0) return strided_v<R, Rout, L, -1, false, false>(a, tw, s);
+        if (a.sign > 0 && a.scale == 1.0) return strided_v<R, Rout, L, 1, false, false>(a, tw, s);
+        if (a.sign > 0) return strided_v<R, Rout, L, 1, true, false>(a, tw, s);
+    }
+    return hipErrorInvalidValue;
 }
 
-template <typename R, int L, int K, int T> hipError_t xsrc_impl_k(const SourceArgs &a, const void *tw, hipStream_t s) {
+template <typename R, int L, int K> hipError_t xsrc_impl_k(const SourceArgs &a, const void *tw, hipStream_t s) {
+    constexpr int T = strided_cols<R>(L);
     using Ld = LdSource<R, K>;
-    using St = StPlain<R, R>;
+    using St = StPlain<R, R, false>;
     Ld ld;
     for (int i = 0; i < NVP_MAX_FIELDS; ++i) {
         const FieldArgs &f = a.f[i < a.nf ? i : 0];
@@ -97,7 +92,7 @@ template <typename R, int L, int K, int T> hipError_t xsrc_impl_k(const SourceAr
     ld.Nx = a.Nx;
     ld.Nz = a.Nz;
     St st{static_cast<cx<R> *>(a.out), 0, a.out_ms, L, R(1)};
-    const size_t lds = ((size_t)T * L + (tw_fits<R, L>((size_t)T * L) ? L : 0)) * sizeof(cx<R>);
+    constexpr size_t lds = strided_lds<R, L, T>();
     dim3 grid((unsigned)((a.inner + T - 1) / T), 1);
     if (a.chunk > 0) {
         auto kern = k_xsrc_staged<R, L, T, K, St>;
@@ -115,29 +110,16 @@ template <typename R, int L, int K, int T> hipError_t xsrc_impl_k(const SourceAr
     return hipGetLastError();
 }
 
-template <typename R, int L, int T> hipError_t xsrc_impl_t(const SourceArgs &a, const void *tw, hipStream_t s) {
-    if (a.order == 1) return xsrc_impl_k<R, L, 2, T>(a, tw, s);
-    if (a.order == 3) return xsrc_impl_k<R, L, 4, T>(a, tw, s);
-    return hipErrorInvalidValue;
-}
-
 template <typename R, int L> hipError_t xsrc_impl(const SourceArgs &a, const void *tw, hipStream_t s) {
-    constexpr int T0 = strided_cols<R>(L);
-    if constexpr (sizeof(R) == 4) {
-        if (a.cols == 8 && T0 != 8) {
-            if constexpr (cols_ok<R, L, 8>()) return xsrc_impl_t<R, L, 8>(a, tw, s);
-        }
-        if (a.cols == 32 && T0 != 32) {
-            if constexpr (cols_ok<R, L, 32>()) return xsrc_impl_t<R, L, 32>(a, tw, s);
-        }
-    }
-    return xsrc_impl_t<R, L, T0>(a, tw, s);
+    if (a.order == 1) return xsrc_impl_k<R, L, 2>(a, tw, s);
+    if (a.order == 3) return xsrc_impl_k<R, L, 4>(a, tw, s);
+    return hipErrorInvalidValue;
 }
 
 template <typename R, int L, int QW>
 hipError_t zconv_qw(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, hipStream_t s) {
     auto kern = k_zconv<R, L, QW>;
-    const size_t lds = ((size_t)4 * QW * slot_len(L) + L) * sizeof(cx<R>);
+    constexpr size_t lds = (size_t)4 * QW * slot_len<R>(L) * sizeof(cx<R>);
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
     const int64_t Hx = Mx / 2 + 1, Hy = My / 2 + 1, nq = Hx * Hy;
@@ -150,7 +132,7 @@ hipError_t zconv_qw(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz,
 template <typename R, int L>
 hipError_t zconv_impl(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, hipStream_t s) {
     // quads per workgroup: up to 256 threads and 80 KiB of LDS
-    constexpr int QW = (4 * plan_threads(L) <= 128 && (8 * slot_len(L) + L) * (int)sizeof(cx<R>) <= 81920) ? 2 : 1;
+    constexpr int QW = (4 * plan_threads(L) <= 128 && 8 * slot_len<R>(L) * (int)sizeof(cx<R>) <= 81920) ? 2 : 1;
     if (zconv_quads_override() == 1) return zconv_qw<R, L, 1>(buf, khat, Mx, My, Nz, tw, s);
     return zconv_qw<R, L, QW>(buf, khat, Mx, My, Nz, tw, s);
 }
@@ -160,7 +142,7 @@ hipError_t kz_impl(double2 *out, const int64_t H[3], const int64_t N[3], double 
                    double self_re, double self_im, const void *tw, hipStream_t s) {
     constexpr int PW = contig_pencils<double>(L);
     auto kern = k_kz<L, PW>;
-    const size_t lds = ((size_t)PW * slot_len(L) + L) * sizeof(double2);
+    constexpr size_t lds = ((size_t)PW * slot_len<double>(L) + plan_tw_len(L, false)) * sizeof(double2);
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
     const int64_t rows = H[0] * H[1];

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/nvp.h"
+#include "fft_core.hpp"
 #include "launch.hpp"
 
 using nvp::FieldArgs;
@@ -48,9 +49,6 @@ struct nvp_ctx {
     std::vector<Twiddle> tw;
     VpCache vp;
     size_t max_lds = 0;
-    // columns per workgroup of the complex64 x and y passes and the source build
-    // (0 = compiled default); read from NVP_COLS_X / NVP_COLS_Y / NVP_COLS_SRC.
-    int cols_x = 0, cols_y = 0, cols_src = 0;
 };
 
 namespace {
@@ -150,33 +148,47 @@ int64_t circulant_len(int64_t n) {
     return -1;
 }
 
-// exp(-2 pi i e / L), e in [0, L), in extended precision, rounded once.
+// Per-stage twiddle tables of length L: for the radix plan run forward and
+// then in reverse order, stage s >= 1 (radix r, Ns = product of the earlier
+// radices) holds exp(-2 pi i j q / (Ns r)) at [j][q-1], j < Ns, 1 <= q < r;
+// computed in extended precision and rounded once.
 nvp_status twiddles(nvp_ctx *ctx, int L, bool dbl, const void **out) {
     for (auto &t : ctx->tw)
         if (t.L == L && t.dbl == (int)dbl) {
             *out = t.dev;
             return NVP_OK;
         }
-    std::vector<double> hd(2 * (size_t)L);
-    for (int e = 0; e < L; ++e) {
-        long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)e / (long double)L;
-        hd[2 * e] = (double)cosl(ang);
-        hd[2 * e + 1] = (double)-sinl(ang);
+    const int n = nvp::twiddle_table_len(L);
+    std::vector<double> hd(2 * (size_t)(n > 0 ? n : 1));
+    size_t e = 0;
+    for (int rev = 0; rev < 2; ++rev) {
+        const int S = nvp::plan_for(L).S;
+        for (int st = 1; st < S; ++st) {
+            const int Ns = nvp::plan_ns(L, rev, st), r = nvp::plan_rad(L, rev, st);
+            for (int j = 0; j < Ns; ++j)
+                for (int q = 1; q < r; ++q, ++e) {
+                    long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)(j * q) /
+                                      (long double)(Ns * r);
+                    hd[2 * e] = (double)cosl(ang);
+                    hd[2 * e + 1] = (double)-sinl(ang);
+                }
+        }
     }
+    const size_t cnt = hd.size() / 2;
     void *dev = nullptr;
-    size_t bytes = (size_t)L * (dbl ? 16 : 8);
+    const size_t bytes = cnt * (dbl ? 16 : 8);
     NVP_HIP(ctx, hipMalloc(&dev, bytes));
-    hipError_t e;
+    hipError_t err;
     if (dbl) {
-        e = hipMemcpy(dev, hd.data(), bytes, hipMemcpyHostToDevice);
+        err = hipMemcpy(dev, hd.data(), bytes, hipMemcpyHostToDevice);
     } else {
-        std::vector<float> hf(2 * (size_t)L);
+        std::vector<float> hf(hd.size());
         for (size_t i = 0; i < hf.size(); ++i) hf[i] = (float)hd[i];
-        e = hipMemcpy(dev, hf.data(), bytes, hipMemcpyHostToDevice);
+        err = hipMemcpy(dev, hf.data(), bytes, hipMemcpyHostToDevice);
     }
-    if (e != hipSuccess) {
+    if (err != hipSuccess) {
         (void)hipFree(dev);
-        return hip_fail(ctx, "twiddle upload", e);
+        return hip_fail(ctx, "twiddle upload", err);
     }
     ctx->tw.push_back({L, (int)dbl, dev});
     *out = dev;
@@ -299,7 +311,6 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
         Timer t(timed, NVP_T_XFWD);
         if (src) {
             SourceArgs s = *src;
-            s.cols = ctx->cols_src;
             s.out = A;
             s.out_ms = Ny * Nz;
             s.inner = Ny * Nz;
@@ -308,7 +319,7 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
             StridedArgs a{};
             a.in = f; a.in_os = 0; a.in_ms = Ny * Nz; a.n_in = (int)Nx;
             a.out = A; a.out_os = 0; a.out_ms = Ny * Nz; a.n_out = (int)Mx;
-            a.scale = 1.0; a.inner = Ny * Nz; a.outer = 1; a.sign = -1; a.cols = ctx->cols_x;
+            a.scale = 1.0; a.inner = Ny * Nz; a.outer = 1; a.sign = -1;
             NVP_HIP(ctx, strided((int)Mx, a, twx, ctx->stream));
         }
     }
@@ -317,7 +328,7 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
         StridedArgs a{};
         a.in = A; a.in_os = Ny * Nz; a.in_ms = Nz; a.n_in = (int)Ny;
         a.out = B; a.out_os = My * Nz; a.out_ms = Nz; a.n_out = (int)My;
-        a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = -1; a.cols = ctx->cols_y;
+        a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = -1;
         NVP_HIP(ctx, strided((int)My, a, twy, ctx->stream));
     }
     {
@@ -330,7 +341,7 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
         StridedArgs a{};
         a.in = B; a.in_os = My * Nz; a.in_ms = Nz; a.n_in = (int)My;
         a.out = A; a.out_os = Ny * Nz; a.out_ms = Nz; a.n_out = (int)Ny;
-        a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = 1; a.cols = ctx->cols_y;
+        a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = 1;
         NVP_HIP(ctx, strided((int)My, a, twy, ctx->stream));
     }
     {
@@ -338,7 +349,7 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
         StridedArgs a{};
         a.in = A; a.in_os = 0; a.in_ms = Ny * Nz; a.n_in = (int)Mx;
         a.out = u; a.out_os = 0; a.out_ms = Ny * Nz; a.n_out = (int)Nx;
-        a.scale = scale; a.inner = Ny * Nz; a.outer = 1; a.sign = 1; a.cols = ctx->cols_x;
+        a.scale = scale; a.inner = Ny * Nz; a.outer = 1; a.sign = 1;
         NVP_HIP(ctx, strided((int)Mx, a, twx, ctx->stream));
     }
     return NVP_OK;
@@ -437,13 +448,6 @@ nvp_status nvp_ctx_create(int device, void *hip_stream, nvp_ctx **out) {
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->max_lds = prop.sharedMemPerBlock;
-    auto env = [](const char *n) {
-        const char *v = getenv(n);
-        return v ? atoi(v) : 0;
-    };
-    c->cols_x = env("NVP_COLS_X");
-    c->cols_y = env("NVP_COLS_Y");
-    c->cols_src = env("NVP_COLS_SRC");
     *out = c;
     return NVP_OK;
 }
