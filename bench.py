@@ -68,7 +68,8 @@ def alg_bytes(P, g1, gn, order_fields):
         b["ktab"] += 16.0 * Ho  # tabulation fused into the z pass: FP64 octant written once
         b["kfft"] += 16.0 * Ho * 2 + 16.0 * Ho + 8.0 * Ho  # y pass r+w FP64; x pass reads FP64, writes complex64
         src = sum(nsz(grids[m - 1]) for m in range(1, n))
-        b["xfwd"] += ELEM * (src + M[0] * N[1] * N[2])
+        b["src"] += ELEM * (src + N[0] * N[1] * N[2])  # native fields in, f_n out
+        b["xfwd"] += ELEM * (N[0] * N[1] * N[2] + M[0] * N[1] * N[2])
         b["yfwd"] += ELEM * (M[0] * N[1] * N[2] + M[0] * M[1] * N[2])
         b["zconv"] += ELEM * (2 * M[0] * M[1] * N[2] + Ho)
         b["yinv"] += ELEM * (M[0] * M[1] * N[2] + M[0] * N[1] * N[2])
@@ -187,8 +188,8 @@ def main():
             "frac": achieved / PEAK_HBM_GBS, "traffic": None,
             "alg_bytes_per_launch": ab[dom] / max(1.0, per_kind[dom]["launches_per_step"]),
             "avg_launch_ms": per_kind[dom]["ms_per_step"] / max(1.0, per_kind[dom]["launches_per_step"])}
-    conv_kinds = ("xfwd", "yfwd", "zconv", "yinv", "xinv")
-    conv_ms = sum(per_kind[k]["ms_per_step"] for k in conv_kinds)
+    conv_kinds = ("src", "xfwd", "yfwd", "zconv", "yinv", "xinv")
+    conv_ms = sum(per_kind[k]["ms_per_step"] for k in conv_kinds if k in per_kind)
     conv_gbs = sum(ab[k] for k in conv_kinds) / (conv_ms * 1e-3) / 1e9
 
     result = {

@@ -150,12 +150,13 @@ nvp_status nvp_plan_destroy(nvp_plan *plan);
 /* Kinds of kernel timed by nvp_plan_get_timing. */
 #define NVP_T_KTAB 0   /* kernel tabulation fused with the first (z) FP64 FFT pass */
 #define NVP_T_KFFT 1   /* kernel spectrum: the y and x FP64 FFT passes and the downcast */
-#define NVP_T_XFWD 2   /* transfer + source build fused into the forward x pass */
+#define NVP_T_XFWD 2   /* forward x pass (with the source build fused in, when that path is used) */
 #define NVP_T_YFWD 3   /* forward y pass */
 #define NVP_T_ZCONV 4  /* z pass: forward FFT, spectral multiply, inverse FFT */
 #define NVP_T_YINV 5   /* inverse y pass */
 #define NVP_T_XINV 6   /* inverse x pass with the C_n / M scale */
-#define NVP_T_KINDS 7
+#define NVP_T_SRC 7    /* transfer + source build as its own tiled kernel */
+#define NVP_T_KINDS 8
 
 /* enable != 0: bracket every kernel launch with HIP events on the plan's
  * stream from now on (adds no device work between kernels). */

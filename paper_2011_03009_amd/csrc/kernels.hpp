@@ -23,7 +23,7 @@ namespace nvp {
 // m >= n.  Mirrored: the column holds entries 0..L/2 of an even sequence of
 // length L, and entry m > L/2 equals entry L - m.
 template <typename R, int L> struct LdPlain {
-    const cx<R> *__restrict__ p;
+    const cx<R> *p;  // may alias the output: in-place passes
     int64_t os, ms;
     int n;
     int mirror;
@@ -45,7 +45,7 @@ template <> __device__ __forceinline__ float2 cvt<double, float>(double2 v) {
 
 // Stores element m < n of column (o, col), times a real scale when SC.
 template <typename R, typename Rout, bool SC> struct StPlain {
-    cx<Rout> *__restrict__ p;
+    cx<Rout> *p;
     int64_t os, ms;
     int n;
     R scale;
@@ -313,6 +313,102 @@ k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t i
             if (act) st(0, col, m, v);
         },
         [&](int m) -> cx<R> & { return lds[m * T + c]; });
+}
+
+// Transfer + source build as a kernel of its own (writes f_n, read by a plain
+// forward x pass afterwards).  One workgroup per target tile of SX x SY x SZ
+// voxels (z fastest); for every field that needs interpolating it loads the
+// source block the tile's stencils touch into LDS once (coalesced along z),
+// then interpolates along z, y and x in turn inside LDS; fields on the target
+// grid are read directly.  Each thread keeps its voxels' interpolated values
+// in registers and finally writes sum_m v_m v_{n-m}.  The host checks that
+// the source blocks of every tile fit the LDS budget given at launch.
+template <typename R, int K, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(TY *TZ)
+k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems) {
+    cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
+    const int Nx = src.Nx, Nz = src.Nz;
+    const int tz = threadIdx.x % TZ, ty = threadIdx.x / TZ;
+    const int ix0 = blockIdx.z * TX, iy0 = blockIdx.y * TY, iz0 = blockIdx.x * TZ;
+    const int ix1 = min(ix0 + TX, Nx), iy1 = min(iy0 + TY, Ny), iz1 = min(iz0 + TZ, Nz);
+    const int iy = iy0 + ty, iz = iz0 + tz;
+    const bool inyz = iy < Ny && iz < Nz;
+    cx<R> v[NVP_MAX_FIELDS][TX];
+#pragma unroll
+    for (int i = 0; i < NVP_MAX_FIELDS; ++i)
+#pragma unroll
+        for (int a = 0; a < TX; ++a) v[i][a] = czero<R>();
+#pragma unroll
+    for (int i = 0; i < NVP_MAX_FIELDS; ++i) {
+        if (i >= src.nf) continue;
+        const FieldDev<R> &g = src.f[i];
+        if (g.identity) {
+#pragma unroll
+            for (int a = 0; a < TX; ++a)
+                if (inyz && ix0 + a < Nx) v[i][a] = g.p[(ix0 + a) * g.s0 + (int64_t)iy * g.s1 + iz];
+            continue;
+        }
+        // source block [sx0, sx0+SX) x [sy0, sy0+SY) x [sz0, sz0+SZ)
+        const int sx0 = g.b[0][ix0], sy0 = g.b[1][iy0], sz0 = g.b[2][iz0];
+        const int SX = g.b[0][ix1 - 1] + K - sx0, SY = g.b[1][iy1 - 1] + K - sy0, SZ = g.b[2][iz1 - 1] + K - sz0;
+        cx<R> *S = lds;                         // [SX][SY][SZ], later T2 [SX][TY][TZ]
+        cx<R> *T1 = lds + (lds_elems - (int64_t)SX * SY * TZ);  // [SX][SY][TZ]
+        const int nS = SX * SY * SZ;
+        for (int e = threadIdx.x; e < nS; e += TY * TZ) {
+            const int sz = e % SZ, r = e / SZ, sy = r % SY, sx = r / SY;
+            S[e] = g.p[(int64_t)(sx0 + sx) * g.s0 + (int64_t)(sy0 + sy) * g.s1 + sz0 + sz];
+        }
+        __syncthreads();
+        const int nT1 = SX * SY * TZ;
+        for (int e = threadIdx.x; e < nT1; e += TY * TZ) {
+            const int z = e % TZ, r = e / TZ;  // r = sx * SY + sy
+            cx<R> acc = czero<R>();
+            if (iz0 + z < Nz) {
+                const int zz = iz0 + z, o = g.b[2][zz] - sz0;
+#pragma unroll
+                for (int d = 0; d < K; ++d) acc = cadd<R>(acc, cscale<R>(S[r * SZ + o + d], g.w[2][zz * K + d]));
+            }
+            T1[e] = acc;
+        }
+        __syncthreads();
+        cx<R> *T2 = S;
+        const int nT2 = SX * TY * TZ;
+        for (int e = threadIdx.x; e < nT2; e += TY * TZ) {
+            const int z = e % TZ, r = e / TZ, y = r % TY, sx = r / TY;
+            cx<R> acc = czero<R>();
+            if (iy0 + y < Ny) {
+                const int yy = iy0 + y, o = g.b[1][yy] - sy0;
+#pragma unroll
+                for (int c = 0; c < K; ++c)
+                    acc = cadd<R>(acc, cscale<R>(T1[((sx * SY) + o + c) * TZ + z], g.w[1][yy * K + c]));
+            }
+            T2[e] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < TX; ++a) {
+            const int ix = ix0 + a;
+            if (ix < Nx) {
+                const int o = g.b[0][ix] - sx0;
+                cx<R> acc = czero<R>();
+#pragma unroll
+                for (int b = 0; b < K; ++b)
+                    acc = cadd<R>(acc, cscale<R>(T2[((o + b) * TY + ty) * TZ + tz], g.w[0][ix * K + b]));
+                v[i][a] = acc;
+            }
+        }
+        __syncthreads();
+    }
+    if (!inyz) return;
+#pragma unroll
+    for (int a = 0; a < TX; ++a) {
+        const int ix = ix0 + a;
+        if (ix >= Nx) break;
+        cx<R> w[NVP_MAX_FIELDS];
+#pragma unroll
+        for (int i = 0; i < NVP_MAX_FIELDS; ++i) w[i] = v[i][a];
+        out[((int64_t)ix * Ny + iy) * Nz + iz] = src.products(w);
+    }
 }
 
 // The z pass of the convolution.  A quad = the up-to-four pencils

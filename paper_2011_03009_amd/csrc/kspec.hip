@@ -2,7 +2,7 @@
 #include <math.h>
 #include <stdlib.h>
 
-#include "kernels.hpp"
+#include "passes_impl.hpp"
 
 namespace nvp {
 
@@ -33,6 +33,46 @@ hipError_t launch_ktab(double2 *out, const int64_t H[3], const int64_t N[3], dou
     hipLaunchKernelGGL(k_ktab, dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s, out, H[0], H[1], H[2], N[0],
                        N[1], N[2], h, kr, ki, make_double2(self_re, self_im));
     return hipGetLastError();
+}
+
+template <typename R, int K>
+static hipError_t source_k(const SourceArgs &a, void *out, int Ny, int64_t lds_elems, hipStream_t s) {
+    LdSource<R, K> ld;
+    for (int i = 0; i < NVP_MAX_FIELDS; ++i) {
+        const FieldArgs &f = a.f[i < a.nf ? i : 0];
+        ld.f[i].p = static_cast<const cx<R> *>(f.p);
+        ld.f[i].s0 = f.s0;
+        ld.f[i].s1 = f.s1;
+        for (int ax = 0; ax < 3; ++ax) {
+            ld.f[i].b[ax] = f.b[ax];
+            ld.f[i].w[ax] = static_cast<const R *>(f.w[ax]);
+        }
+        ld.f[i].identity = f.identity;
+    }
+    ld.nf = a.nf;
+    ld.Nx = a.Nx;
+    ld.Nz = a.Nz;
+    auto kern = k_source<R, K, NVP_SRC_TX, NVP_SRC_TY, NVP_SRC_TZ>;
+    const size_t lds = (size_t)lds_elems * sizeof(cx<R>);
+    hipError_t e = allow_lds(kern, lds > 65536 ? 163840 : lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)((a.Nz + NVP_SRC_TZ - 1) / NVP_SRC_TZ), (unsigned)((Ny + NVP_SRC_TY - 1) / NVP_SRC_TY),
+              (unsigned)((a.Nx + NVP_SRC_TX - 1) / NVP_SRC_TX));
+    hipLaunchKernelGGL(kern, grid, dim3(NVP_SRC_TY * NVP_SRC_TZ), lds, s, ld, static_cast<cx<R> *>(out), Ny,
+                       lds_elems);
+    return hipGetLastError();
+}
+
+hipError_t launch_source_c64(const SourceArgs &a, void *out, int Ny, int64_t lds_elems, hipStream_t s) {
+    if (a.order == 1) return source_k<float, 2>(a, out, Ny, lds_elems, s);
+    if (a.order == 3) return source_k<float, 4>(a, out, Ny, lds_elems, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_source_c128(const SourceArgs &a, void *out, int Ny, int64_t lds_elems, hipStream_t s) {
+    if (a.order == 1) return source_k<double, 2>(a, out, Ny, lds_elems, s);
+    if (a.order == 3) return source_k<double, 4>(a, out, Ny, lds_elems, s);
+    return hipErrorInvalidValue;
 }
 
 bool length_supported(int L) { return plan_for(L).S > 0; }

@@ -65,6 +65,14 @@ hipError_t launch_strided_f64_c64(int L, const StridedArgs &a, const void *tw, h
 hipError_t launch_xsrc_c64(int L, const SourceArgs &a, const void *tw, hipStream_t s);
 hipError_t launch_xsrc_c128(int L, const SourceArgs &a, const void *tw, hipStream_t s);
 
+// Transfer + source build (k_source): f_n written to `out` [Nx][Ny][Nz]; tiles
+// of SRC_TX x SRC_TY x SRC_TZ target voxels, lds_elems complex entries of LDS.
+#define NVP_SRC_TX 4
+#define NVP_SRC_TY 8
+#define NVP_SRC_TZ 32
+hipError_t launch_source_c64(const SourceArgs &a, void *out, int Ny, int64_t lds_elems, hipStream_t s);
+hipError_t launch_source_c128(const SourceArgs &a, void *out, int Ny, int64_t lds_elems, hipStream_t s);
+
 hipError_t launch_zconv_c64(int L, void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw,
                             hipStream_t s);
 hipError_t launch_zconv_c128(int L, void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw,

@@ -66,6 +66,7 @@ struct Harm {
     void *khat = nullptr;
     bool khat_ok = false;
     int chunk = 0;  // x-chunk of the staged source build (0: direct gathers)
+    int64_t src_lds = 0;  // > 0: separate tiled source kernel with this many LDS entries
     HarmField f[NVP_MAX_FIELDS];
 };
 
@@ -88,6 +89,7 @@ struct nvp_plan {
     void *A = nullptr, *B = nullptr, *tables = nullptr;
     size_t bytes_A = 0, bytes_B = 0, bytes_tables = 0, bytes_khat = 0;
     bool cache = true;
+    bool use_source_kernel = true;  // NVP_FUSED_SOURCE=1 selects the source build fused into the x pass
     bool timing = false;
     std::vector<TimedEvent> events;
     std::vector<hipEvent_t> pool;
@@ -297,7 +299,7 @@ size_t kscratch_bytes(const int64_t M[3]) { return (size_t)(M[0] / 2 + 1) * (M[1
 // y inv, x inv with `scale` into u.
 nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid *g, const int64_t M[3],
                     const void *khat, void *A, void *B, const void *f, const SourceArgs *src, void *u,
-                    double scale) {
+                    double scale, int64_t src_lds = 0) {
     const int64_t Nx = g->n[0], Ny = g->n[1], Nz = g->n[2];
     const int64_t Mx = M[0], My = M[1], Mz = M[2];
     const bool dbl = prec == NVP_C128;
@@ -307,6 +309,16 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
     if ((st = twiddles(ctx, (int)My, dbl, &twy))) return st;
     if ((st = twiddles(ctx, (int)Mz, dbl, &twz))) return st;
     auto strided = dbl ? nvp::launch_strided_c128 : nvp::launch_strided_c64;
+    if (src && src_lds > 0) {
+        // transfer + source into the first Nx rows of A, then the x pass in place
+        {
+            Timer t(timed, NVP_T_SRC);
+            NVP_HIP(ctx, (dbl ? nvp::launch_source_c128 : nvp::launch_source_c64)(*src, A, (int)Ny, src_lds,
+                                                                                ctx->stream));
+        }
+        f = A;
+        src = nullptr;
+    }
     {
         Timer t(timed, NVP_T_XFWD);
         if (src) {
@@ -696,6 +708,32 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
             if (ok) h.chunk = (int)c;
         }
     }
+    // Tiled source kernel: the largest source block any tile touches, per axis,
+    // over the fields that need interpolating; used when its LDS fits 96 KiB.
+    for (auto &h : p->h) {
+        int64_t msx = 0, msy = 0, msz = 0;
+        bool any = false;
+        const int64_t T[3] = {NVP_SRC_TX, NVP_SRC_TY, NVP_SRC_TZ};
+        for (int m = 1; m < h.n; ++m) {
+            if (h.f[m - 1].identity) continue;
+            any = true;
+            int64_t *mx[3] = {&msx, &msy, &msz};
+            for (int ax = 0; ax < 3; ++ax) {
+                const int *b = reinterpret_cast<const int *>(host.data() + h.f[m - 1].off_b[ax]);
+                const int64_t n = h.g.n[ax];
+                for (int64_t i0 = 0; i0 < n; i0 += T[ax]) {
+                    const int64_t i1 = i0 + T[ax] < n ? i0 + T[ax] : n;
+                    const int64_t span = b[i1 - 1] + K - b[i0];
+                    if (span > *mx[ax]) *mx[ax] = span;
+                }
+            }
+        }
+        h.src_lds = 0;
+        const int64_t blk = msx * msy * msz, t2 = msx * T[1] * T[2];
+        const int64_t elems = (blk > t2 ? blk : t2) + msx * msy * T[2];
+        if (!any) h.src_lds = 1;  // every field already on the target grid: no staging
+        else if (elems * (int64_t)csize(prec) <= 98304) h.src_lds = elems;
+    }
     hipError_t e = hipSuccess;
     if (tbytes) e = hipMalloc(&p->tables, tbytes);
     if (e == hipSuccess) e = hipMalloc(&p->A, maxA);
@@ -710,6 +748,10 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
         free_plan_memory(p);
         delete p;
         return hip_fail(ctx, "nvp_plan_cascade: allocation", e);
+    }
+    {
+        const char *fs = getenv("NVP_FUSED_SOURCE");
+        p->use_source_kernel = !(fs && atoi(fs) == 1);
     }
     p->bytes_A = maxA;
     p->bytes_B = maxB;
@@ -766,7 +808,8 @@ nvp_status nvp_execute_harmonic(nvp_plan *plan, int n, const void *const *fields
         }
     }
     const double scale = h.Cn / ((double)h.M[0] * (double)h.M[1] * (double)h.M[2]);
-    return convolve(ctx, plan, plan->prec, &h.g, h.M, h.khat, plan->A, plan->B, nullptr, &src, pn_dev, scale);
+    return convolve(ctx, plan, plan->prec, &h.g, h.M, h.khat, plan->A, plan->B, nullptr, &src, pn_dev, scale,
+                    plan->use_source_kernel ? h.src_lds : 0);
 }
 
 nvp_status nvp_execute_cascade(nvp_plan *plan, const void *p1_dev, void *const *pn_dev) {

@@ -14,7 +14,7 @@ from . import _native
 from ._native import Grid, Medium
 
 NVP_C64, NVP_C128 = 0, 1
-TIMING_KINDS = ("ktab", "kfft", "xfwd", "yfwd", "zconv", "yinv", "xinv")
+TIMING_KINDS = ("ktab", "kfft", "xfwd", "yfwd", "zconv", "yinv", "xinv", "src")
 _DT = {NVP_C64: torch.complex64, NVP_C128: torch.complex128}
 
 

@@ -143,12 +143,16 @@ def nested_grids(short_x=False):
     return focus, g1, gn
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("short_x", [False, True])
 @pytest.mark.parametrize("prec", [P.NVP_C128, P.NVP_C64])
 @pytest.mark.parametrize("order", [1, 3])
-def test_tiny_nested_cascade_matches_oracle(ctx, order, prec, short_x):
+def test_tiny_nested_cascade_matches_oracle(ctx, order, prec, short_x, fused, monkeypatch):
+    """fused: the source build fused into the x pass (NVP_FUSED_SOURCE=1) instead of its own tiled kernel."""
     focus, g1, gn = nested_grids(short_x)
-    say("case nested-cascade order=%d prec=%d short_x=%d" % (order, prec, short_x))
+    say("case nested-cascade order=%d prec=%d short_x=%d fused=%d" % (order, prec, short_x, fused))
+    if fused:
+        monkeypatch.setenv("NVP_FUSED_SOURCE", "1")
     k1 = oracle.wavenumber(1, F0, WATER)
     pts = bowl.bowl_points(7.5e-3, 15e-3, 128, 1)
     p1 = bowl.incident_field(pts, 7.5e-3, 15e-3, k1, 1e6, g1.coords(0), g1.coords(1), g1.coords(2)).numpy()
