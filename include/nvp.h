@@ -145,6 +145,87 @@ nvp_status nvp_execute_harmonic(nvp_plan *plan, int n, const void *const *fields
 nvp_status nvp_execute_cascade(nvp_plan *plan, const void *p1_dev, void *const *pn_dev);
 nvp_status nvp_plan_destroy(nvp_plan *plan);
 
+/* The source term of harmonic n (eqs. harm2-harm5: f_n = sum over m of
+ * p_m p_{n-m}, no conjugates) on the plan's grid of harmonic n, with the
+ * fields transferred exactly as nvp_execute_harmonic does: fields[m-1] = p_m
+ * on its plan grid for m = 1..n-1; f_dev receives N_n complex elements in the
+ * grid's [Nx][Ny][Nz] layout.  Enqueued on the context stream.
+ * NVP_E_UNSUPPORTED when this grid pair takes the fused source path only. */
+nvp_status nvp_source_term(nvp_plan *plan, int n, const void *const *fields, void *f_dev);
+
+/* ---- truncation boxes (Section 5) ------------------------------------------ */
+
+#define NVP_QBOX_MAX_COUNT 32
+
+/* Localisation boxes of a source term by the measure Q(x) = log10(|f(x)| /
+ * max |f|) of Section 5: for each threshold q0[i] <= 0 (i < count <= 32), the
+ * smallest voxel box outside which Q < q0[i], written as box[6i .. 6i+5] =
+ * lo_x, lo_y, lo_z, hi_x, hi_y, hi_z (inclusive voxel indices).  A voxel is
+ * inside when |f|^2 >= 10^(2 q0) max |f|^2, evaluated in FP64 (the power by
+ * the C library's pow); an all-zero f gives the whole grid.  f_dev: device,
+ * n[0] n[1] n[2] complex elements, [Nx][Ny][Nz]; q0, box: host.  Waits for
+ * the result. */
+nvp_status nvp_qbox(nvp_ctx *ctx, const int64_t n[3], const void *f_dev, nvp_prec prec, int count,
+                    const double *q0, int64_t *box);
+
+/* Truncated potentials at one voxel (the sums of eq. quad restricted to
+ * boxes, for the truncation-convergence sweeps of Section 5): out[2i] + i
+ * out[2i+1] = -sum over voxels j inside box i of K(x_t - x_j) f_j, with the
+ * kernel of Section 3.1 for wavenumber k and the self voxel from its ball
+ * integral, FP64 kernel and accumulation.  t: target voxel index on g; box:
+ * host, count * 6 int64 as in nvp_qbox, each non-empty box inside the grid
+ * (a box with hi < lo on an axis is empty and sums to 0); out: host, 2 count
+ * doubles.  count <= 32.  Waits for the result. */
+nvp_status nvp_box_potential(nvp_ctx *ctx, double k_re, double k_im, const nvp_grid *g, const void *f_dev,
+                             nvp_prec prec, const int64_t t[3], int count, const int64_t *box, double *out);
+
+/* ---- learned box predictor ------------------------------------------------- */
+
+/* A 5-64-64-64-3 tanh MLP in FP32 that maps a transducer and harmonic
+ * (aperture, focal length, frequency, source pressure, harmonic index) to the
+ * three box fractions of that harmonic's truncation box (the paper's
+ * fractions of the reference domain, Section 5 and its domain table; the
+ * paper itself chooses boxes by a rule of thumb instead).  Inputs are
+ * standardised by (x - mean) / std inside the forward pass.  Parameters
+ * (float, row-major W[out][in]): W1[64][5] b1[64] W2[64][64] b2[64]
+ * W3[64][64] b3[64] W4[3][64] b4[3].  Training minimises the pinball loss of
+ * quantile tau averaged over the batch and the outputs,
+ * L = (1 / 3B) sum rho_tau(t - y), rho_tau(u) = u (tau - [u < 0]), with Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8).  All x, y, t, grad buffers are device
+ * arrays in sample-major layout ([B][5], [B][3], [B][3], [8899]). */
+#define NVP_BOXNET_IN 5
+#define NVP_BOXNET_OUT 3
+#define NVP_BOXNET_PARAMS 8899
+#define NVP_BOXNET_MAX_BATCH 65536
+#define NVP_BOXNET_BETA1 0.9f
+#define NVP_BOXNET_BETA2 0.999f
+#define NVP_BOXNET_EPS 1e-8f
+
+typedef struct nvp_boxnet nvp_boxnet;
+
+/* Network for batches of up to max_batch samples; parameters and Adam state
+ * zero, mean 0 and std 1.  Owned by the caller until nvp_boxnet_destroy. */
+nvp_status nvp_boxnet_create(nvp_ctx *ctx, int max_batch, nvp_boxnet **out);
+/* Host copy in/out of the NVP_BOXNET_PARAMS parameters (n must equal it);
+ * setting them also clears the Adam moments and step count.  Both wait. */
+nvp_status nvp_boxnet_set_params(nvp_boxnet *bn, const float *params, int64_t n);
+nvp_status nvp_boxnet_get_params(nvp_boxnet *bn, float *params, int64_t n);
+/* Input standardisation (host arrays of 5; std > 0). */
+nvp_status nvp_boxnet_set_norm(nvp_boxnet *bn, const float *mean, const float *stdev);
+/* y = net(x) for batch samples; enqueued on the context stream. */
+nvp_status nvp_boxnet_predict(nvp_boxnet *bn, int batch, const float *x_dev, float *y_dev);
+/* grad_dev = dL/dparams for targets t_dev, 0 < tau < 1, without updating the
+ * parameters; loss_host (optional) receives L and makes the call wait.
+ * Weight gradients are summed over the batch in sample order (no atomics),
+ * so repeated calls give identical bits. */
+nvp_status nvp_boxnet_grads(nvp_boxnet *bn, int batch, const float *x_dev, const float *t_dev, float tau,
+                            float *grad_dev, float *loss_host);
+/* One Adam step of learning rate lr on the batch; loss_host (optional)
+ * receives the loss before the step and makes the call wait. */
+nvp_status nvp_boxnet_train_step(nvp_boxnet *bn, int batch, const float *x_dev, const float *t_dev, float tau,
+                                 float lr, float *loss_host);
+nvp_status nvp_boxnet_destroy(nvp_boxnet *bn);
+
 /* ---- timing of the plan's kernels ---------------------------------------- */
 
 /* Kinds of kernel timed by nvp_plan_get_timing. */

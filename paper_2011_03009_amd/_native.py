@@ -23,6 +23,8 @@ _dp = ctypes.POINTER(ctypes.c_double)
 _i64 = ctypes.c_int64
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _st = ctypes.c_int32
+_f = ctypes.c_float
+_fp = ctypes.POINTER(ctypes.c_float)
 SIGNATURES = {
     "nvp_status_str": (ctypes.c_char_p, [_st]),
     "nvp_last_error": (ctypes.c_char_p, [_vp]),
@@ -47,6 +49,17 @@ SIGNATURES = {
     "nvp_plan_destroy": (_st, [_vp]),
     "nvp_plan_set_timing": (_st, [_vp, _i]),
     "nvp_plan_get_timing": (_st, [_vp, _dp, _i64p, _i]),
+    "nvp_source_term": (_st, [_vp, _i, ctypes.POINTER(_vp), _vp]),
+    "nvp_qbox": (_st, [_vp, _i64p, _vp, _i, _i, _dp, _i64p]),
+    "nvp_box_potential": (_st, [_vp, _d, _d, ctypes.POINTER(Grid), _vp, _i, _i64p, _i, _i64p, _dp]),
+    "nvp_boxnet_create": (_st, [_vp, _i, ctypes.POINTER(_vp)]),
+    "nvp_boxnet_set_params": (_st, [_vp, _fp, _i64]),
+    "nvp_boxnet_get_params": (_st, [_vp, _fp, _i64]),
+    "nvp_boxnet_set_norm": (_st, [_vp, _fp, _fp]),
+    "nvp_boxnet_predict": (_st, [_vp, _i, _vp, _vp]),
+    "nvp_boxnet_grads": (_st, [_vp, _i, _vp, _vp, _f, _vp, _fp]),
+    "nvp_boxnet_train_step": (_st, [_vp, _i, _vp, _vp, _f, _f, _fp]),
+    "nvp_boxnet_destroy": (_st, [_vp]),
 }
 
 _lib = None

@@ -423,9 +423,46 @@ void free_plan_memory(nvp_plan *p) {
     p->pool.clear();
 }
 
+// Transfer + source arguments of harmonic n from fields[m-1] = p_m.
+SourceArgs source_args(const nvp_plan *plan, int n, const void *const *fields) {
+    const Harm &h = plan->h[n - 2];
+    SourceArgs src{};
+    src.nf = n - 1;
+    src.order = plan->order;
+    src.Nx = (int)h.g.n[0];
+    src.Nz = (int)h.g.n[2];
+    src.chunk = h.chunk;
+    const unsigned char *tb = static_cast<const unsigned char *>(plan->tables);
+    for (int m = 1; m < n; ++m) {
+        const nvp_grid &sg = m == 1 ? plan->g1 : plan->h[m - 2].g;
+        FieldArgs &fa = src.f[m - 1];
+        const HarmField &hf = h.f[m - 1];
+        fa.p = fields[m - 1];
+        fa.s0 = sg.n[1] * sg.n[2];
+        fa.s1 = sg.n[2];
+        fa.identity = hf.identity;
+        for (int ax = 0; ax < 3; ++ax) {
+            fa.b[ax] = hf.identity ? nullptr : reinterpret_cast<const int *>(tb + hf.off_b[ax]);
+            fa.w[ax] = hf.identity ? nullptr : static_cast<const void *>(tb + hf.off_w[ax]);
+        }
+    }
+    return src;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
+
+namespace nvp {
+
+// Context access for the other translation units behind the C ABI.
+int ctx_device(const nvp_ctx *c) { return c->device; }
+hipStream_t ctx_stream(const nvp_ctx *c) { return c->stream; }
+nvp_status ctx_fail(nvp_ctx *c, nvp_status s, const char *msg) { return fail(c, s, msg); }
+nvp_status ctx_hip_fail(nvp_ctx *c, const char *what, hipError_t e) { return hip_fail(c, what, e); }
+void ctx_self_cell(double kr, double ki, double h, double *re, double *im) { self_cell(kr, ki, h, re, im); }
+
+}  // namespace nvp
 
 extern "C" {
 
@@ -787,26 +824,7 @@ nvp_status nvp_execute_harmonic(nvp_plan *plan, int n, const void *const *fields
         if ((st = kernel_spectrum(ctx, plan, h.kr, h.ki, &h.g, h.M, plan->prec, h.khat, plan->B))) return st;
         h.khat_ok = true;
     }
-    SourceArgs src{};
-    src.nf = n - 1;
-    src.order = plan->order;
-    src.Nx = (int)h.g.n[0];
-    src.Nz = (int)h.g.n[2];
-    src.chunk = h.chunk;
-    const unsigned char *tb = static_cast<const unsigned char *>(plan->tables);
-    for (int m = 1; m < n; ++m) {
-        const nvp_grid &sg = m == 1 ? plan->g1 : plan->h[m - 2].g;
-        FieldArgs &fa = src.f[m - 1];
-        const HarmField &hf = h.f[m - 1];
-        fa.p = fields[m - 1];
-        fa.s0 = sg.n[1] * sg.n[2];
-        fa.s1 = sg.n[2];
-        fa.identity = hf.identity;
-        for (int ax = 0; ax < 3; ++ax) {
-            fa.b[ax] = hf.identity ? nullptr : reinterpret_cast<const int *>(tb + hf.off_b[ax]);
-            fa.w[ax] = hf.identity ? nullptr : static_cast<const void *>(tb + hf.off_w[ax]);
-        }
-    }
+    SourceArgs src = source_args(plan, n, fields);
     const double scale = h.Cn / ((double)h.M[0] * (double)h.M[1] * (double)h.M[2]);
     return convolve(ctx, plan, plan->prec, &h.g, h.M, h.khat, plan->A, plan->B, nullptr, &src, pn_dev, scale,
                     plan->use_source_kernel ? h.src_lds : 0);
@@ -823,6 +841,24 @@ nvp_status nvp_execute_cascade(nvp_plan *plan, const void *p1_dev, void *const *
         if (st) return st;
         fields[n - 1] = pn_dev[n - 2];
     }
+    return NVP_OK;
+}
+
+nvp_status nvp_source_term(nvp_plan *plan, int n, const void *const *fields, void *f_dev) {
+    if (!plan) return NVP_E_INVALID;
+    nvp_ctx *ctx = plan->ctx;
+    if (n < 2 || n > plan->n_harm || !fields || !f_dev)
+        return fail(ctx, NVP_E_INVALID, "nvp_source_term: bad argument");
+    for (int m = 1; m < n; ++m)
+        if (!fields[m - 1] || fields[m - 1] == f_dev)
+            return fail(ctx, NVP_E_INVALID, "nvp_source_term: null or aliased field");
+    const Harm &h = plan->h[n - 2];
+    if (h.src_lds <= 0)
+        return fail(ctx, NVP_E_UNSUPPORTED, "nvp_source_term: the source block of this grid pair exceeds LDS");
+    NVP_HIP(ctx, hipSetDevice(ctx->device));
+    const SourceArgs src = source_args(plan, n, fields);
+    NVP_HIP(ctx, (plan->prec == NVP_C128 ? nvp::launch_source_c128 : nvp::launch_source_c64)(
+                     src, f_dev, (int)h.g.n[1], h.src_lds, ctx->stream));
     return NVP_OK;
 }
 

@@ -241,6 +241,19 @@ class CascadePlan:
         _check(_native.lib().nvp_execute_harmonic(self.handle, n, arr, _ptr(out)), self.ctx.handle)
         return out
 
+    def source_term(self, n, fields, out=None):
+        """f_n on the grid of harmonic n from fields[m-1] = p_m, m = 1..n-1."""
+        if len(fields) != n - 1:
+            raise ValueError("harmonic %d needs %d fields" % (n, n - 1))
+        for m, f in enumerate(fields, start=1):
+            _need(f, self.dtype, self._sz(m), "p_%d" % m)
+        if out is None:
+            out = torch.empty(self.shape(n), dtype=self.dtype, device=fields[0].device)
+        _need(out, self.dtype, self._sz(n), "out")
+        arr = (ctypes.c_void_p * len(fields))(*[f.data_ptr() for f in fields])
+        _check(_native.lib().nvp_source_term(self.handle, n, arr, _ptr(out)), self.ctx.handle)
+        return out
+
     def execute(self, p1, outs=None):
         """p1 on g1 -> [p_2, ..., p_n_harm]."""
         _need(p1, self.dtype, self._sz(1), "p1")
@@ -256,6 +269,119 @@ class CascadePlan:
     def close(self):
         if self.handle:
             _native.lib().nvp_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------- truncation boxes
+
+def qbox(ctx, f, q0):
+    """Localisation boxes of f (3-D complex tensor) for thresholds q0: int64 array [len(q0)][6]."""
+    import numpy as np
+    n = tuple(f.shape)
+    if len(n) != 3:
+        raise ValueError("f must be 3-D")
+    _need(f, f.dtype, n[0] * n[1] * n[2], "f")
+    q = np.ascontiguousarray(np.asarray(q0, dtype=np.float64).reshape(-1))
+    box = np.zeros((len(q), 6), dtype=np.int64)
+    _check(_native.lib().nvp_qbox(ctx.handle, _i3(n), _ptr(f), prec_of(f.dtype), len(q),
+                                  q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  box.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), ctx.handle)
+    return box
+
+
+def box_potential(ctx, k, g, f, target, boxes):
+    """-sum over each box of K(x_target - x_j) f_j; complex128 numpy array, one value per box."""
+    import numpy as np
+    g = grid(g)
+    n = tuple(g.n)
+    _need(f, f.dtype, n[0] * n[1] * n[2], "f")
+    b = np.ascontiguousarray(np.asarray(boxes, dtype=np.int64).reshape(-1, 6))
+    out = np.zeros(2 * len(b), dtype=np.float64)
+    k = complex(k)
+    _check(_native.lib().nvp_box_potential(ctx.handle, k.real, k.imag, ctypes.byref(g), _ptr(f), prec_of(f.dtype),
+                                           _i3(target), len(b), b.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), ctx.handle)
+    return out[0::2] + 1j * out[1::2]
+
+
+# ------------------------------------------------------------- box predictor
+
+BOXNET_PARAMS = 8899
+BOXNET_IN, BOXNET_OUT = 5, 3
+
+
+class BoxNet:
+    """nvp_boxnet: the box-predictor MLP; inputs and targets are float32 CUDA tensors."""
+
+    def __init__(self, ctx, max_batch):
+        self.ctx = ctx
+        self.max_batch = int(max_batch)
+        h = ctypes.c_void_p()
+        _check(_native.lib().nvp_boxnet_create(ctx.handle, self.max_batch, ctypes.byref(h)), ctx.handle)
+        self.handle = h
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        _check(_native.lib().nvp_boxnet_set_params(self.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                   p.size), self.ctx.handle)
+
+    def get_params(self):
+        import numpy as np
+        p = np.zeros(BOXNET_PARAMS, dtype=np.float32)
+        _check(_native.lib().nvp_boxnet_get_params(self.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                   p.size), self.ctx.handle)
+        return p
+
+    def set_norm(self, mean, std):
+        import numpy as np
+        m = np.ascontiguousarray(np.asarray(mean, dtype=np.float32))
+        s = np.ascontiguousarray(np.asarray(std, dtype=np.float32))
+        _check(_native.lib().nvp_boxnet_set_norm(self.handle, m.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                 s.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), self.ctx.handle)
+
+    def _io(self, x, t=None):
+        B = x.shape[0]
+        if not 1 <= B <= self.max_batch:
+            raise ValueError("batch of %d outside 1..%d" % (B, self.max_batch))
+        _need(x, torch.float32, B * BOXNET_IN, "x")
+        if t is not None:
+            _need(t, torch.float32, B * BOXNET_OUT, "t")
+        return B
+
+    def predict(self, x, out=None):
+        B = self._io(x)
+        if out is None:
+            out = torch.empty((B, BOXNET_OUT), dtype=torch.float32, device=x.device)
+        _need(out, torch.float32, B * BOXNET_OUT, "out")
+        _check(_native.lib().nvp_boxnet_predict(self.handle, B, _ptr(x), _ptr(out)), self.ctx.handle)
+        return out
+
+    def grads(self, x, t, tau):
+        """(gradient tensor [8899], loss) without updating the parameters."""
+        B = self._io(x, t)
+        g = torch.empty(BOXNET_PARAMS, dtype=torch.float32, device=x.device)
+        loss = ctypes.c_float()
+        _check(_native.lib().nvp_boxnet_grads(self.handle, B, _ptr(x), _ptr(t), float(tau), _ptr(g),
+                                              ctypes.byref(loss)), self.ctx.handle)
+        return g, loss.value
+
+    def train_step(self, x, t, tau, lr, want_loss=True):
+        B = self._io(x, t)
+        loss = ctypes.c_float()
+        _check(_native.lib().nvp_boxnet_train_step(self.handle, B, _ptr(x), _ptr(t), float(tau), float(lr),
+                                                   ctypes.byref(loss) if want_loss else None), self.ctx.handle)
+        return loss.value if want_loss else None
+
+    def close(self):
+        if self.handle:
+            _native.lib().nvp_boxnet_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
