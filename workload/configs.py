@@ -81,3 +81,22 @@ def precision_subbox(P_f=5.0e6, n_points=4096, seed=0, side=96):
     cfg["grids"] = {n: dict(n=(side,) * 3, i_f=(half,) * 3) for n in range(2, 6)}
     cfg.pop("uniform_grids")
     return cfg
+
+
+def batch_transducers(count=64, seed=0):
+    """Seeded transducers of the batched workload: aperture radius 2-8 cm, focal length 4-16 cm,
+    0.5-1.5 MHz, surface pressure 0.2-1.5 MPa, 3-5 harmonics (uniform draws; a draw with
+    R > 0.8 l, which is no usable bowl, is drawn again).
+
+    Returns a list of dicts with keys R, l, f0, p0, n_harm.
+    """
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        R, l = rng.uniform(0.02, 0.08), rng.uniform(0.04, 0.16)
+        f0, p0, nh = rng.uniform(0.5e6, 1.5e6), rng.uniform(0.2e6, 1.5e6), int(rng.integers(3, 6))
+        if R > 0.8 * l:
+            continue
+        out.append(dict(R=R, l=l, f0=f0, p0=p0, n_harm=nh))
+    return out
