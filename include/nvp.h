@@ -226,6 +226,58 @@ nvp_status nvp_boxnet_train_step(nvp_boxnet *bn, int batch, const float *x_dev, 
                                  float lr, float *loss_host);
 nvp_status nvp_boxnet_destroy(nvp_boxnet *bn);
 
+/* ---- autotuning and batches ------------------------------------------------ */
+
+/* Times the launch choices of every harmonic of the plan and keeps the
+ * fastest: the column tile of the x and the y passes (default or half), the
+ * pencil quads per z-pass workgroup (1 or 2) and the source build (its own
+ * tiled kernel or fused into the x pass).  Each choice is timed over reps
+ * executions on zero-filled fields (the kernels have no data-dependent
+ * control flow).  cache_path (optional): a text file of earlier choices,
+ * keyed by device, precision, transfer order and shapes; entries found there
+ * are used without timing, new ones are written back.  Waits for the device.
+ * Results of a tuned plan differ from the default only by the rounding order
+ * of the source build. */
+nvp_status nvp_plan_autotune(nvp_plan *plan, const char *cache_path, int reps);
+/* The launch choices of harmonic n: choice[4] = x tile, y tile (0 default,
+ * 1 half), z quads (0 default, 1, 2), source (-1 default, 1 tiled, 0 fused). */
+nvp_status nvp_plan_get_tuning(const nvp_plan *plan, int n, int *choice);
+
+/* One problem of a batch: the arguments of nvp_plan_cascade. */
+typedef struct {
+    nvp_medium med;
+    double f0;
+    int n_harm;
+    nvp_grid g1;
+    const nvp_grid *gn; /* n_harm - 1 grids, read during nvp_batch_create only */
+} nvp_problem;
+
+typedef struct nvp_batch nvp_batch;
+
+/* Many cascades (e.g. one per transducer) planned together.  Outputs are
+ * numbered problem by problem: problem i writes p_2..p_{n_harm} to output
+ * slots off_i .. off_i + n_harm - 2, off_i = sum over earlier problems of
+ * (n_harm - 1); nvp_batch_outputs gives the total.  Each problem keeps its
+ * own plan (workspace and kernel spectra). */
+nvp_status nvp_batch_create(nvp_ctx *ctx, int count, const nvp_problem *problems, nvp_prec prec,
+                            int transfer_order, nvp_batch **out);
+nvp_status nvp_batch_outputs(const nvp_batch *batch, int64_t *n_out);
+/* enable != 0 (default): from the second execution on, the whole batch runs as
+ * one HIP graph in which problem i is recorded on branch i mod branches
+ * (1..16, default 4) so that independent problems may overlap.  The graph is
+ * recorded again whenever the buffer pointers change.  enable = 0: every
+ * execution launches the kernels one by one on the context stream. */
+nvp_status nvp_batch_set_graph(nvp_batch *batch, int enable, int branches);
+/* nvp_plan_autotune for every problem, sharing one cache (identical shapes
+ * are timed once). */
+nvp_status nvp_batch_autotune(nvp_batch *batch, const char *cache_path, int reps);
+/* p1_dev[i]: p_1 of problem i; pn_dev[slot]: outputs as numbered above.  The
+ * first execution (and every execution with the kernel cache of some problem
+ * off) runs eagerly and fills the kernel-spectrum caches; later ones launch
+ * the graph.  Enqueued on the context stream. */
+nvp_status nvp_batch_execute(nvp_batch *batch, const void *const *p1_dev, void *const *pn_dev);
+nvp_status nvp_batch_destroy(nvp_batch *batch);
+
 /* ---- timing of the plan's kernels ---------------------------------------- */
 
 /* Kinds of kernel timed by nvp_plan_get_timing. */

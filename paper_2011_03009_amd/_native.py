@@ -15,6 +15,11 @@ class Grid(ctypes.Structure):
     _fields_ = [("origin", ctypes.c_double * 3), ("h", ctypes.c_double), ("n", ctypes.c_int64 * 3)]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("med", Medium), ("f0", ctypes.c_double), ("n_harm", ctypes.c_int), ("g1", Grid),
+                ("gn", ctypes.POINTER(Grid))]
+
+
 # Every symbol the header declares, with (restype, argtypes).
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
@@ -50,6 +55,14 @@ SIGNATURES = {
     "nvp_plan_set_timing": (_st, [_vp, _i]),
     "nvp_plan_get_timing": (_st, [_vp, _dp, _i64p, _i]),
     "nvp_source_term": (_st, [_vp, _i, ctypes.POINTER(_vp), _vp]),
+    "nvp_plan_autotune": (_st, [_vp, ctypes.c_char_p, _i]),
+    "nvp_plan_get_tuning": (_st, [_vp, _i, ctypes.POINTER(_i)]),
+    "nvp_batch_create": (_st, [_vp, _i, ctypes.POINTER(Problem), _i, _i, ctypes.POINTER(_vp)]),
+    "nvp_batch_outputs": (_st, [_vp, _i64p]),
+    "nvp_batch_set_graph": (_st, [_vp, _i, _i]),
+    "nvp_batch_autotune": (_st, [_vp, ctypes.c_char_p, _i]),
+    "nvp_batch_execute": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "nvp_batch_destroy": (_st, [_vp]),
     "nvp_qbox": (_st, [_vp, _i64p, _vp, _i, _i, _dp, _i64p]),
     "nvp_box_potential": (_st, [_vp, _d, _d, ctypes.POINTER(Grid), _vp, _i, _i64p, _i, _i64p, _dp]),
     "nvp_boxnet_create": (_st, [_vp, _i, ctypes.POINTER(_vp)]),

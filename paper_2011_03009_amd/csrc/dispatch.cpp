@@ -40,15 +40,15 @@ hipError_t launch_xsrc_c128(int L, const SourceArgs &a, const void *tw, hipStrea
 }
 
 hipError_t launch_zconv_c64(int L, void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw,
-                            hipStream_t s) {
-#define X(n) case n: return zconv_impl<float, n>(buf, khat, Mx, My, Nz, tw, s);
+                            int quads, hipStream_t s) {
+#define X(n) case n: return zconv_impl<float, n>(buf, khat, Mx, My, Nz, tw, quads, s);
     NVP_DISPATCH()
 #undef X
 }
 
 hipError_t launch_zconv_c128(int L, void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw,
-                             hipStream_t s) {
-#define X(n) case n: return zconv_impl<double, n>(buf, khat, Mx, My, Nz, tw, s);
+                             int quads, hipStream_t s) {
+#define X(n) case n: return zconv_impl<double, n>(buf, khat, Mx, My, Nz, tw, quads, s);
     NVP_DISPATCH()
 #undef X
 }

@@ -10,7 +10,7 @@ namespace nvp {
 template <typename R, typename Rout, int L> hipError_t strided_impl(const StridedArgs &, const void *, hipStream_t);
 template <typename R, int L> hipError_t xsrc_impl(const SourceArgs &, const void *, hipStream_t);
 template <typename R, int L>
-hipError_t zconv_impl(void *, const void *, int64_t, int64_t, int, const void *, hipStream_t);
+hipError_t zconv_impl(void *, const void *, int64_t, int64_t, int, const void *, int, hipStream_t);
 
 template <int L>
 hipError_t kz_impl(double2 *, const int64_t[3], const int64_t[3], double, double, double, double, double, const void *,

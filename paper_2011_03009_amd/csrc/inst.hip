@@ -12,8 +12,9 @@ template hipError_t strided_impl<double, double, NVP_L>(const StridedArgs &, con
 template hipError_t strided_impl<double, float, NVP_L>(const StridedArgs &, const void *, hipStream_t);
 template hipError_t xsrc_impl<float, NVP_L>(const SourceArgs &, const void *, hipStream_t);
 template hipError_t xsrc_impl<double, NVP_L>(const SourceArgs &, const void *, hipStream_t);
-template hipError_t zconv_impl<float, NVP_L>(void *, const void *, int64_t, int64_t, int, const void *, hipStream_t);
-template hipError_t zconv_impl<double, NVP_L>(void *, const void *, int64_t, int64_t, int, const void *,
+template hipError_t zconv_impl<float, NVP_L>(void *, const void *, int64_t, int64_t, int, const void *, int,
+                                             hipStream_t);
+template hipError_t zconv_impl<double, NVP_L>(void *, const void *, int64_t, int64_t, int, const void *, int,
                                               hipStream_t);
 
 template hipError_t kz_impl<NVP_L>(double2 *, const int64_t[3], const int64_t[3], double, double, double, double,

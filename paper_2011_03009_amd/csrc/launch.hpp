@@ -35,6 +35,7 @@ struct StridedArgs {
     double scale;
     int64_t inner, outer;
     int sign;
+    int tile;  // 0: default columns per workgroup, 1: half as many (not for mirror or mixed precision)
 };
 
 // Field of the fused source build (see LdSource).
@@ -73,10 +74,11 @@ hipError_t launch_xsrc_c128(int L, const SourceArgs &a, const void *tw, hipStrea
 hipError_t launch_source_c64(const SourceArgs &a, void *out, int Ny, int64_t lds_elems, hipStream_t s);
 hipError_t launch_source_c128(const SourceArgs &a, void *out, int Ny, int64_t lds_elems, hipStream_t s);
 
+// quads: pencil quads per workgroup (0 default, 1 or 2).
 hipError_t launch_zconv_c64(int L, void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw,
-                            hipStream_t s);
+                            int quads, hipStream_t s);
 hipError_t launch_zconv_c128(int L, void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw,
-                             hipStream_t s);
+                             int quads, hipStream_t s);
 
 // Kernel tabulation fused with the first (z) FP64 pass of the kernel spectrum;
 // writes the octant [Hx][Hy][Hz] at `out`.

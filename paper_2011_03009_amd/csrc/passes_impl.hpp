@@ -37,9 +37,8 @@ template <typename R, int L, int T> constexpr size_t strided_lds() {
            sizeof(cx<R>);
 }
 
-template <typename R, typename Rout, int L, int SG, bool SC, bool MIRROR>
+template <typename R, typename Rout, int L, int SG, bool SC, bool MIRROR, int T = strided_cols<R>(L)>
 hipError_t strided_v(const StridedArgs &a, const void *tw, hipStream_t s) {
-    constexpr int T = strided_cols<R>(L);
     using Ld = LdPlain<R, L>;
     using St = StPlain<R, Rout, SC>;
     Ld ld{static_cast<const cx<R> *>(a.in), a.in_os, a.in_ms, a.n_in, a.mirror};
@@ -54,8 +53,21 @@ hipError_t strided_v(const StridedArgs &a, const void *tw, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Variants in use: forward, inverse, inverse with the epilogue scale, and
-// (FP64 only) forward on mirrored even sequences.
+// Half the default column count: the tile-width alternative of the autotuner.
+template <typename R> constexpr int strided_cols_half(int L) {
+    const int t = strided_cols<R>(L) / 2;
+    return t < 4 ? 4 : t;
+}
+
+template <typename R, typename Rout, int L, int SG, bool SC>
+hipError_t strided_tiles(const StridedArgs &a, const void *tw, hipStream_t s) {
+    if (a.tile == 1) return strided_v<R, Rout, L, SG, SC, false, strided_cols_half<R>(L)>(a, tw, s);
+    return strided_v<R, Rout, L, SG, SC, false>(a, tw, s);
+}
+
+// Variants in use: forward, inverse, inverse with the epilogue scale (each at
+// the default or half tile width), and (FP64 only) forward on mirrored even
+// sequences.
 template <typename R, typename Rout, int L>
 hipError_t strided_impl(const StridedArgs &a, const void *tw, hipStream_t s) {
     if (a.mirror) {
@@ -65,9 +77,9 @@ hipError_t strided_impl(const StridedArgs &a, const void *tw, hipStream_t s) {
         return hipErrorInvalidValue;
     }
     if constexpr (sizeof(R) == sizeof(Rout)) {
-        if (a.sign < 0 && a.scale == 1.0) return strided_v<R, Rout, L, -1, false, false>(a, tw, s);
-        if (a.sign > 0 && a.scale == 1.0) return strided_v<R, Rout, L, 1, false, false>(a, tw, s);
-        if (a.sign > 0) return strided_v<R, Rout, L, 1, true, false>(a, tw, s);
+        if (a.sign < 0 && a.scale == 1.0) return strided_tiles<R, Rout, L, -1, false>(a, tw, s);
+        if (a.sign > 0 && a.scale == 1.0) return strided_tiles<R, Rout, L, 1, false>(a, tw, s);
+        if (a.sign > 0) return strided_tiles<R, Rout, L, 1, true>(a, tw, s);
     }
     return hipErrorInvalidValue;
 }
@@ -129,11 +141,14 @@ hipError_t zconv_qw(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz,
     return hipGetLastError();
 }
 
+// quads: pencil quads per workgroup, 0 for the default (2 when that keeps the
+// workgroup within 256 threads and 80 KiB of LDS, else 1), or 1 / 2 forced
+// (2 falls back to 1 where it does not fit).
 template <typename R, int L>
-hipError_t zconv_impl(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, hipStream_t s) {
-    // quads per workgroup: up to 256 threads and 80 KiB of LDS
+hipError_t zconv_impl(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, int quads,
+                      hipStream_t s) {
     constexpr int QW = (4 * plan_threads(L) <= 128 && 8 * slot_len<R>(L) * (int)sizeof(cx<R>) <= 81920) ? 2 : 1;
-    if (zconv_quads_override() == 1) return zconv_qw<R, L, 1>(buf, khat, Mx, My, Nz, tw, s);
+    if (quads == 1 || zconv_quads_override() == 1) return zconv_qw<R, L, 1>(buf, khat, Mx, My, Nz, tw, s);
     return zconv_qw<R, L, QW>(buf, khat, Mx, My, Nz, tw, s);
 }
 

@@ -6,10 +6,14 @@
 // plain IEEE double operations in the order written here.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -58,7 +62,15 @@ struct HarmField {
     size_t off_b[3]{}, off_w[3]{};  // byte offsets in the plan's table blob
 };
 
+// Launch choices of one harmonic (the autotuner's search space).
+struct Tune {
+    int x_tile = 0, y_tile = 0;  // strided passes: 0 default columns per workgroup, 1 half
+    int quads = 0;               // z pass: pencil quads per workgroup (0 default, 1, 2)
+    int src = -1;                // source build: -1 default, 1 its own tiled kernel, 0 fused into the x pass
+};
+
 struct Harm {
+    Tune tune;
     int n = 0;
     nvp_grid g{};
     int64_t M[3]{};
@@ -299,7 +311,7 @@ size_t kscratch_bytes(const int64_t M[3]) { return (size_t)(M[0] / 2 + 1) * (M[1
 // y inv, x inv with `scale` into u.
 nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid *g, const int64_t M[3],
                     const void *khat, void *A, void *B, const void *f, const SourceArgs *src, void *u,
-                    double scale, int64_t src_lds = 0) {
+                    double scale, int64_t src_lds = 0, const Tune &tn = Tune{}) {
     const int64_t Nx = g->n[0], Ny = g->n[1], Nz = g->n[2];
     const int64_t Mx = M[0], My = M[1], Mz = M[2];
     const bool dbl = prec == NVP_C128;
@@ -331,7 +343,7 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
             StridedArgs a{};
             a.in = f; a.in_os = 0; a.in_ms = Ny * Nz; a.n_in = (int)Nx;
             a.out = A; a.out_os = 0; a.out_ms = Ny * Nz; a.n_out = (int)Mx;
-            a.scale = 1.0; a.inner = Ny * Nz; a.outer = 1; a.sign = -1;
+            a.scale = 1.0; a.inner = Ny * Nz; a.outer = 1; a.sign = -1; a.tile = tn.x_tile;
             NVP_HIP(ctx, strided((int)Mx, a, twx, ctx->stream));
         }
     }
@@ -340,20 +352,20 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
         StridedArgs a{};
         a.in = A; a.in_os = Ny * Nz; a.in_ms = Nz; a.n_in = (int)Ny;
         a.out = B; a.out_os = My * Nz; a.out_ms = Nz; a.n_out = (int)My;
-        a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = -1;
+        a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = -1; a.tile = tn.y_tile;
         NVP_HIP(ctx, strided((int)My, a, twy, ctx->stream));
     }
     {
         Timer t(timed, NVP_T_ZCONV);
         NVP_HIP(ctx, (dbl ? nvp::launch_zconv_c128 : nvp::launch_zconv_c64)((int)Mz, B, khat, Mx, My, (int)Nz, twz,
-                                                                          ctx->stream));
+                                                                          tn.quads, ctx->stream));
     }
     {
         Timer t(timed, NVP_T_YINV);
         StridedArgs a{};
         a.in = B; a.in_os = My * Nz; a.in_ms = Nz; a.n_in = (int)My;
         a.out = A; a.out_os = Ny * Nz; a.out_ms = Nz; a.n_out = (int)Ny;
-        a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = 1;
+        a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = 1; a.tile = tn.y_tile;
         NVP_HIP(ctx, strided((int)My, a, twy, ctx->stream));
     }
     {
@@ -361,7 +373,7 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
         StridedArgs a{};
         a.in = A; a.in_os = 0; a.in_ms = Ny * Nz; a.n_in = (int)Mx;
         a.out = u; a.out_os = 0; a.out_ms = Ny * Nz; a.n_out = (int)Nx;
-        a.scale = scale; a.inner = Ny * Nz; a.outer = 1; a.sign = 1;
+        a.scale = scale; a.inner = Ny * Nz; a.outer = 1; a.sign = 1; a.tile = tn.x_tile;
         NVP_HIP(ctx, strided((int)Mx, a, twx, ctx->stream));
     }
     return NVP_OK;
@@ -826,8 +838,9 @@ nvp_status nvp_execute_harmonic(nvp_plan *plan, int n, const void *const *fields
     }
     SourceArgs src = source_args(plan, n, fields);
     const double scale = h.Cn / ((double)h.M[0] * (double)h.M[1] * (double)h.M[2]);
+    const bool tiled_src = plan->use_source_kernel && h.tune.src != 0;
     return convolve(ctx, plan, plan->prec, &h.g, h.M, h.khat, plan->A, plan->B, nullptr, &src, pn_dev, scale,
-                    plan->use_source_kernel ? h.src_lds : 0);
+                    tiled_src ? h.src_lds : 0, h.tune);
 }
 
 nvp_status nvp_execute_cascade(nvp_plan *plan, const void *p1_dev, void *const *pn_dev) {
@@ -896,6 +909,371 @@ nvp_status nvp_plan_get_timing(nvp_plan *plan, double *ms, int64_t *count, int n
         plan->pool.push_back(e.b);
     }
     plan->events.clear();
+    return NVP_OK;
+}
+
+
+// ------------------------------------------------------------------ autotuning
+
+}  // extern "C"
+
+namespace {
+
+// Tuning-cache key of one harmonic: device, precision, transfer order and the
+// shapes that decide the launches (target grid, circulant, source grids).
+std::string tune_key(const nvp_plan *p, int n, const char *arch) {
+    const Harm &h = p->h[n - 2];
+    std::ostringstream k;
+    k << arch << "|c" << (p->prec == NVP_C64 ? 64 : 128) << "|o" << p->order << "|N" << h.g.n[0] << "x" << h.g.n[1]
+      << "x" << h.g.n[2] << "|M" << h.M[0] << "x" << h.M[1] << "x" << h.M[2] << "|S";
+    for (int m = 1; m < n; ++m) {
+        const nvp_grid &sg = m == 1 ? p->g1 : p->h[m - 2].g;
+        k << (h.f[m - 1].identity ? "=" : "") << sg.n[0] << "x" << sg.n[1] << "x" << sg.n[2] << ";";
+    }
+    return k.str();
+}
+
+void read_tune_cache(const char *path, std::map<std::string, Tune> &out) {
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+        std::istringstream ls(line);
+        std::string key;
+        Tune t;
+        if (ls >> key >> t.x_tile >> t.y_tile >> t.quads >> t.src) out[key] = t;
+    }
+}
+
+bool write_tune_cache(const char *path, const std::map<std::string, Tune> &m) {
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream o(tmp);
+        if (!o) return false;
+        for (const auto &kv : m)
+            o << kv.first << " " << kv.second.x_tile << " " << kv.second.y_tile << " " << kv.second.quads << " "
+              << kv.second.src << "\n";
+        if (!o) return false;
+    }
+    return std::rename(tmp.c_str(), path) == 0;
+}
+
+struct DevMem {
+    std::vector<void *> p;
+    ~DevMem() {
+        for (void *q : p) (void)hipFree(q);
+    }
+};
+
+// Times the launch choices of every harmonic of `plan` on zero-filled fields
+// (the kernels have no data-dependent control flow) and keeps the fastest.
+// Choices found in `cache` are taken without timing; new ones are added.
+nvp_status autotune_plan(nvp_plan *plan, std::map<std::string, Tune> &cache, int reps) {
+    nvp_ctx *ctx = plan->ctx;
+    NVP_HIP(ctx, hipSetDevice(ctx->device));
+    hipDeviceProp_t prop;
+    NVP_HIP(ctx, hipGetDeviceProperties(&prop, ctx->device));
+    const size_t cs = csize(plan->prec);
+    DevMem mem;
+    std::vector<const void *> fields(plan->n_harm);
+    size_t out_elems = 1;
+    for (int m = 1; m <= plan->n_harm; ++m) {
+        const nvp_grid &g = m == 1 ? plan->g1 : plan->h[m - 2].g;
+        const size_t elems = (size_t)g.n[0] * g.n[1] * g.n[2];
+        if (m == plan->n_harm) {
+            out_elems = std::max(out_elems, elems);
+            break;
+        }
+        void *q = nullptr;
+        NVP_HIP(ctx, hipMalloc(&q, elems * cs));
+        mem.p.push_back(q);
+        NVP_HIP(ctx, hipMemsetAsync(q, 0, elems * cs, ctx->stream));
+        fields[m - 1] = q;
+        if (m >= 2) out_elems = std::max(out_elems, elems);
+    }
+    void *out = nullptr;
+    NVP_HIP(ctx, hipMalloc(&out, out_elems * cs));
+    mem.p.push_back(out);
+    hipEvent_t e0, e1;
+    NVP_HIP(ctx, hipEventCreate(&e0));
+    NVP_HIP(ctx, hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev{e0, e1};
+    const bool timing = plan->timing;
+    plan->timing = false;
+    nvp_status st = NVP_OK;
+    for (int n = 2; n <= plan->n_harm && st == NVP_OK; ++n) {
+        Harm &h = plan->h[n - 2];
+        const std::string key = tune_key(plan, n, prop.gcnArchName);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            h.tune = it->second;
+            continue;
+        }
+        float best = 1e30f;
+        Tune best_t{};
+        const int src_opts = (plan->use_source_kernel && h.src_lds > 0) ? 2 : 1;
+        for (int xt = 0; xt < 2 && st == NVP_OK; ++xt)
+            for (int yt = 0; yt < 2 && st == NVP_OK; ++yt)
+                for (int q = 1; q <= 2 && st == NVP_OK; ++q)
+                    for (int so = 0; so < src_opts && st == NVP_OK; ++so) {
+                        Tune t;
+                        t.x_tile = xt;
+                        t.y_tile = yt;
+                        t.quads = q;
+                        t.src = src_opts == 2 ? 1 - so : 0;
+                        h.tune = t;
+                        if ((st = nvp_execute_harmonic(plan, n, fields.data(), out))) break;  // warm-up
+                        if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = NVP_E_HIP; break; }
+                        for (int r = 0; r < reps && st == NVP_OK; ++r) st = nvp_execute_harmonic(plan, n, fields.data(), out);
+                        if (st) break;
+                        float ms = 0;
+                        if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                            st = hip_fail(ctx, "autotune timing", hipGetLastError());
+                            break;
+                        }
+                        if (ms < best) {
+                            best = ms;
+                            best_t = t;
+                        }
+                    }
+        h.tune = best_t;
+        cache[key] = best_t;
+    }
+    plan->timing = timing;
+    if (st == NVP_OK) NVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return st;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ batches
+
+struct nvp_batch {
+    nvp_ctx *ctx = nullptr;
+    std::vector<nvp_plan *> plans;
+    std::vector<int64_t> off;  // first output slot of each problem
+    int64_t n_out = 0;
+    bool graph = true;
+    int branches = 4;
+    hipStream_t cap = nullptr;       // stream the graph is recorded from (the context stream may be the null stream)
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;  // fork, then one join event per branch
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    std::vector<const void *> cap_in;
+    std::vector<void *> cap_out;
+    bool warm = false;
+};
+
+namespace {
+
+void drop_graph(nvp_batch *b) {
+    if (b->ge) (void)hipGraphExecDestroy(b->ge);
+    if (b->g) (void)hipGraphDestroy(b->g);
+    b->ge = nullptr;
+    b->g = nullptr;
+    b->cap_in.clear();
+    b->cap_out.clear();
+}
+
+void free_batch(nvp_batch *b) {
+    drop_graph(b);
+    for (auto *p : b->plans) nvp_plan_destroy(p);
+    for (auto s : b->streams) (void)hipStreamDestroy(s);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    b->cap = nullptr;
+    for (auto e : b->events) (void)hipEventDestroy(e);
+    b->plans.clear();
+    b->streams.clear();
+    b->events.clear();
+}
+
+nvp_status run_eager(nvp_batch *b, const void *const *p1, void *const *pn) {
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+        nvp_status st = nvp_execute_cascade(b->plans[i], p1[i], pn + b->off[i]);
+        if (st) return st;
+    }
+    return NVP_OK;
+}
+
+// Records every problem's cascade into one graph: problem i on branch
+// i mod branches, each branch a stream forked from and joined back into the
+// recording stream, so independent problems may run concurrently.
+nvp_status capture(nvp_batch *b, const void *const *p1, void *const *pn) {
+    nvp_ctx *ctx = b->ctx;
+    const int S = std::min<int>(b->branches, (int)b->plans.size());
+    if (!b->cap) NVP_HIP(ctx, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    while ((int)b->streams.size() < S) {
+        hipStream_t s;
+        NVP_HIP(ctx, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        b->streams.push_back(s);
+    }
+    while ((int)b->events.size() < S + 1) {
+        hipEvent_t e;
+        NVP_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        b->events.push_back(e);
+    }
+    const hipStream_t user = ctx->stream, origin = b->cap;
+    NVP_HIP(ctx, hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
+    nvp_status st = NVP_OK;
+    hipError_t e = hipEventRecord(b->events[0], origin);
+    for (int s = 0; s < S && e == hipSuccess; ++s) e = hipStreamWaitEvent(b->streams[s], b->events[0], 0);
+    if (e != hipSuccess) st = hip_fail(ctx, "batch capture fork", e);
+    for (size_t i = 0; i < b->plans.size() && st == NVP_OK; ++i) {
+        ctx->stream = b->streams[i % S];
+        st = nvp_execute_cascade(b->plans[i], p1[i], pn + b->off[i]);
+        ctx->stream = user;
+    }
+    for (int s = 0; s < S && st == NVP_OK; ++s) {
+        e = hipEventRecord(b->events[s + 1], b->streams[s]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(origin, b->events[s + 1], 0);
+        if (e != hipSuccess) st = hip_fail(ctx, "batch capture join", e);
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(origin, &g);
+    if (st == NVP_OK && e != hipSuccess) st = hip_fail(ctx, "hipStreamEndCapture", e);
+    if (st != NVP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(ctx, "hipGraphInstantiate", e);
+    }
+    b->g = g;
+    b->ge = ge;
+    b->cap_in.assign(p1, p1 + b->plans.size());
+    b->cap_out.assign(pn, pn + b->n_out);
+    return NVP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nvp_status nvp_plan_autotune(nvp_plan *plan, const char *cache_path, int reps) {
+    if (!plan) return NVP_E_INVALID;
+    if (reps < 1 || reps > 100) return fail(plan->ctx, NVP_E_INVALID, "nvp_plan_autotune: reps out of range");
+    std::map<std::string, Tune> cache;
+    if (cache_path) read_tune_cache(cache_path, cache);
+    nvp_status st = autotune_plan(plan, cache, reps);
+    if (st == NVP_OK && cache_path && !write_tune_cache(cache_path, cache))
+        return fail(plan->ctx, NVP_E_INVALID, std::string("nvp_plan_autotune: cannot write ") + cache_path);
+    return st;
+}
+
+nvp_status nvp_plan_get_tuning(const nvp_plan *plan, int n, int *choice) {
+    if (!plan || !choice || n < 2 || n > plan->n_harm) return NVP_E_INVALID;
+    const Tune &t = plan->h[n - 2].tune;
+    choice[0] = t.x_tile;
+    choice[1] = t.y_tile;
+    choice[2] = t.quads;
+    choice[3] = t.src;
+    return NVP_OK;
+}
+
+nvp_status nvp_batch_create(nvp_ctx *ctx, int count, const nvp_problem *problems, nvp_prec prec, int transfer_order,
+                            nvp_batch **out) {
+    if (!ctx) return NVP_E_INVALID;
+    if (!out || !problems || count < 1) return fail(ctx, NVP_E_INVALID, "nvp_batch_create: bad argument");
+    *out = nullptr;
+    nvp_batch *b = new (std::nothrow) nvp_batch;
+    if (!b) return fail(ctx, NVP_E_NOMEM, "batch allocation");
+    b->ctx = ctx;
+    for (int i = 0; i < count; ++i) {
+        const nvp_problem &pr = problems[i];
+        nvp_plan *p = nullptr;
+        nvp_status st = nvp_plan_cascade(ctx, &pr.med, pr.f0, pr.n_harm, &pr.g1, pr.gn, prec, transfer_order, &p);
+        if (st) {
+            const std::string msg = "problem " + std::to_string(i) + ": " + ctx->err;
+            free_batch(b);
+            delete b;
+            return fail(ctx, st, msg);
+        }
+        b->plans.push_back(p);
+        b->off.push_back(b->n_out);
+        b->n_out += pr.n_harm - 1;
+    }
+    *out = b;
+    return NVP_OK;
+}
+
+nvp_status nvp_batch_outputs(const nvp_batch *b, int64_t *n_out) {
+    if (!b || !n_out) return NVP_E_INVALID;
+    *n_out = b->n_out;
+    return NVP_OK;
+}
+
+nvp_status nvp_batch_set_graph(nvp_batch *b, int enable, int branches) {
+    if (!b) return NVP_E_INVALID;
+    if (branches < 1 || branches > 16) return fail(b->ctx, NVP_E_INVALID, "nvp_batch_set_graph: branches not in 1..16");
+    if ((enable != 0) != b->graph || branches != b->branches) drop_graph(b);
+    b->graph = enable != 0;
+    b->branches = branches;
+    return NVP_OK;
+}
+
+nvp_status nvp_batch_autotune(nvp_batch *b, const char *cache_path, int reps) {
+    if (!b) return NVP_E_INVALID;
+    if (reps < 1 || reps > 100) return fail(b->ctx, NVP_E_INVALID, "nvp_batch_autotune: reps out of range");
+    std::map<std::string, Tune> cache;
+    if (cache_path) read_tune_cache(cache_path, cache);
+    for (auto *p : b->plans) {
+        nvp_status st = autotune_plan(p, cache, reps);
+        if (st) return st;
+    }
+    drop_graph(b);  // launch choices changed
+    if (cache_path && !write_tune_cache(cache_path, cache))
+        return fail(b->ctx, NVP_E_INVALID, std::string("nvp_batch_autotune: cannot write ") + cache_path);
+    return NVP_OK;
+}
+
+nvp_status nvp_batch_execute(nvp_batch *b, const void *const *p1_dev, void *const *pn_dev) {
+    if (!b) return NVP_E_INVALID;
+    nvp_ctx *ctx = b->ctx;
+    if (!p1_dev || !pn_dev) return fail(ctx, NVP_E_INVALID, "nvp_batch_execute: null buffer list");
+    for (size_t i = 0; i < b->plans.size(); ++i)
+        if (!p1_dev[i]) return fail(ctx, NVP_E_INVALID, "nvp_batch_execute: null p1");
+    for (int64_t i = 0; i < b->n_out; ++i)
+        if (!pn_dev[i]) return fail(ctx, NVP_E_INVALID, "nvp_batch_execute: null output");
+    NVP_HIP(ctx, hipSetDevice(ctx->device));
+    if (!b->graph || !b->warm) {
+        // eager: also the first run of a graph batch, which computes and caches every
+        // kernel spectrum and twiddle table so that the captured graph holds the
+        // convolutions only
+        nvp_status st = run_eager(b, p1_dev, pn_dev);
+        if (st) return st;
+        for (auto *p : b->plans)
+            for (auto &h : p->h)
+                if (!h.khat_ok) return NVP_OK;  // kernel cache off: stay eager
+        b->warm = true;
+        return NVP_OK;
+    }
+    const bool same = b->ge && std::equal(b->cap_in.begin(), b->cap_in.end(), p1_dev) &&
+                      std::equal(b->cap_out.begin(), b->cap_out.end(), pn_dev);
+    if (!same) {
+        drop_graph(b);
+        nvp_status st = capture(b, p1_dev, pn_dev);
+        if (st) return st;
+    }
+    NVP_HIP(ctx, hipGraphLaunch(b->ge, ctx->stream));
+    return NVP_OK;
+}
+
+nvp_status nvp_batch_destroy(nvp_batch *b) {
+    if (!b) return NVP_E_INVALID;
+    (void)hipSetDevice(b->ctx->device);
+    (void)hipStreamSynchronize(b->ctx->stream);
+    free_batch(b);
+    delete b;
     return NVP_OK;
 }
 

@@ -11,7 +11,7 @@ import ctypes
 import torch
 
 from . import _native
-from ._native import Grid, Medium
+from ._native import Grid, Medium, Problem
 
 NVP_C64, NVP_C128 = 0, 1
 TIMING_KINDS = ("ktab", "kfft", "xfwd", "yfwd", "zconv", "yinv", "xinv", "src")
@@ -254,6 +254,16 @@ class CascadePlan:
         _check(_native.lib().nvp_source_term(self.handle, n, arr, _ptr(out)), self.ctx.handle)
         return out
 
+    def autotune(self, cache_path=None, reps=3):
+        """Time the launch choices of each harmonic and keep the fastest (optionally through a cache file)."""
+        _check(_native.lib().nvp_plan_autotune(self.handle, cache_path.encode() if cache_path else None, reps),
+               self.ctx.handle)
+
+    def tuning(self, n):
+        c = (ctypes.c_int * 4)()
+        _check(_native.lib().nvp_plan_get_tuning(self.handle, n, c))
+        return dict(x_tile=c[0], y_tile=c[1], quads=c[2], src=c[3])
+
     def execute(self, p1, outs=None):
         """p1 on g1 -> [p_2, ..., p_n_harm]."""
         _need(p1, self.dtype, self._sz(1), "p1")
@@ -269,6 +279,66 @@ class CascadePlan:
     def close(self):
         if self.handle:
             _native.lib().nvp_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """nvp_batch: many cascades executed together (as one HIP graph from the second execution on)."""
+
+    def __init__(self, ctx, problems, prec=NVP_C64, order=1):
+        """problems: list of dicts with med, f0, g1, grids (the grids of p_2..p_n)."""
+        self.ctx = ctx
+        self.prec = prec
+        self.dtype = _DT[prec]
+        self._gn = []
+        arr = (Problem * len(problems))()
+        self.shapes = []
+        for i, pr in enumerate(problems):
+            gn = (Grid * len(pr["grids"]))(*[grid(g) for g in pr["grids"]])
+            self._gn.append(gn)
+            g1 = grid(pr["g1"])
+            arr[i] = Problem(medium(pr["med"]), float(pr["f0"]), len(pr["grids"]) + 1, g1,
+                             ctypes.cast(gn, ctypes.POINTER(Grid)))
+            self.shapes.append([tuple(g1.n)] + [tuple(g.n) for g in gn])
+        h = ctypes.c_void_p()
+        _check(_native.lib().nvp_batch_create(ctx.handle, len(problems), arr, prec, order, ctypes.byref(h)),
+               ctx.handle)
+        self.handle = h
+
+    def set_graph(self, enable, branches=4):
+        _check(_native.lib().nvp_batch_set_graph(self.handle, int(bool(enable)), branches), self.ctx.handle)
+
+    def autotune(self, cache_path=None, reps=3):
+        _check(_native.lib().nvp_batch_autotune(self.handle, cache_path.encode() if cache_path else None, reps),
+               self.ctx.handle)
+
+    def outputs(self, device="cuda"):
+        """Freshly allocated outputs: per problem, [p_2, ..., p_n]."""
+        return [[torch.empty(s, dtype=self.dtype, device=device) for s in sh[1:]] for sh in self.shapes]
+
+    def execute(self, p1s, outs):
+        """p1s[i]: p_1 of problem i; outs[i]: its [p_2, ..., p_n] (written)."""
+        ins, flat = [], []
+        for i, sh in enumerate(self.shapes):
+            _need(p1s[i], self.dtype, sh[0][0] * sh[0][1] * sh[0][2], "p1 of problem %d" % i)
+            ins.append(p1s[i].data_ptr())
+            for j, s in enumerate(sh[1:]):
+                _need(outs[i][j], self.dtype, s[0] * s[1] * s[2], "output %d of problem %d" % (j, i))
+                flat.append(outs[i][j].data_ptr())
+        a = (ctypes.c_void_p * len(ins))(*ins)
+        b = (ctypes.c_void_p * len(flat))(*flat)
+        _check(_native.lib().nvp_batch_execute(self.handle, a, b), self.ctx.handle)
+        return outs
+
+    def close(self):
+        if self.handle:
+            _native.lib().nvp_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
