@@ -92,31 +92,106 @@ def time_steps(torch, plan, p1, outs, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
-def cpu_baseline(cfg, g1_p, gn_p, p1_dev, budget_s):
-    """The FP64 oracle on a bounded sample: p2 at a set of voxels of its 256^3 grid."""
+def cpu_baseline(cfg, g1_p, gn_p, p1_dev, budget_s, order):
+    """The FP64 oracle on a bounded sample: p2 at random voxels of its 256^3 grid.
+
+    The oracle's steps as it runs them for one harmonic: transfer of p1 onto
+    the 256^3 grid and the source term (whole grid, once), then the direct
+    midpoint sum at each sampled voxel.  The sample size is chosen from a
+    256-voxel probe (enough voxels to keep every host thread busy) so that
+    the whole sample takes about budget_s seconds.
+    """
     import numpy as np
     import oracle
     W = cfg["medium"]
+    f0 = cfg["f0"]
     g1 = oracle.Grid(tuple(g1_p.origin), g1_p.h, tuple(g1_p.n))
     g2 = oracle.Grid(tuple(gn_p[0].origin), gn_p[0].h, tuple(gn_p[0].n))
     p1 = p1_dev.to("cpu").numpy().astype(np.complex128)
+    k2 = oracle.wavenumber(2, f0, W)
+    C2 = oracle.cascade_constant(2, f0, W)
     rng = np.random.default_rng(11)
-    n_t = 16
+    t0 = time.perf_counter()
+    f = oracle.source_term(2, {1: oracle.transfer(p1, g1, g2, order)})
+    t_fixed = time.perf_counter() - t0
+    probe = rng.integers(0, g2.size(), 256)
+    t0 = time.perf_counter()
+    C2 * oracle.conv_direct(f, g2.h, k2, targets=probe)
+    per = (time.perf_counter() - t0) / 256
+    n_t = int(max(256, min(200000, (budget_s - t_fixed) / max(per, 1e-6))))
     t = rng.integers(0, g2.size(), n_t)
     t0 = time.perf_counter()
-    oracle.harmonic(2, {1: (p1, g1)}, g2, cfg["f0"], W, 3, method="direct", targets=t)
-    dt = time.perf_counter() - t0
-    # grow the sample to about budget_s of work (per-target cost dominates)
-    if dt < budget_s / 3:
-        n_t = int(min(4096, max(16, n_t * budget_s / max(dt, 1e-3) * 0.8)))
-        t = rng.integers(0, g2.size(), n_t)
-        t0 = time.perf_counter()
-        oracle.harmonic(2, {1: (p1, g1)}, g2, cfg["f0"], W, 3, method="direct", targets=t)
-        dt = time.perf_counter() - t0
+    C2 * oracle.conv_direct(f, g2.h, k2, targets=t)
+    t_sum = time.perf_counter() - t0
+    dt = t_fixed + t_sum
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": n_t / dt, "unit": "voxels/s", "cores": cores, "kind": "oracle",
-            "sample": "p2 at %d random voxels of the 256^3 grid: FP64 direct midpoint sum over all 16.8M "
-                      "source voxels, tricubic transfer of p1 included (%.1f s)" % (n_t, dt)}
+            "sample": "p2 at %d random voxels of the 256^3 grid: transfer (order %d) and source term of the whole "
+                      "grid (%.1f s) plus the FP64 direct midpoint sum over all 16.8M source voxels per sampled "
+                      "voxel (%.1f s)" % (n_t, order, t_fixed, t_sum)}
+
+
+def batch_bench(P, torch, ctx, W, steps, log):
+    """The batched workload: 64 seeded transducers, harmonic boxes from the trained box predictor.
+
+    Every transducer's p_1 grid covers its reference window; p_2..p_n live on
+    the predicted boxes (uneven grids).  Kernel spectra are cached after the
+    first run, so a timed run is the transfer + source builds and the
+    convolutions of every harmonic of every transducer.
+    """
+    from paper_2011_03009_amd import boxpred as BP
+    from paper_2011_03009_amd import train_boxnet as TB
+    Ts = TB.transducers(64, 0)
+    net, _ = BP.load_net(ctx)
+    inc = TB.make_incident()
+    probs, p1s = [], []
+    for T in Ts:
+        fr = BP.predict_fractions(net, T, ctx)
+        geo = BP.Geometry(T, W)
+        g1 = geo.g1()
+        probs.append(dict(med=W, f0=T.f0, g1=g1, grids=[geo.grid(n, fr[n]) for n in range(2, T.n_harm + 1)]))
+        p1s.append(inc(T, g1))
+    net.close()
+    vox = sum(nsz(g) for p in probs for g in p["grids"])
+    sizes = [nsz(g) for p in probs for g in p["grids"]]
+    b = P.Batch(ctx, probs, prec=P.NVP_C64, order=3)
+    outs = b.outputs()
+    stream = torch.cuda.current_stream()
+
+    def timed(k):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            b.execute(p1s, outs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    res = {"transducers": len(Ts), "harmonic_grids": len(sizes), "voxels": vox,
+           "smallest_grid": min(sizes), "largest_grid": max(sizes)}
+    b.set_graph(False)
+    b.execute(p1s, outs)  # kernel spectra and twiddles
+    torch.cuda.synchronize()
+    res["eager_ms"] = timed(steps)
+    b.set_graph(True, 4)
+    b.execute(p1s, outs)
+    torch.cuda.synchronize()
+    res["graph_ms"] = timed(steps)
+    t0 = time.perf_counter()
+    b.autotune(None, reps=2)
+    res["autotune_s"] = time.perf_counter() - t0
+    b.set_graph(True, 4)
+    b.execute(p1s, outs)
+    torch.cuda.synchronize()
+    res["tuned_graph_ms"] = timed(steps)
+    b.set_graph(False)
+    res["tuned_eager_ms"] = timed(steps)
+    best = min(res["eager_ms"], res["graph_ms"], res["tuned_graph_ms"], res["tuned_eager_ms"])
+    res["voxels_per_s"] = vox / (best * 1e-3)
+    b.close()
+    log("bench: batched %s" % res)
+    return res
 
 
 def main():
@@ -128,6 +203,7 @@ def main():
     ap.add_argument("--pf", type=float, default=3.5e6, help="focal pressure (Pa)")
     ap.add_argument("--no-uniform", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--calib", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (a known-size reference for HBM counters)")
@@ -233,9 +309,13 @@ def main():
         del plan_u, outs_u
         torch.cuda.empty_cache()
 
+    if not a.no_batch:
+        log("bench: batched transducers")
+        result["batched"] = batch_bench(P, torch, ctx, W, 5, log)
+
     if not a.no_cpu:
         log("bench: oracle CPU baseline")
-        result["cpu_baseline"] = cpu_baseline(cfg, g1, gn, p1, a.cpu_budget)
+        result["cpu_baseline"] = cpu_baseline(cfg, g1, gn, p1, a.cpu_budget, a.order)
     ctx.close()
     print(json.dumps(result), flush=True)
 
