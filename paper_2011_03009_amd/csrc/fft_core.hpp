@@ -55,11 +55,19 @@ template <int SG, typename R> __device__ __forceinline__ cx<R> cmulk(cx<R> a, R 
 
 template <int N, typename R> struct Dft;
 
+// run_lo<SG, K>: the same transform when only v[0..K-1] may be nonzero (the
+// rest are taken as zero, whatever they hold), so no work is spent on them.
+
 template <typename R> struct Dft<2, R> {
     template <int SG> static __device__ __forceinline__ void run(cx<R> *v) {
         cx<R> a = v[0], b = v[1];
         v[0] = cadd<R>(a, b);
         v[1] = csub<R>(a, b);
+    }
+    template <int SG, int K> static __device__ __forceinline__ void run_lo(cx<R> *v) {
+        static_assert(K >= 1, "at least one nonzero input");
+        if constexpr (K >= 2) run<SG>(v);
+        else v[1] = v[0];
     }
 };
 
@@ -72,15 +80,33 @@ template <typename R> struct Dft<4, R> {
         v[1] = cadd<R>(b, d);
         v[3] = csub<R>(b, d);
     }
+    template <int SG, int K> static __device__ __forceinline__ void run_lo(cx<R> *v) {
+        static_assert(K >= 1, "at least one nonzero input");
+        if constexpr (K >= 4) {
+            run<SG>(v);
+        } else {
+            const cx<R> a = K >= 3 ? cadd<R>(v[0], v[2]) : v[0], b = K >= 3 ? csub<R>(v[0], v[2]) : v[0];
+            const cx<R> c = K >= 2 ? v[1] : czero<R>(), d = crot<SG, R>(c);
+            if constexpr (K >= 2) {
+                v[0] = cadd<R>(a, c);
+                v[2] = csub<R>(a, c);
+                v[1] = cadd<R>(b, d);
+                v[3] = csub<R>(b, d);
+            } else {
+                v[1] = v[2] = v[3] = v[0];
+            }
+        }
+    }
 };
 
 // Even/odd split: y_p = E_p + W^p O_p, y_{p+N/2} = E_p - W^p O_p.
 template <typename R> struct Dft<8, R> {
-    template <int SG> static __device__ __forceinline__ void run(cx<R> *v) {
+    template <int SG> static __device__ __forceinline__ void run(cx<R> *v) { run_lo<SG, 8>(v); }
+    template <int SG, int K> static __device__ __forceinline__ void run_lo(cx<R> *v) {
         cx<R> e[4] = {v[0], v[2], v[4], v[6]};
         cx<R> o[4] = {v[1], v[3], v[5], v[7]};
-        Dft<4, R>::template run<SG>(e);
-        Dft<4, R>::template run<SG>(o);
+        Dft<4, R>::template run_lo<SG, (K + 1) / 2>(e);
+        Dft<4, R>::template run_lo<SG, K / 2>(o);
         const R c = R(0.707106781186547524400844362105);
         // W^1 = c (1 + SG i), W^3 = c (-1 + SG i)
         o[1] = SG > 0 ? mk<R>(c * (o[1].x - o[1].y), c * (o[1].x + o[1].y))
@@ -97,15 +123,16 @@ template <typename R> struct Dft<8, R> {
 };
 
 template <typename R> struct Dft<16, R> {
-    template <int SG> static __device__ __forceinline__ void run(cx<R> *v) {
+    template <int SG> static __device__ __forceinline__ void run(cx<R> *v) { run_lo<SG, 16>(v); }
+    template <int SG, int K> static __device__ __forceinline__ void run_lo(cx<R> *v) {
         cx<R> e[8], o[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             e[i] = v[2 * i];
             o[i] = v[2 * i + 1];
         }
-        Dft<8, R>::template run<SG>(e);
-        Dft<8, R>::template run<SG>(o);
+        Dft<8, R>::template run_lo<SG, (K + 1) / 2>(e);
+        Dft<8, R>::template run_lo<SG, K / 2>(o);
         const R c1 = R(0.923879532511286756128183189397);  // cos(pi/8)
         const R s1 = R(0.382683432365089771728459984030);  // sin(pi/8)
         const R c2 = R(0.707106781186547524400844362105);
@@ -142,14 +169,20 @@ __host__ __device__ constexpr double odd_sin(int N, int k) {
 
 // Odd N: pair v_q with v_{N-q}:  y_p = v_0 + sum_q a_q cos(2 pi p q / N) +- SG i sum_q b_q sin(...).
 template <int N, typename R> struct DftOdd {
-    template <int SG> static __device__ __forceinline__ void run(cx<R> *v) {
+    template <int SG> static __device__ __forceinline__ void run(cx<R> *v) { run_lo<SG, N>(v); }
+    template <int SG, int K> static __device__ __forceinline__ void run_lo(cx<R> *v) {
+        static_assert(K > (N - 1) / 2, "inputs 1..(N-1)/2 are taken as nonzero");
         constexpr int H = (N - 1) / 2;
         cx<R> a[H], b[H];
         cx<R> y0 = v[0];
 #pragma unroll
         for (int q = 1; q <= H; ++q) {
-            a[q - 1] = cadd<R>(v[q], v[N - q]);
-            b[q - 1] = csub<R>(v[q], v[N - q]);
+            if (N - q < K) {
+                a[q - 1] = cadd<R>(v[q], v[N - q]);
+                b[q - 1] = csub<R>(v[q], v[N - q]);
+            } else {
+                a[q - 1] = b[q - 1] = v[q];
+            }
             y0 = cadd<R>(y0, a[q - 1]);
         }
         cx<R> out[N];
@@ -236,6 +269,28 @@ __host__ __device__ constexpr int twiddle_table_len(int L) { return plan_tw_len(
 
 // ---------------------------------------------------------------- engine
 
+// LDS slot of one contiguous pencil.  Pad elements spread the Stockham
+// stages' strided writes and contiguous reads over the 64 four-byte banks:
+// for complex64, two per 32 elements and one more per 128; for complex128,
+// one per 16 (the layouts with the fewest conflicts in a model of the
+// engine's access patterns over the compiled lengths).
+template <typename R> __host__ __device__ constexpr int pencil_pad(int m) {
+    if constexpr (sizeof(R) == 4) return m + 2 * (m >> 5) + (m >> 7);
+    else return m + (m >> 4);
+}
+
+// Accessor of a padded pencil slot.  at(pad(B), c) addresses element B + c as
+// pad(B) + pad(c): a per-thread base plus a compile-time offset, valid where
+// the engine has checked pad(B + c) = pad(B) + pad(c) for every thread.
+template <typename R> struct PencilSlot {
+    cx<R> *p;
+    static __host__ __device__ constexpr int pad(int m) { return pencil_pad<R>(m); }
+    __device__ __forceinline__ cx<R> &operator()(int m) const { return p[pad(m)]; }
+    __device__ __forceinline__ cx<R> &at(int pad_base, int c) const { return p[pad_base + pad(c)]; }
+};
+template <class T> struct is_pencil_slot { static constexpr bool value = false; };
+template <typename R> struct is_pencil_slot<PencilSlot<R>> { static constexpr bool value = true; };
+
 // Orders LDS traffic between the lanes of one wavefront.  A thread's own
 // accesses on either side may provably not alias (so the compiler would be
 // free to swap them), but other lanes' do: the memory clobber keeps every LDS
@@ -283,17 +338,29 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
         for (int i = 0; i < E / r; ++i) Dft<r, R>::template run<SG>(v + i * r);
     }
 
-    // Stockham destination of butterfly b = t + i P at stage s, written so
-    // that it is a per-thread base plus a compile-time offset when possible.
-    template <int s> static __device__ __forceinline__ int wr_index(int t, int i) {
-        constexpr int Ns = ns(s), r = rad(s);
-        if constexpr (P % Ns == 0) return (t / Ns) * Ns * r + (t % Ns) + i * P * r;
-        else if constexpr (P * (E / r) <= Ns) return t + i * P;
-        else {
-            const int b = t + i * P;
-            return (b / Ns) * Ns * r + b % Ns;
+    // Inputs at or beyond L/2 of a column whose upper half is zero: first-stage
+    // slots q >= K0 (K0 = ceil(r0 / 2)) hold elements >= L/2 for every thread.
+    static constexpr int K0 = (rad(0) + 1) / 2;
+    template <int SG, bool ZH> static __device__ __forceinline__ void bflies0(cx<R> *v) {
+        constexpr int r0 = rad(0);
+        if constexpr (ZH) {
+#pragma unroll
+            for (int i = 0; i < E / r0; ++i) Dft<r0, R>::template run_lo<SG, K0>(v + i * r0);
+        } else {
+            bflies<r0, SG>(v);
         }
     }
+
+    // Stockham destination of butterfly b = t + i P at stage s, written so
+    // that it is a per-thread base plus a compile-time offset when possible.
+    static __host__ __device__ constexpr int wr_idx(int s, int t, int i) {
+        const int Ns = ns(s), r = rad(s);
+        if (P % Ns == 0) return (t / Ns) * Ns * r + (t % Ns) + i * P * r;
+        if (P * (E / r) <= Ns) return t + i * P;
+        const int b = t + i * P;
+        return (b / Ns) * Ns * r + b % Ns;
+    }
+    template <int s> static __device__ __forceinline__ int wr_index(int t, int i) { return wr_idx(s, t, i); }
     // j = b mod Ns for b = t + i P, likewise.
     template <int s> static __device__ __forceinline__ int tw_j(int t, int i) {
         constexpr int Ns = ns(s), r = rad(s);
@@ -302,29 +369,61 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
         else return (t + i * P) % Ns;
     }
 
-    // First-stage inputs: v[i r0 + q] = x[t + i P + q L / r0].
-    template <class Ld> static __device__ __forceinline__ void load0(cx<R> *v, int t, Ld ld) {
+    // Whether the writes of stage s (element wr_idx(s, t, i) + p Ns) and the
+    // reads of stage s (element t + i P + q L / r) may address a padded slot
+    // as pad(base) + pad(offset), checked for every thread and slot.
+    static constexpr bool split_writes(int s) {
+        const int Ns = ns(s), r = rad(s);
+        if (!(P % Ns == 0 || P * (E / r) <= Ns)) return false;
+        for (int t = 0; t < P; ++t) {
+            const int B = wr_idx(s, t, 0);
+            for (int i = 0; i < E / r; ++i)
+                for (int p = 0; p < r; ++p) {
+                    const int c = wr_idx(s, t, i) - B + p * Ns;
+                    if (c < 0 || pencil_pad<R>(B + c) != pencil_pad<R>(B) + pencil_pad<R>(c)) return false;
+                }
+        }
+        return true;
+    }
+    static constexpr bool split_reads(int s) {
+        const int r = rad(s);
+        for (int t = 0; t < P; ++t)
+            for (int i = 0; i < E / r; ++i)
+                for (int q = 0; q < r; ++q) {
+                    const int c = i * P + q * (L / r);
+                    if (pencil_pad<R>(t + c) != pencil_pad<R>(t) + pencil_pad<R>(c)) return false;
+                }
+        return true;
+    }
+
+    // First-stage inputs: v[i r0 + q] = x[t + i P + q L / r0].  ZH: the
+    // column's elements from L/2 on are zero and are not read.
+    template <bool ZH = false, class Ld> static __device__ __forceinline__ void load0(cx<R> *v, int t, Ld ld) {
         constexpr int r0 = rad(0);
 #pragma unroll
         for (int i = 0; i < E / r0; ++i) {
             const int b = t + i * P;
 #pragma unroll
-            for (int q = 0; q < r0; ++q) v[i * r0 + q] = ld(b + q * (L / r0));
+            for (int q = 0; q < r0; ++q) {
+                if (!ZH || q < K0) v[i * r0 + q] = ld(b + q * (L / r0));
+                else v[i * r0 + q] = czero<R>();
+            }
         }
     }
 
     // All stages on v (loaded by load0); st(m, x) receives the outputs.
-    template <int SG, class Tw, class St, class Lds>
+    // ZH: inputs from L/2 on are zero.  OH: only outputs below L/2 are stored.
+    template <int SG, bool ZH = false, bool OH = false, class Tw, class St, class Lds>
     static __device__ __forceinline__ void compute(cx<R> *v, int t, Tw tw, St st, Lds lds) {
-        bflies<rad(0), SG>(v);
-        next<0, SG, true>(v, t, tw, st, lds);
+        bflies0<SG, ZH>(v);
+        next<0, SG, true, OH>(v, t, tw, st, lds);
     }
 
     // All stages on v; the outputs stay in v (see out_index).
-    template <int SG, class Tw, class Lds>
+    template <int SG, bool ZH = false, class Tw, class Lds>
     static __device__ __forceinline__ void compute_keep(cx<R> *v, int t, Tw tw, Lds lds) {
-        bflies<rad(0), SG>(v);
-        next<0, SG, false>(v, t, tw, [](int, cx<R>) {}, lds);
+        bflies0<SG, ZH>(v);
+        next<0, SG, false, false>(v, t, tw, [](int, cx<R>) {}, lds);
     }
 
     // Transform this thread's share of one column.
@@ -332,15 +431,15 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
     //   st(m, x)  <- output element m (last stage, natural order)
     //   lds(m)    -> reference to element m of this column's LDS slot
     // LDS_IN: ld reads the same LDS slot, so wait before overwriting it.
-    template <int SG, bool LDS_IN, class Tw, class Ld, class St, class Lds>
+    template <int SG, bool LDS_IN, bool ZH = false, bool OH = false, class Tw, class Ld, class St, class Lds>
     static __device__ __forceinline__ void run(int t, Tw tw, Ld ld, St st, Lds lds) {
         cx<R> v[E];
-        load0(v, t, ld);
+        load0<ZH>(v, t, ld);
         if constexpr (LDS_IN) sync();
-        compute<SG>(v, t, tw, st, lds);
+        compute<SG, ZH, OH>(v, t, tw, st, lds);
     }
 
-    template <int s, int SG, bool STORE, class Tw, class St, class Lds>
+    template <int s, int SG, bool STORE, bool OH, class Tw, class St, class Lds>
     static __device__ __forceinline__ void next(cx<R> *v, int t, Tw tw, St st, Lds lds) {
         constexpr int r = rad(s);
         constexpr int Ns = ns(s);
@@ -350,33 +449,52 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
                 for (int i = 0; i < E / r; ++i) {
                     const int b = t + i * P;
 #pragma unroll
-                    for (int p = 0; p < r; ++p) st(b + p * (L / r), v[i * r + p]);
+                    for (int p = 0; p < r; ++p)
+                        if (!OH || p < (r + 1) / 2) st(b + p * (L / r), v[i * r + p]);
                 }
             }
         } else {
+            constexpr int r1 = rad(s + 1);
+            constexpr int off = TW_BASE + plan_tw_off(L, REV, s + 1);
+            // next stage's twiddles first: their loads are in flight during the LDS exchange
+            cx<R> wv[E / r1][r1 - 1];
+#pragma unroll
+            for (int i = 0; i < E / r1; ++i) {
+                const int jb = off + tw_j<s + 1>(t, i) * (r1 - 1) - 1;
+#pragma unroll
+                for (int q = 1; q < r1; ++q) wv[i][q - 1] = tw(jb + q);
+            }
+            constexpr bool WS = is_pencil_slot<Lds>::value && split_writes(s);
+            const int pw = WS ? pencil_pad<R>(wr_index<s>(t, 0)) : 0;
 #pragma unroll
             for (int i = 0; i < E / r; ++i) {
                 const int w = wr_index<s>(t, i);
 #pragma unroll
-                for (int p = 0; p < r; ++p) lds(w + p * Ns) = v[i * r + p];
+                for (int p = 0; p < r; ++p) {
+                    if constexpr (WS) lds.at(pw, wr_idx(s, 0, i) - wr_idx(s, 0, 0) + p * Ns) = v[i * r + p];
+                    else lds(w + p * Ns) = v[i * r + p];
+                }
             }
             sync();
-            constexpr int r1 = rad(s + 1);
-            constexpr int off = TW_BASE + plan_tw_off(L, REV, s + 1);
+            constexpr bool RS = is_pencil_slot<Lds>::value && split_reads(s + 1);
+            const int pr = RS ? pencil_pad<R>(t) : 0;
 #pragma unroll
             for (int i = 0; i < E / r1; ++i) {
                 const int b = t + i * P;
-                const int jb = off + tw_j<s + 1>(t, i) * (r1 - 1) - 1;
-                v[i * r1] = lds(b);
+                if constexpr (RS) v[i * r1] = lds.at(pr, i * P);
+                else v[i * r1] = lds(b);
 #pragma unroll
                 for (int q = 1; q < r1; ++q) {
-                    const cx<R> x = lds(b + q * (L / r1)), w = tw(jb + q);
+                    cx<R> x;
+                    if constexpr (RS) x = lds.at(pr, i * P + q * (L / r1));
+                    else x = lds(b + q * (L / r1));
+                    const cx<R> w = wv[i][q - 1];
                     v[i * r1 + q] = SG < 0 ? cmul<R>(x, w) : cmulc<R>(x, w);
                 }
             }
             sync();
             bflies<r1, SG>(v);
-            next<s + 1, SG, STORE>(v, t, tw, st, lds);
+            next<s + 1, SG, STORE, OH>(v, t, tw, st, lds);
         }
     }
 };

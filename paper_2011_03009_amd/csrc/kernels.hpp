@@ -124,10 +124,9 @@ template <typename R, int K> struct LdSource {
 
 extern __shared__ __align__(16) unsigned char nvp_smem[];
 
-// LDS slot of a contiguous pencil: one pad element per 16 spreads the strided
-// writes of the early Stockham stages over the banks.
-__host__ __device__ constexpr int padded(int m) { return m + (m >> 4); }
-template <typename R> __host__ __device__ constexpr int slot_len(int L) { return padded(L) + 1; }
+// LDS slot of a contiguous pencil (see PencilSlot).
+template <typename R> __host__ __device__ constexpr int padded(int m) { return pencil_pad<R>(m); }
+template <typename R> __host__ __device__ constexpr int slot_len(int L) { return padded<R>(L) + 1; }
 
 // Copies n entries of a twiddle table into LDS (all threads of the workgroup).
 template <typename R> __device__ __forceinline__ void stage_table(cx<R> *dst, const cx<R> *src, int n) {
@@ -184,10 +183,16 @@ k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, int64_t inner) {
         F::template run<SG, true>(t, twf, [&](int m) { return lds[(m <= L / 2 ? m : L - m) * T + c]; }, store,
                                   ref);
     } else {
+        // forward passes read columns whose upper half is zero (M >= 2N - 1);
+        // inverse passes keep at most the lower half
+        constexpr bool ZH = SG < 0, OH = SG > 0;
         cx<R> v[F::E];
-        F::load0(v, t, [&](int m) { return act ? ld(o, col, m) : czero<R>(); });
-        if constexpr (TWL) stage_table<R>(twl, tw, NT);
-        F::template compute<SG>(v, t, twf, store, ref);
+        F::template load0<ZH>(v, t, [&](int m) { return act ? ld(o, col, m) : czero<R>(); });
+        if constexpr (TWL) {
+            stage_table<R>(twl, tw, NT);
+            __syncthreads();  // the engine reads a stage's twiddles before its LDS exchange
+        }
+        F::template compute<SG, ZH, OH>(v, t, twf, store, ref);
     }
 }
 
@@ -213,7 +218,7 @@ k_xsrc(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t inner) {
 #pragma unroll 1
     for (int m = t; m < Nx; m += F::P) lds[m * T + c] = act ? src.value(m, iy, iz) : czero<R>();
     __syncthreads();
-    F::template run<-1, true>(
+    F::template run<-1, true, true>(
         t, twf, [&](int m) { return m < Nx ? lds[m * T + c] : czero<R>(); },
         [&](int m, cx<R> v) {
             if (act) st(0, col, m, v);
@@ -307,7 +312,7 @@ k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t i
         }
         __syncthreads();
     }
-    F::template run<-1, true>(
+    F::template run<-1, true, true>(
         t, twf, [&](int m) { return m < Nx ? lds[m * T + c] : czero<R>(); },
         [&](int m, cx<R> v) {
             if (act) st(0, col, m, v);
@@ -441,17 +446,23 @@ k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int
     cx<R> *pen = buf + (px * My + py) * (int64_t)Nz;
     const cx<R> *krow = khat + (kx * Hy + ky) * (int64_t)HZ;
     cx<R> *my = lds + slot * SL;
-    auto ref = [&](int m) -> cx<R> & { return my[padded(m)]; };
+    const PencilSlot<R> ref{my};
     cx<R> v[E];
-    F::load0(v, t, [&](int m) { return (act && m < Nz) ? pen[m] : czero<R>(); });
-    auto twf = [&](int e) { return tw[e]; };
-    F::template compute_keep<-1>(v, t, twf, ref);
+    // the pencil's upper half is zero (Mz >= 2 Nz - 1) and only its lower half is kept
+    F::template load0<true>(v, t, [&](int m) { return (act && m < Nz) ? pen[m] : czero<R>(); });
+    // the spectrum values this thread multiplies by, loaded before the forward
+    // transform so that their latency overlaps it
+    cx<R> kv[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int k = F::out_index(t, i);
-        v[i] = valid ? cmul<R>(v[i], krow[k <= L / 2 ? k : L - k]) : czero<R>();
+        kv[i] = valid ? krow[k <= L / 2 ? k : L - k] : czero<R>();
     }
-    G::template compute<1>(v, t, twf,
+    auto twf = [&](int e) { return tw[e]; };
+    F::template compute_keep<-1, true>(v, t, twf, ref);
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = cmul<R>(v[i], kv[i]);
+    G::template compute<1, false, true>(v, t, twf,
                            [&](int m, cx<R> x) {
                                if (act && m < Nz) pen[m] = x;
                            },
@@ -496,15 +507,15 @@ k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, 
                 v = make_double2(mag * cs, mag * sn);
             }
         }
-        my[padded(k)] = v;
+        my[padded<double>(k)] = v;
     }
     wave_sync();
     F::template run<-1, true>(
-        t, twf, [&](int m) { return my[padded(m <= L / 2 ? m : L - m)]; },
+        t, twf, [&](int m) { return my[padded<double>(m <= L / 2 ? m : L - m)]; },
         [&](int m, cx<double> v) {
             if (act && m < HZ) out[row * HZ + m] = v;
         },
-        [&](int m) -> cx<double> & { return my[padded(m)]; });
+        PencilSlot<double>{my});
 }
 
 }  // namespace nvp
