@@ -291,6 +291,18 @@ template <typename R> struct PencilSlot {
 template <class T> struct is_pencil_slot { static constexpr bool value = false; };
 template <typename R> struct is_pencil_slot<PencilSlot<R>> { static constexpr bool value = true; };
 
+// Accessor of T interleaved columns holding one real plane: element m of
+// column c at p[m T + c].  With it the engine exchanges real and imaginary
+// parts in two rounds, so a column needs half the LDS (twice the columns per
+// CU) for twice the barriers.
+template <typename R, int T> struct SplitCols {
+    R *p;
+    int c;
+    __device__ __forceinline__ R &re(int m) const { return p[m * T + c]; }
+};
+template <class T> struct is_split_cols { static constexpr bool value = false; };
+template <typename R, int T> struct is_split_cols<SplitCols<R, T>> { static constexpr bool value = true; };
+
 // Orders LDS traffic between the lanes of one wavefront.  A thread's own
 // accesses on either side may provably not alias (so the compiler would be
 // free to swap them), but other lanes' do: the memory clobber keeps every LDS
@@ -439,6 +451,40 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
         compute<SG, ZH, OH>(v, t, tw, st, lds);
     }
 
+    // The LDS exchange after stage s through a single real plane: real parts,
+    // then imaginary parts; the next stage's inputs come out twiddled.
+    template <int s, int SG, class W, class Lds>
+    static __device__ __forceinline__ void exchange_split(cx<R> *v, int t, W twq, Lds lds) {
+        constexpr int r = rad(s), Ns = ns(s), r1 = rad(s + 1);
+        R xr[E];
+#pragma unroll
+        for (int part = 0; part < 2; ++part) {
+#pragma unroll
+            for (int i = 0; i < E / r; ++i) {
+                const int w = wr_index<s>(t, i);
+#pragma unroll
+                for (int p = 0; p < r; ++p) lds.re(w + p * Ns) = part ? v[i * r + p].y : v[i * r + p].x;
+            }
+            sync();
+#pragma unroll
+            for (int i = 0; i < E / r1; ++i) {
+                const int b = t + i * P;
+#pragma unroll
+                for (int q = 0; q < r1; ++q) {
+                    const R y = lds.re(b + q * (L / r1));
+                    if (part == 0) {
+                        xr[i * r1 + q] = y;
+                    } else {
+                        const cx<R> x = mk<R>(xr[i * r1 + q], y);
+                        if (q == 0) v[i * r1] = x;
+                        else v[i * r1 + q] = SG < 0 ? cmul<R>(x, twq(i, q)) : cmulc<R>(x, twq(i, q));
+                    }
+                }
+            }
+            sync();
+        }
+    }
+
     template <int s, int SG, bool STORE, bool OH, class Tw, class St, class Lds>
     static __device__ __forceinline__ void next(cx<R> *v, int t, Tw tw, St st, Lds lds) {
         constexpr int r = rad(s);
@@ -456,14 +502,25 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
         } else {
             constexpr int r1 = rad(s + 1);
             constexpr int off = TW_BASE + plan_tw_off(L, REV, s + 1);
-            // next stage's twiddles first: their loads are in flight during the LDS exchange
+            // next stage's twiddles first, so that their loads are in flight during the
+            // LDS exchange (complex64; complex128 values would cost too many registers)
+            constexpr bool PRE = sizeof(R) == 4;
             cx<R> wv[E / r1][r1 - 1];
+            if constexpr (PRE) {
 #pragma unroll
-            for (int i = 0; i < E / r1; ++i) {
-                const int jb = off + tw_j<s + 1>(t, i) * (r1 - 1) - 1;
+                for (int i = 0; i < E / r1; ++i) {
+                    const int jb = off + tw_j<s + 1>(t, i) * (r1 - 1) - 1;
 #pragma unroll
-                for (int q = 1; q < r1; ++q) wv[i][q - 1] = tw(jb + q);
+                    for (int q = 1; q < r1; ++q) wv[i][q - 1] = tw(jb + q);
+                }
             }
+            auto twq = [&](int i, int q) {
+                if constexpr (PRE) return wv[i][q - 1];
+                else return tw(off + tw_j<s + 1>(t, i) * (r1 - 1) - 1 + q);
+            };
+            if constexpr (is_split_cols<Lds>::value) {
+                exchange_split<s, SG>(v, t, twq, lds);
+            } else {
             constexpr bool WS = is_pencil_slot<Lds>::value && split_writes(s);
             const int pw = WS ? pencil_pad<R>(wr_index<s>(t, 0)) : 0;
 #pragma unroll
@@ -488,11 +545,12 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
                     cx<R> x;
                     if constexpr (RS) x = lds.at(pr, i * P + q * (L / r1));
                     else x = lds(b + q * (L / r1));
-                    const cx<R> w = wv[i][q - 1];
+                    const cx<R> w = twq(i, q);
                     v[i * r1 + q] = SG < 0 ? cmul<R>(x, w) : cmulc<R>(x, w);
                 }
             }
             sync();
+            }
             bflies<r1, SG>(v);
             next<s + 1, SG, STORE, OH>(v, t, tw, st, lds);
         }

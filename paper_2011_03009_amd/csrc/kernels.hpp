@@ -148,14 +148,28 @@ template <typename R> constexpr bool tw_fits(size_t data_elems, size_t tw_elems)
 // SG: -1 forward, +1 inverse.  MIRROR: the columns hold entries 0..L/2 of even
 // sequences; they are read once into LDS and the transform takes its first
 // stage from there.
+// LDS bytes of a strided workgroup's columns.  The mirror passes (the FP64
+// kernel spectrum) stage their L/2+1 input entries as complex values, then
+// exchange through one real plane, so a column needs about L reals instead of
+// L complex values.
+template <typename R, int L, int T, bool MIRROR> constexpr size_t strided_data_bytes() {
+    if constexpr (MIRROR) {
+        const size_t a = (size_t)T * L * sizeof(R), b = (size_t)T * (L / 2 + 1) * sizeof(cx<R>);
+        return a > b ? a : b;
+    } else {
+        return (size_t)T * L * sizeof(cx<R>);
+    }
+}
+
 template <typename R, int L, int T, int SG, bool MIRROR, class Ld, class St>
 __global__ void __launch_bounds__(T *plan_threads(L))
 k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, int64_t inner) {
     using F = Fft<R, L>;
     constexpr int NT = plan_tw_len(L, false);
-    constexpr bool TWL = tw_fits<R>((size_t)T * L, NT);
+    constexpr size_t DATA = strided_data_bytes<R, L, T, MIRROR>();
+    constexpr bool TWL = tw_fits<R>(DATA / sizeof(cx<R>), NT);
     cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
-    cx<R> *twl = lds + T * L;
+    cx<R> *twl = reinterpret_cast<cx<R> *>(nvp_smem + DATA);
     auto twf = [&](int e) { return TWL ? twl[e] : tw[e]; };
     const int tid = threadIdx.x, c = tid % T, t = tid / T;
     const int64_t col = (int64_t)blockIdx.x * T + c;
@@ -181,7 +195,7 @@ k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, int64_t inner) {
         if constexpr (TWL) stage_table<R>(twl, tw, NT);
         __syncthreads();
         F::template run<SG, true>(t, twf, [&](int m) { return lds[(m <= L / 2 ? m : L - m) * T + c]; }, store,
-                                  ref);
+                                  SplitCols<R, T>{reinterpret_cast<R *>(nvp_smem), c});
     } else {
         // forward passes read columns whose upper half is zero (M >= 2N - 1);
         // inverse passes keep at most the lower half

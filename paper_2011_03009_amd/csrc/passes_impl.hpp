@@ -32,9 +32,10 @@ template <class K> inline hipError_t allow_lds(K kern, size_t bytes) {
                                (int)bytes);
 }
 
-template <typename R, int L, int T> constexpr size_t strided_lds() {
-    return ((size_t)T * L + (tw_fits<R>((size_t)T * L, plan_tw_len(L, false)) ? plan_tw_len(L, false) : 0)) *
-           sizeof(cx<R>);
+template <typename R, int L, int T, bool MIRROR = false> constexpr size_t strided_lds() {
+    constexpr size_t data = strided_data_bytes<R, L, T, MIRROR>();
+    return data + (tw_fits<R>(data / sizeof(cx<R>), plan_tw_len(L, false)) ? plan_tw_len(L, false) : 0) *
+                      sizeof(cx<R>);
 }
 
 template <typename R, typename Rout, int L, int SG, bool SC, bool MIRROR, int T = strided_cols<R>(L)>
@@ -44,7 +45,7 @@ hipError_t strided_v(const StridedArgs &a, const void *tw, hipStream_t s) {
     Ld ld{static_cast<const cx<R> *>(a.in), a.in_os, a.in_ms, a.n_in, a.mirror};
     St st{static_cast<cx<Rout> *>(a.out), a.out_os, a.out_ms, a.n_out, (R)a.scale};
     auto kern = k_strided<R, L, T, SG, MIRROR, Ld, St>;
-    constexpr size_t lds = strided_lds<R, L, T>();
+    constexpr size_t lds = strided_lds<R, L, T, MIRROR>();
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
     dim3 grid((unsigned)((a.inner + T - 1) / T), (unsigned)a.outer);
