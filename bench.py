@@ -32,6 +32,40 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash():
+    """SHA-256 over the library's sources: HBM counter figures apply only to the kernels they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2011_03009_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "nvp.h"), "rb").read())
+    return h.hexdigest()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_nested_cascade_paper_scale.md")
+
+
+def counter_traffic(kind):
+    """HBM bytes per launch of `kind` from the committed counter summary, or None when it is absent or
+    was taken on other kernel sources."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    i = text.find("```json")
+    if i < 0:
+        return None
+    j = text.find("```", i + 7)
+    d = json.loads(text[i + 7:j])
+    if d.get("source_hash") != kernel_source_hash() or kind not in d.get("kinds", {}):
+        return None
+    k = d["kinds"][kind]
+    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+
+
 def build_inputs(P, torch, cfg, device):
     from workload import bowl
     W = cfg["medium"]
@@ -261,7 +295,7 @@ def main():
     dom = max(per_kind, key=lambda k: per_kind[k]["ms_per_step"])
     achieved = per_kind[dom]["alg_GBs"]
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+            "frac": achieved / PEAK_HBM_GBS, "traffic": counter_traffic(dom),
             "alg_bytes_per_launch": ab[dom] / max(1.0, per_kind[dom]["launches_per_step"]),
             "avg_launch_ms": per_kind[dom]["ms_per_step"] / max(1.0, per_kind[dom]["launches_per_step"])}
     conv_kinds = ("src", "xfwd", "yfwd", "zconv", "yinv", "xinv")

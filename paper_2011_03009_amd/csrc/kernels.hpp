@@ -370,49 +370,60 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
         // source block [sx0, sx0+SX) x [sy0, sy0+SY) x [sz0, sz0+SZ)
         const int sx0 = g.b[0][ix0], sy0 = g.b[1][iy0], sz0 = g.b[2][iz0];
         const int SX = g.b[0][ix1 - 1] + K - sx0, SY = g.b[1][iy1 - 1] + K - sy0, SZ = g.b[2][iz1 - 1] + K - sz0;
+        const int rows = SX * SY;
         cx<R> *S = lds;                         // [SX][SY][SZ], later T2 [SX][TY][TZ]
-        cx<R> *T1 = lds + (lds_elems - (int64_t)SX * SY * TZ);  // [SX][SY][TZ]
-        const int nS = SX * SY * SZ;
-        for (int e = threadIdx.x; e < nS; e += TY * TZ) {
-            const int sz = e % SZ, r = e / SZ, sy = r % SY, sx = r / SY;
-            S[e] = g.p[(int64_t)(sx0 + sx) * g.s0 + (int64_t)(sy0 + sy) * g.s1 + sz0 + sz];
-        }
-        __syncthreads();
-        const int nT1 = SX * SY * TZ;
-        for (int e = threadIdx.x; e < nT1; e += TY * TZ) {
-            const int z = e % TZ, r = e / TZ;  // r = sx * SY + sy
-            cx<R> acc = czero<R>();
-            if (iz0 + z < Nz) {
-                const int zz = iz0 + z, o = g.b[2][zz] - sz0;
+        cx<R> *T1 = lds + (lds_elems - (int64_t)rows * TZ);  // [SX][SY][TZ]
+        // the tile's z and y stencils: one per thread (z = tz, y = ty), loaded
+        // before the block so that their latency overlaps its loads
+        const int zz = iz0 + tz, yy = iy0 + ty;
+        const bool okz = zz < Nz, oky = yy < Ny;
+        const int oz = okz ? g.b[2][zz] - sz0 : 0, oy = oky ? g.b[1][yy] - sy0 : 0;
+        R wz[K], wy[K], wx[TX][K];
+        int ox[TX];
 #pragma unroll
-                for (int d = 0; d < K; ++d) acc = cadd<R>(acc, cscale<R>(S[r * SZ + o + d], g.w[2][zz * K + d]));
-            }
-            T1[e] = acc;
+        for (int d = 0; d < K; ++d) {
+            wz[d] = okz ? g.w[2][zz * K + d] : R(0);
+            wy[d] = oky ? g.w[1][yy * K + d] : R(0);
+        }
+#pragma unroll
+        for (int a = 0; a < TX; ++a) {
+            const bool okx = ix0 + a < Nx;
+            ox[a] = okx ? g.b[0][ix0 + a] - sx0 : 0;
+#pragma unroll
+            for (int b = 0; b < K; ++b) wx[a][b] = okx ? g.w[0][(ix0 + a) * K + b] : R(0);
+        }
+        // rows of SZ contiguous source values, TZ lanes per row
+        for (int row = ty; row < rows; row += TY) {
+            const int sx = row / SY, sy = row - sx * SY;
+            const cx<R> *src = g.p + (int64_t)(sx0 + sx) * g.s0 + (int64_t)(sy0 + sy) * g.s1 + sz0;
+            for (int sz = tz; sz < SZ; sz += TZ) S[row * SZ + sz] = src[sz];
         }
         __syncthreads();
+        // z interpolation: T1[row][z] for this thread's z
+        for (int row = ty; row < rows; row += TY) {
+            cx<R> acc = czero<R>();
+#pragma unroll
+            for (int d = 0; d < K; ++d) acc = cadd<R>(acc, cscale<R>(S[row * SZ + oz + d], wz[d]));
+            T1[row * TZ + tz] = acc;
+        }
+        __syncthreads();
+        // y interpolation: T2[sx][y][z] for this thread's (y, z)
         cx<R> *T2 = S;
-        const int nT2 = SX * TY * TZ;
-        for (int e = threadIdx.x; e < nT2; e += TY * TZ) {
-            const int z = e % TZ, r = e / TZ, y = r % TY, sx = r / TY;
+        for (int sx = 0; sx < SX; ++sx) {
             cx<R> acc = czero<R>();
-            if (iy0 + y < Ny) {
-                const int yy = iy0 + y, o = g.b[1][yy] - sy0;
 #pragma unroll
-                for (int c = 0; c < K; ++c)
-                    acc = cadd<R>(acc, cscale<R>(T1[((sx * SY) + o + c) * TZ + z], g.w[1][yy * K + c]));
-            }
-            T2[e] = acc;
+            for (int c = 0; c < K; ++c) acc = cadd<R>(acc, cscale<R>(T1[((sx * SY) + oy + c) * TZ + tz], wy[c]));
+            T2[(sx * TY + ty) * TZ + tz] = acc;
         }
         __syncthreads();
 #pragma unroll
         for (int a = 0; a < TX; ++a) {
             const int ix = ix0 + a;
             if (ix < Nx) {
-                const int o = g.b[0][ix] - sx0;
                 cx<R> acc = czero<R>();
 #pragma unroll
                 for (int b = 0; b < K; ++b)
-                    acc = cadd<R>(acc, cscale<R>(T2[((o + b) * TY + ty) * TZ + tz], g.w[0][ix * K + b]));
+                    acc = cadd<R>(acc, cscale<R>(T2[((ox[a] + b) * TY + ty) * TZ + tz], wx[a][b]));
                 v[i][a] = acc;
             }
         }
