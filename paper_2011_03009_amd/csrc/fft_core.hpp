@@ -210,6 +210,13 @@ template <typename R> struct Dft<3, R> : DftOdd<3, R> {};
 template <typename R> struct Dft<5, R> : DftOdd<5, R> {};
 template <typename R> struct Dft<7, R> : DftOdd<7, R> {};
 
+// ---------------------------------------------------------------- octant layout
+
+// Row stride (entries) of the kernel-spectrum octant [Mx/2+1][My/2+1][*] along
+// z: Mz/2+1 rounded up to 16, so that every row starts on a 128-byte line in
+// complex64 and a 256-byte boundary in complex128.
+__host__ __device__ constexpr int64_t octant_row(int64_t Mz) { return (Mz / 2 + 1 + 15) / 16 * 16; }
+
 // ---------------------------------------------------------------- plans
 
 struct PlanDesc {

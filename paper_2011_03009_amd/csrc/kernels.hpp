@@ -469,7 +469,7 @@ k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int
     const int64_t py = (j & 2) ? (My - ky) % My : ky;
     const bool act = valid && !(((j & 1) && px == kx) || ((j & 2) && py == ky));
     cx<R> *pen = buf + (px * My + py) * (int64_t)Nz;
-    const cx<R> *krow = khat + (kx * Hy + ky) * (int64_t)HZ;
+    const cx<R> *krow = khat + (kx * Hy + ky) * octant_row(L);
     cx<R> *my = lds + slot * SL;
     const PencilSlot<R> ref{my};
     cx<R> v[E];
@@ -538,7 +538,7 @@ k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, 
     F::template run<-1, true>(
         t, twf, [&](int m) { return my[padded<double>(m <= L / 2 ? m : L - m)]; },
         [&](int m, cx<double> v) {
-            if (act && m < HZ) out[row * HZ + m] = v;
+            if (act && m < HZ) out[row * octant_row(L) + m] = v;
         },
         PencilSlot<double>{my});
 }

@@ -81,10 +81,8 @@ hipError_t launch_zconv_c128(int L, void *buf, const void *khat, int64_t Mx, int
                              int quads, hipStream_t s);
 
 // Kernel tabulation fused with the first (z) FP64 pass of the kernel spectrum;
-// writes the octant [Hx][Hy][Hz] at `out`.
+// writes the octant [Hx][Hy][Hz] (rows octant_row(L) apart) at `out`.
 hipError_t launch_kz(int L, double2 *out, const int64_t H[3], const int64_t N[3], double h, double kr, double ki,
                      double self_re, double self_im, const void *tw, hipStream_t s);
-hipError_t launch_ktab(double2 *out, const int64_t H[3], const int64_t N[3], double h, double kr, double ki,
-                       double self_re, double self_im, hipStream_t s);
 
 }  // namespace nvp

@@ -265,8 +265,8 @@ struct Timer {
 // ------------------------------------------------------------------ kernel spectrum
 
 // Octant of the FP64 DFT of the circulant-embedded kernel, stored as
-// [Mx/2+1][My/2+1][Mz/2+1] in the plan precision at `khat`.  `scratch` holds
-// the FP64 octant during the three passes.
+// [Mx/2+1][My/2+1][Mz/2+1] (rows padded to octant_row(Mz)) in the plan
+// precision at `khat`.  `scratch` holds the FP64 octant during the three passes.
 nvp_status kernel_spectrum(nvp_ctx *ctx, nvp_plan *timed, double kr, double ki, const nvp_grid *g,
                            const int64_t M[3], nvp_prec prec, void *khat, void *scratch) {
     const int64_t H[3] = {M[0] / 2 + 1, M[1] / 2 + 1, M[2] / 2 + 1};
@@ -282,28 +282,31 @@ nvp_status kernel_spectrum(nvp_ctx *ctx, nvp_plan *timed, double kr, double ki, 
                                     ctx->stream));
     }
     Timer t(timed, NVP_T_KFFT);
+    const int64_t HZS = nvp::octant_row(M[2]);  // padded row stride along z
     StridedArgs a{};
     // y
     if ((st = twiddles(ctx, (int)M[1], true, &tw))) return st;
-    a.in = scratch; a.in_os = H[1] * H[2]; a.in_ms = H[2]; a.mirror = 1;
-    a.out = scratch; a.out_os = H[1] * H[2]; a.out_ms = H[2]; a.n_out = (int)H[1];
+    a.in = scratch; a.in_os = H[1] * HZS; a.in_ms = HZS; a.mirror = 1;
+    a.out = scratch; a.out_os = H[1] * HZS; a.out_ms = HZS; a.n_out = (int)H[1];
     a.scale = 1.0; a.inner = H[2]; a.outer = H[0]; a.sign = -1;
     NVP_HIP(ctx, nvp::launch_strided_c128((int)M[1], a, tw, ctx->stream));
-    // x, written in the plan precision
+    // x, written in the plan precision; columns (y, z) as outer y, inner z
     if ((st = twiddles(ctx, (int)M[0], true, &tw))) return st;
     a = StridedArgs{};
-    a.in = scratch; a.in_os = 0; a.in_ms = H[1] * H[2]; a.mirror = 1;
-    a.out = khat; a.out_os = 0; a.out_ms = H[1] * H[2]; a.n_out = (int)H[0];
-    a.scale = 1.0; a.inner = H[1] * H[2]; a.outer = 1; a.sign = -1;
+    a.in = scratch; a.in_os = HZS; a.in_ms = H[1] * HZS; a.mirror = 1;
+    a.out = khat; a.out_os = HZS; a.out_ms = H[1] * HZS; a.n_out = (int)H[0];
+    a.scale = 1.0; a.inner = H[2]; a.outer = H[1]; a.sign = -1;
     if (prec == NVP_C64) NVP_HIP(ctx, nvp::launch_strided_f64_c64((int)M[0], a, tw, ctx->stream));
     else NVP_HIP(ctx, nvp::launch_strided_c128((int)M[0], a, tw, ctx->stream));
     return NVP_OK;
 }
 
 size_t khat_bytes(const int64_t M[3], nvp_prec prec) {
-    return (size_t)(M[0] / 2 + 1) * (M[1] / 2 + 1) * (M[2] / 2 + 1) * csize(prec);
+    return (size_t)(M[0] / 2 + 1) * (M[1] / 2 + 1) * nvp::octant_row(M[2]) * csize(prec);
 }
-size_t kscratch_bytes(const int64_t M[3]) { return (size_t)(M[0] / 2 + 1) * (M[1] / 2 + 1) * (M[2] / 2 + 1) * 16; }
+size_t kscratch_bytes(const int64_t M[3]) {
+    return (size_t)(M[0] / 2 + 1) * (M[1] / 2 + 1) * nvp::octant_row(M[2]) * 16;
+}
 
 // ------------------------------------------------------------------ the five passes
 
