@@ -357,6 +357,29 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
     for (int i = 0; i < NVP_MAX_FIELDS; ++i)
 #pragma unroll
         for (int a = 0; a < TX; ++a) v[i][a] = czero<R>();
+    // A field's source block [sx0, sx0+SX) x [sy0, sy0+SY) x [sz0, sz0+SZ).
+    struct Block {
+        int sx0, sy0, sz0, SX, SY, SZ;
+    };
+    auto block_of = [&](const FieldDev<R> &g) {
+        Block b;
+        b.sx0 = g.b[0][ix0];
+        b.sy0 = g.b[1][iy0];
+        b.sz0 = g.b[2][iz0];
+        b.SX = g.b[0][ix1 - 1] + K - b.sx0;
+        b.SY = g.b[1][iy1 - 1] + K - b.sy0;
+        b.SZ = g.b[2][iz1 - 1] + K - b.sz0;
+        return b;
+    };
+    // The next field's block is loaded into registers (up to PR rows of PZ
+    // z-values per thread) while this one is interpolated, so that its load
+    // latency overlaps the work; a larger block is loaded when it is reached.
+    // (complex64 only: complex128 values would spill registers)
+    constexpr bool PIPE = sizeof(R) == 4;
+    constexpr int PR = PIPE ? 8 : 1, PZ = PIPE ? 2 : 1;
+    cx<R> pre[PR][PZ];
+    int pre_field = -1;
+    auto fits = [&](const Block &b) { return PIPE && b.SX * b.SY <= PR * TY && b.SZ <= PZ * TZ; };
 #pragma unroll
     for (int i = 0; i < NVP_MAX_FIELDS; ++i) {
         if (i >= src.nf) continue;
@@ -367,9 +390,8 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
                 if (inyz && ix0 + a < Nx) v[i][a] = g.p[(ix0 + a) * g.s0 + (int64_t)iy * g.s1 + iz];
             continue;
         }
-        // source block [sx0, sx0+SX) x [sy0, sy0+SY) x [sz0, sz0+SZ)
-        const int sx0 = g.b[0][ix0], sy0 = g.b[1][iy0], sz0 = g.b[2][iz0];
-        const int SX = g.b[0][ix1 - 1] + K - sx0, SY = g.b[1][iy1 - 1] + K - sy0, SZ = g.b[2][iz1 - 1] + K - sz0;
+        const Block bk = block_of(g);
+        const int sx0 = bk.sx0, sy0 = bk.sy0, sz0 = bk.sz0, SX = bk.SX, SY = bk.SY, SZ = bk.SZ;
         const int rows = SX * SY;
         cx<R> *S = lds;                         // [SX][SY][SZ], later T2 [SX][TY][TZ]
         cx<R> *T1 = lds + (lds_elems - (int64_t)rows * TZ);  // [SX][SY][TZ]
@@ -393,12 +415,43 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
             for (int b = 0; b < K; ++b) wx[a][b] = okx ? g.w[0][(ix0 + a) * K + b] : R(0);
         }
         // rows of SZ contiguous source values, TZ lanes per row
-        for (int row = ty; row < rows; row += TY) {
-            const int sx = row / SY, sy = row - sx * SY;
-            const cx<R> *src = g.p + (int64_t)(sx0 + sx) * g.s0 + (int64_t)(sy0 + sy) * g.s1 + sz0;
-            for (int sz = tz; sz < SZ; sz += TZ) S[row * SZ + sz] = src[sz];
+        if (pre_field == i) {
+#pragma unroll
+            for (int r = 0; r < PR; ++r) {
+                const int row = ty + r * TY;
+#pragma unroll
+                for (int z = 0; z < PZ; ++z) {
+                    const int sz = tz + z * TZ;
+                    if (row < rows && sz < SZ) S[row * SZ + sz] = pre[r][z];
+                }
+            }
+        } else {
+            for (int row = ty; row < rows; row += TY) {
+                const int sx = row / SY, sy = row - sx * SY;
+                const cx<R> *sp = g.p + (int64_t)(sx0 + sx) * g.s0 + (int64_t)(sy0 + sy) * g.s1 + sz0;
+                for (int sz = tz; sz < SZ; sz += TZ) S[row * SZ + sz] = sp[sz];
+            }
         }
         __syncthreads();
+        if (i + 1 < NVP_MAX_FIELDS && i + 1 < src.nf && !src.f[i + 1 < NVP_MAX_FIELDS ? i + 1 : i].identity) {
+            const FieldDev<R> &gn = src.f[i + 1 < NVP_MAX_FIELDS ? i + 1 : i];
+            const Block nb = block_of(gn);
+            if (fits(nb)) {
+#pragma unroll
+                for (int r = 0; r < PR; ++r) {
+                    const int row = ty + r * TY;
+                    const int sx = row / nb.SY, sy = row - sx * nb.SY;
+                    const cx<R> *sp =
+                        gn.p + (int64_t)(nb.sx0 + sx) * gn.s0 + (int64_t)(nb.sy0 + sy) * gn.s1 + nb.sz0;
+#pragma unroll
+                    for (int z = 0; z < PZ; ++z) {
+                        const int sz = tz + z * TZ;
+                        if (row < nb.SX * nb.SY && sz < nb.SZ) pre[r][z] = sp[sz];
+                    }
+                }
+                pre_field = i + 1;
+            }
+        }
         // z interpolation: T1[row][z] for this thread's z
         for (int row = ty; row < rows; row += TY) {
             cx<R> acc = czero<R>();
