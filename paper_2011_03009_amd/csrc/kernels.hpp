@@ -148,10 +148,11 @@ template <typename R> constexpr bool tw_fits(size_t data_elems, size_t tw_elems)
 // SG: -1 forward, +1 inverse.  MIRROR: the columns hold entries 0..L/2 of even
 // sequences; they are read once into LDS and the transform takes its first
 // stage from there.
-// LDS bytes of a strided workgroup's columns.  The mirror passes (the FP64
-// kernel spectrum) stage their L/2+1 input entries as complex values, then
-// exchange through one real plane, so a column needs about L reals instead of
-// L complex values.
+// LDS bytes of a k_strided workgroup's columns: L complex values per column,
+// except in the mirror passes (the FP64 kernel spectrum), which stage their
+// L/2+1 input entries as complex values and then exchange through one real
+// plane (real parts, then imaginary parts), so that a column needs about L
+// reals.  (The same split measured slower for the complex64 passes.)
 template <typename R, int L, int T, bool MIRROR> constexpr size_t strided_data_bytes() {
     if constexpr (MIRROR) {
         const size_t a = (size_t)T * L * sizeof(R), b = (size_t)T * (L / 2 + 1) * sizeof(cx<R>);
@@ -175,7 +176,6 @@ k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, int64_t inner) {
     const int64_t col = (int64_t)blockIdx.x * T + c;
     const int64_t o = blockIdx.y;
     const bool act = col < inner;
-    auto ref = [&](int m) -> cx<R> & { return lds[m * T + c]; };
     auto store = [&](int m, cx<R> v) {
         if (act) st(o, col, m, v);
     };
@@ -206,7 +206,7 @@ k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, int64_t inner) {
             stage_table<R>(twl, tw, NT);
             __syncthreads();  // the engine reads a stage's twiddles before its LDS exchange
         }
-        F::template compute<SG, ZH, OH>(v, t, twf, store, ref);
+        F::template compute<SG, ZH, OH>(v, t, twf, store, [&](int m) -> cx<R> & { return lds[m * T + c]; });
     }
 }
 

@@ -32,10 +32,16 @@ template <class K> inline hipError_t allow_lds(K kern, size_t bytes) {
                                (int)bytes);
 }
 
-template <typename R, int L, int T, bool MIRROR = false> constexpr size_t strided_lds() {
+template <typename R, int L, int T, bool MIRROR> constexpr size_t strided_lds() {
     constexpr size_t data = strided_data_bytes<R, L, T, MIRROR>();
     return data + (tw_fits<R>(data / sizeof(cx<R>), plan_tw_len(L, false)) ? plan_tw_len(L, false) : 0) *
                       sizeof(cx<R>);
+}
+
+// The fused source passes keep complex columns of L entries in LDS.
+template <typename R, int L, int T> constexpr size_t xsrc_lds() {
+    return ((size_t)T * L + (tw_fits<R>((size_t)T * L, plan_tw_len(L, false)) ? plan_tw_len(L, false) : 0)) *
+           sizeof(cx<R>);
 }
 
 template <typename R, typename Rout, int L, int SG, bool SC, bool MIRROR, int T = strided_cols<R>(L)>
@@ -105,7 +111,7 @@ template <typename R, int L, int K> hipError_t xsrc_impl_k(const SourceArgs &a, 
     ld.Nx = a.Nx;
     ld.Nz = a.Nz;
     St st{static_cast<cx<R> *>(a.out), 0, a.out_ms, L, R(1)};
-    constexpr size_t lds = strided_lds<R, L, T>();
+    constexpr size_t lds = xsrc_lds<R, L, T>();
     dim3 grid((unsigned)((a.inner + T - 1) / T), 1);
     if (a.chunk > 0) {
         auto kern = k_xsrc_staged<R, L, T, K, St>;
