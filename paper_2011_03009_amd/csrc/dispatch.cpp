@@ -53,9 +53,9 @@ hipError_t launch_zconv_c128(int L, void *buf, const void *khat, int64_t Mx, int
 #undef X
 }
 
-hipError_t launch_kz(int L, double2 *out, const int64_t H[3], const int64_t N[3], double h, double kr, double ki,
-                     double self_re, double self_im, const void *tw, hipStream_t s) {
-#define X(n) case n: return kz_impl<n>(out, H, N, h, kr, ki, self_re, self_im, tw, s);
+hipError_t launch_kz(int L, double2 *out, const int64_t H[3], const int64_t N[3], const double2 *ktab,
+                     const void *tw, hipStream_t s) {
+#define X(n) case n: return kz_impl<n>(out, H, N, ktab, tw, s);
     NVP_DISPATCH()
 #undef X
 }

@@ -13,7 +13,6 @@ template <typename R, int L>
 hipError_t zconv_impl(void *, const void *, int64_t, int64_t, int, const void *, int, hipStream_t);
 
 template <int L>
-hipError_t kz_impl(double2 *, const int64_t[3], const int64_t[3], double, double, double, double, double, const void *,
-                   hipStream_t);
+hipError_t kz_impl(double2 *, const int64_t[3], const int64_t[3], const double2 *, const void *, hipStream_t);
 
 }  // namespace nvp

@@ -549,14 +549,15 @@ k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int
 
 // First pass of the kernel spectrum, fused with the kernel's tabulation: one
 // octant row (i, j) per pencil.  The row's Hz = L/2+1 values of K at offsets
-// (i, j, k) -- h^3 G_k(|d| h) of equation "quad", the self value at the
-// origin, zero for k >= Nz or beyond the grid in x or y (the embedding is
-// exact for M >= 2N - 1) -- are computed into LDS in FP64, then the FFT of the
-// even extension to length L is written back as the row's first Hz outputs.
+// (i, j, k) -- ktab[i^2 + j^2 + k^2] (h^3 G_k(|d| h) of equation "quad", the
+// self value at the origin), zero for k >= Nz or beyond the grid in x or y (the
+// embedding is exact for M >= 2N - 1) -- are gathered into LDS in FP64, then
+// the FFT of the even extension to length L is written back as the row's first
+// Hz outputs.
 template <int L, int PW>
 __global__ void __launch_bounds__(PW *plan_threads(L))
-k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, int64_t Nz, double h, double kr,
-     double ki, double2 self, const double2 *__restrict__ tw) {
+k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, int64_t Nz,
+     const double2 *__restrict__ ktab, const double2 *__restrict__ tw) {
     using F = Fft<double, L, false, true>;
     constexpr int HZ = L / 2 + 1;
     constexpr int SL = slot_len<double>(L);
@@ -574,17 +575,7 @@ k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, 
 #pragma unroll 1
     for (int k = t; k < HZ; k += F::P) {
         double2 v = make_double2(0.0, 0.0);
-        if (act && i < Nx && jj < Ny && k < Nz) {
-            if (i == 0 && jj == 0 && k == 0) {
-                v = self;
-            } else {
-                const double d = h * sqrt((double)(i * i + jj * jj + (int64_t)k * k));
-                const double mag = h * h * h * exp(-ki * d) / (4.0 * M_PI * d);
-                double sn, cs;
-                sincos(kr * d, &sn, &cs);
-                v = make_double2(mag * cs, mag * sn);
-            }
-        }
+        if (act && i < Nx && jj < Ny && k < Nz) v = ktab[i * i + jj * jj + (int64_t)k * k];
         my[padded<double>(k)] = v;
     }
     wave_sync();

@@ -80,9 +80,13 @@ hipError_t launch_zconv_c64(int L, void *buf, const void *khat, int64_t Mx, int6
 hipError_t launch_zconv_c128(int L, void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw,
                              int quads, hipStream_t s);
 
-// Kernel tabulation fused with the first (z) FP64 pass of the kernel spectrum;
-// writes the octant [Hx][Hy][Hz] (rows octant_row(L) apart) at `out`.
-hipError_t launch_kz(int L, double2 *out, const int64_t H[3], const int64_t N[3], double h, double kr, double ki,
-                     double self_re, double self_im, const void *tw, hipStream_t s);
+// The kernel by squared integer distance: ktab[q], q < n (see k_kradial).
+hipError_t launch_kradial(double2 *ktab, int64_t n, double h, double kr, double ki, double self_re, double self_im,
+                          hipStream_t s);
+// Kernel tabulation (gathered from ktab) fused with the first (z) FP64 pass of
+// the kernel spectrum; writes the octant [Hx][Hy][Hz] (rows octant_row(L)
+// apart) at `out`.
+hipError_t launch_kz(int L, double2 *out, const int64_t H[3], const int64_t N[3], const double2 *ktab,
+                     const void *tw, hipStream_t s);
 
 }  // namespace nvp

@@ -160,8 +160,8 @@ hipError_t zconv_impl(void *buf, const void *khat, int64_t Mx, int64_t My, int N
 }
 
 template <int L>
-hipError_t kz_impl(double2 *out, const int64_t H[3], const int64_t N[3], double h, double kr, double ki,
-                   double self_re, double self_im, const void *tw, hipStream_t s) {
+hipError_t kz_impl(double2 *out, const int64_t H[3], const int64_t N[3], const double2 *ktab, const void *tw,
+                   hipStream_t s) {
     constexpr int PW = contig_pencils<double>(L);
     auto kern = k_kz<L, PW>;
     constexpr size_t lds = ((size_t)PW * slot_len<double>(L) + plan_tw_len(L, false)) * sizeof(double2);
@@ -169,8 +169,7 @@ hipError_t kz_impl(double2 *out, const int64_t H[3], const int64_t N[3], double 
     if (attr != hipSuccess) return attr;
     const int64_t rows = H[0] * H[1];
     hipLaunchKernelGGL(kern, dim3((unsigned)((rows + PW - 1) / PW)), dim3(PW * plan_threads(L)), lds, s, out, H[0],
-                       H[1], N[0], N[1], N[2], h, kr, ki, make_double2(self_re, self_im),
-                       static_cast<const double2 *>(tw));
+                       H[1], N[0], N[1], N[2], ktab, static_cast<const double2 *>(tw));
     return hipGetLastError();
 }
 

@@ -264,13 +264,20 @@ struct Timer {
 
 // ------------------------------------------------------------------ kernel spectrum
 
+// Entries of the kernel-by-squared-distance table of grid g: every |d|^2 of
+// an offset inside the grid.
+int64_t radial_entries(const nvp_grid *g) {
+    return (g->n[0] - 1) * (g->n[0] - 1) + (g->n[1] - 1) * (g->n[1] - 1) + (g->n[2] - 1) * (g->n[2] - 1) + 1;
+}
+
 // Octant of the FP64 DFT of the circulant-embedded kernel, stored as
 // [Mx/2+1][My/2+1][Mz/2+1] (rows padded to octant_row(Mz)) in the plan
-// precision at `khat`.  `scratch` holds the FP64 octant during the three passes.
+// precision at `khat`.  `scratch` holds the FP64 octant during the three
+// passes, `ktab` the kernel by squared distance (radial_entries(g) FP64 values).
 nvp_status kernel_spectrum(nvp_ctx *ctx, nvp_plan *timed, double kr, double ki, const nvp_grid *g,
-                           const int64_t M[3], nvp_prec prec, void *khat, void *scratch) {
+                           const int64_t M[3], nvp_prec prec, void *khat, void *scratch, void *ktab) {
     const int64_t H[3] = {M[0] / 2 + 1, M[1] / 2 + 1, M[2] / 2 + 1};
-    double sr, si;
+    double sr, si;  // self voxel
     self_cell(kr, ki, g->h, &sr, &si);
     const void *tw;
     nvp_status st;
@@ -278,8 +285,10 @@ nvp_status kernel_spectrum(nvp_ctx *ctx, nvp_plan *timed, double kr, double ki, 
     if ((st = twiddles(ctx, (int)M[2], true, &tw))) return st;
     {
         Timer t(timed, NVP_T_KTAB);
-        NVP_HIP(ctx, nvp::launch_kz((int)M[2], static_cast<double2 *>(scratch), H, g->n, g->h, kr, ki, sr, si, tw,
-                                    ctx->stream));
+        NVP_HIP(ctx, nvp::launch_kradial(static_cast<double2 *>(ktab), radial_entries(g), g->h, kr, ki, sr, si,
+                                         ctx->stream));
+        NVP_HIP(ctx, nvp::launch_kz((int)M[2], static_cast<double2 *>(scratch), H, g->n,
+                                    static_cast<const double2 *>(ktab), tw, ctx->stream));
     }
     Timer t(timed, NVP_T_KFFT);
     const int64_t HZS = nvp::octant_row(M[2]);  // padded row stride along z
@@ -382,7 +391,12 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
     return NVP_OK;
 }
 
-size_t bytesA(const nvp_grid *g, const int64_t M[3], nvp_prec p) { return (size_t)M[0] * g->n[1] * g->n[2] * csize(p); }
+// Buffer A: the x-pass buffer [Mx][Ny][Nz]; before the convolution it holds
+// the kernel-by-squared-distance table of the kernel spectrum.
+size_t bytesA(const nvp_grid *g, const int64_t M[3], nvp_prec p) {
+    const size_t a = (size_t)M[0] * g->n[1] * g->n[2] * csize(p), t = (size_t)radial_entries(g) * 16;
+    return a > t ? a : t;
+}
 size_t bytesB(const nvp_grid *g, const int64_t M[3], nvp_prec p) {
     size_t b = (size_t)M[0] * M[1] * g->n[2] * csize(p);
     size_t k = kscratch_bytes(M);
@@ -644,7 +658,7 @@ nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nv
             c = VpCache{};
             return fail(ctx, NVP_E_NOMEM, "nvp_volume_potential: device allocation failed");
         }
-        if ((st = kernel_spectrum(ctx, nullptr, k_re, k_im, g, M, prec, c.khat, c.B))) return st;
+        if ((st = kernel_spectrum(ctx, nullptr, k_re, k_im, g, M, prec, c.khat, c.B, c.A))) return st;
         c.valid = true;
         c.kr = k_re;
         c.ki = k_im;
@@ -836,7 +850,7 @@ nvp_status nvp_execute_harmonic(nvp_plan *plan, int n, const void *const *fields
     Harm &h = plan->h[n - 2];
     nvp_status st;
     if (!h.khat_ok || !plan->cache) {
-        if ((st = kernel_spectrum(ctx, plan, h.kr, h.ki, &h.g, h.M, plan->prec, h.khat, plan->B))) return st;
+        if ((st = kernel_spectrum(ctx, plan, h.kr, h.ki, &h.g, h.M, plan->prec, h.khat, plan->B, plan->A))) return st;
         h.khat_ok = true;
     }
     SourceArgs src = source_args(plan, n, fields);
