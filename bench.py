@@ -221,7 +221,16 @@ def batch_bench(P, torch, ctx, W, steps, log):
     res["tuned_graph_ms"] = timed(steps)
     b.set_graph(False)
     res["tuned_eager_ms"] = timed(steps)
-    best = min(res["eager_ms"], res["graph_ms"], res["tuned_graph_ms"], res["tuned_eager_ms"])
+    # multi-task launches: each pass of each harmonic level as one launch per transform length
+    b.set_grouped(True)
+    b.set_graph(True, 1)
+    b.execute(p1s, outs)
+    torch.cuda.synchronize()
+    res["grouped_graph_ms"] = timed(steps)
+    b.set_graph(False)
+    res["grouped_eager_ms"] = timed(steps)
+    best = min(res["eager_ms"], res["graph_ms"], res["tuned_graph_ms"], res["tuned_eager_ms"],
+               res["grouped_graph_ms"], res["grouped_eager_ms"])
     res["voxels_per_s"] = vox / (best * 1e-3)
     b.close()
     log("bench: batched %s" % res)

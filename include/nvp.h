@@ -268,6 +268,14 @@ nvp_status nvp_batch_outputs(const nvp_batch *batch, int64_t *n_out);
  * recorded again whenever the buffer pointers change.  enable = 0: every
  * execution launches the kernels one by one on the context stream. */
 nvp_status nvp_batch_set_graph(nvp_batch *batch, int enable, int branches);
+/* enable != 0: run the batch level by level (harmonic n of every problem that
+ * has it) with each pass of the convolution as one multi-task launch over the
+ * problems that share its transform length (a task table in device memory
+ * maps each workgroup to its problem), instead of one launch per problem;
+ * inside a graph when nvp_batch_set_graph enables one (as by default).
+ * Problems whose harmonic takes the fused source path run that harmonic on
+ * their own.  Results are the same bits as per-problem execution. */
+nvp_status nvp_batch_set_grouped(nvp_batch *batch, int enable);
 /* nvp_plan_autotune for every problem, sharing one cache (identical shapes
  * are timed once). */
 nvp_status nvp_batch_autotune(nvp_batch *batch, const char *cache_path, int reps);

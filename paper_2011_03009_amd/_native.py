@@ -60,6 +60,7 @@ SIGNATURES = {
     "nvp_batch_create": (_st, [_vp, _i, ctypes.POINTER(Problem), _i, _i, ctypes.POINTER(_vp)]),
     "nvp_batch_outputs": (_st, [_vp, _i64p]),
     "nvp_batch_set_graph": (_st, [_vp, _i, _i]),
+    "nvp_batch_set_grouped": (_st, [_vp, _i]),
     "nvp_batch_autotune": (_st, [_vp, ctypes.c_char_p, _i]),
     "nvp_batch_execute": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "nvp_batch_destroy": (_st, [_vp]),

@@ -60,4 +60,32 @@ hipError_t launch_kz(int L, double2 *out, const int64_t H[3], const int64_t N[3]
 #undef X
 }
 
+hipError_t launch_strided_multi_c64(int L, const StridedTaskArgs *tasks, int ntasks, int64_t blocks, int sign,
+                                    int scaled, const void *tw, hipStream_t s) {
+#define X(n) case n: return strided_multi_impl<float, n>(tasks, ntasks, blocks, sign, scaled, tw, s);
+    NVP_DISPATCH()
+#undef X
+}
+
+hipError_t launch_strided_multi_c128(int L, const StridedTaskArgs *tasks, int ntasks, int64_t blocks, int sign,
+                                     int scaled, const void *tw, hipStream_t s) {
+#define X(n) case n: return strided_multi_impl<double, n>(tasks, ntasks, blocks, sign, scaled, tw, s);
+    NVP_DISPATCH()
+#undef X
+}
+
+hipError_t launch_zconv_multi_c64(int L, const ZconvTaskArgs *tasks, int ntasks, int64_t blocks, const void *tw,
+                                  hipStream_t s) {
+#define X(n) case n: return zconv_multi_impl<float, n>(tasks, ntasks, blocks, tw, s);
+    NVP_DISPATCH()
+#undef X
+}
+
+hipError_t launch_zconv_multi_c128(int L, const ZconvTaskArgs *tasks, int ntasks, int64_t blocks, const void *tw,
+                                   hipStream_t s) {
+#define X(n) case n: return zconv_multi_impl<double, n>(tasks, ntasks, blocks, tw, s);
+    NVP_DISPATCH()
+#undef X
+}
+
 }  // namespace nvp

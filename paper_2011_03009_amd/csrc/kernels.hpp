@@ -162,9 +162,10 @@ template <typename R, int L, int T, bool MIRROR> constexpr size_t strided_data_b
     }
 }
 
+// One workgroup's tile: columns bx T .. bx T + T-1 of outer index o.
 template <typename R, int L, int T, int SG, bool MIRROR, class Ld, class St>
-__global__ void __launch_bounds__(T *plan_threads(L))
-k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, int64_t inner) {
+__device__ __forceinline__ void strided_tile(Ld ld, St st, const cx<R> *__restrict__ tw, int64_t inner, int64_t bx,
+                                             int64_t o) {
     using F = Fft<R, L>;
     constexpr int NT = plan_tw_len(L, false);
     constexpr size_t DATA = strided_data_bytes<R, L, T, MIRROR>();
@@ -173,8 +174,7 @@ k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, int64_t inner) {
     cx<R> *twl = reinterpret_cast<cx<R> *>(nvp_smem + DATA);
     auto twf = [&](int e) { return TWL ? twl[e] : tw[e]; };
     const int tid = threadIdx.x, c = tid % T, t = tid / T;
-    const int64_t col = (int64_t)blockIdx.x * T + c;
-    const int64_t o = blockIdx.y;
+    const int64_t col = bx * T + c;
     const bool act = col < inner;
     auto store = [&](int m, cx<R> v) {
         if (act) st(o, col, m, v);
@@ -208,6 +208,29 @@ k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, int64_t inner) {
         }
         F::template compute<SG, ZH, OH>(v, t, twf, store, [&](int m) -> cx<R> & { return lds[m * T + c]; });
     }
+}
+
+template <typename R, int L, int T, int SG, bool MIRROR, class Ld, class St>
+__global__ void __launch_bounds__(T *plan_threads(L))
+k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, int64_t inner) {
+    strided_tile<R, L, T, SG, MIRROR>(ld, st, tw, inner, blockIdx.x, blockIdx.y);
+}
+
+// Multi-task launch (batches): the pass of several problems of the same
+// transform length in one grid.  Task k owns blocks [first_k, first_{k+1});
+// its tile (bx, o) follows from the block's offset in that range.  Each
+// task's arguments are read once per workgroup (uniform loads).
+template <typename R, int L, int T, int SG, bool SC>
+__global__ void __launch_bounds__(T *plan_threads(L))
+k_strided_multi(const StridedTaskArgs *__restrict__ tasks, int ntasks, const cx<R> *__restrict__ tw) {
+    const int64_t b = blockIdx.x;
+    int k = 0;
+    while (k + 1 < ntasks && tasks[k + 1].first <= b) ++k;
+    const StridedTaskArgs a = tasks[k];
+    const int64_t local = b - a.first;
+    LdPlain<R, L> ld{static_cast<const cx<R> *>(a.in), a.in_os, a.in_ms, a.n_in, 0};
+    StPlain<R, R, SC> st{static_cast<cx<R> *>(a.out), a.out_os, a.out_ms, a.n_out, (R)a.scale};
+    strided_tile<R, L, T, SG, false>(ld, st, tw, a.inner, local % a.tiles, local / a.tiles);
 }
 
 // Forward x pass with the source build fused in front, direct form: each
@@ -505,9 +528,9 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
 // inverse runs the radix plan in reverse order, so the forward outputs feed
 // it straight from registers, where the product with K^ is taken.
 template <typename R, int L, int QW>
-__global__ void __launch_bounds__(4 * QW * plan_threads(L))
-k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int64_t My, int Nz, int64_t Hy,
-        int64_t n_quads, const cx<R> *__restrict__ tw) {
+__device__ __forceinline__ void zconv_block(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx,
+                                            int64_t My, int Nz, int64_t Hy, int64_t n_quads,
+                                            const cx<R> *__restrict__ tw, int64_t block) {
     using F = Fft<R, L, false, true>;
     using G = Fft<R, L, true, true>;
     constexpr int E = F::E;
@@ -515,7 +538,7 @@ k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int
     constexpr int SL = slot_len<R>(L);
     cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
     const int tid = threadIdx.x, t = tid % F::P, slot = tid / F::P, j = slot & 3;
-    const int64_t quad = (int64_t)blockIdx.x * QW + (slot >> 2);
+    const int64_t quad = block * QW + (slot >> 2);
     const bool valid = quad < n_quads;
     const int64_t kx = valid ? quad / Hy : 0, ky = valid ? quad % Hy : 0;
     const int64_t px = (j & 1) ? (Mx - kx) % Mx : kx;
@@ -545,6 +568,25 @@ k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int
                                if (act && m < Nz) pen[m] = x;
                            },
                            ref);
+}
+
+template <typename R, int L, int QW>
+__global__ void __launch_bounds__(4 * QW * plan_threads(L))
+k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int64_t My, int Nz, int64_t Hy,
+        int64_t n_quads, const cx<R> *__restrict__ tw) {
+    zconv_block<R, L, QW>(buf, khat, Mx, My, Nz, Hy, n_quads, tw, blockIdx.x);
+}
+
+// Multi-task z pass (batches), laid out like k_strided_multi.
+template <typename R, int L, int QW>
+__global__ void __launch_bounds__(4 * QW * plan_threads(L))
+k_zconv_multi(const ZconvTaskArgs *__restrict__ tasks, int ntasks, const cx<R> *__restrict__ tw) {
+    const int64_t b = blockIdx.x;
+    int k = 0;
+    while (k + 1 < ntasks && tasks[k + 1].first <= b) ++k;
+    const ZconvTaskArgs a = tasks[k];
+    zconv_block<R, L, QW>(static_cast<cx<R> *>(a.buf), static_cast<const cx<R> *>(a.khat), a.Mx, a.My, a.Nz, a.Hy,
+                          a.n_quads, tw, b - a.first);
 }
 
 // First pass of the kernel spectrum, fused with the kernel's tabulation: one

@@ -38,6 +38,29 @@ struct StridedArgs {
     int tile;  // 0: default columns per workgroup, 1: half as many (not for mirror or mixed precision)
 };
 
+// One problem's strided pass in a multi-task launch (batches): the
+// StridedArgs of that pass, its column tiles per outer index and its first
+// block in the grid (tasks sorted by first; the launch has sum tiles * outer
+// blocks).
+struct StridedTaskArgs {
+    const void *in;
+    int64_t in_os, in_ms;
+    int n_in;
+    void *out;
+    int64_t out_os, out_ms;
+    int n_out;
+    double scale;
+    int64_t inner, tiles, first;
+};
+
+// One problem's z pass in a multi-task launch.
+struct ZconvTaskArgs {
+    void *buf;
+    const void *khat;
+    int64_t Mx, My, Hy, n_quads, first;
+    int Nz;
+};
+
 // Field of the fused source build (see LdSource).
 struct FieldArgs {
     const void *p;
@@ -79,6 +102,22 @@ hipError_t launch_zconv_c64(int L, void *buf, const void *khat, int64_t Mx, int6
                             int quads, hipStream_t s);
 hipError_t launch_zconv_c128(int L, void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw,
                              int quads, hipStream_t s);
+
+// Multi-task launches (tasks_dev: device array of ntasks entries; blocks: the
+// grid size they cover).  sign -1 forward, +1 inverse; scaled: inverse with
+// the per-task scale.
+hipError_t launch_strided_multi_c64(int L, const StridedTaskArgs *tasks_dev, int ntasks, int64_t blocks, int sign,
+                                    int scaled, const void *tw, hipStream_t s);
+hipError_t launch_strided_multi_c128(int L, const StridedTaskArgs *tasks_dev, int ntasks, int64_t blocks, int sign,
+                                     int scaled, const void *tw, hipStream_t s);
+hipError_t launch_zconv_multi_c64(int L, const ZconvTaskArgs *tasks_dev, int ntasks, int64_t blocks, const void *tw,
+                                  hipStream_t s);
+hipError_t launch_zconv_multi_c128(int L, const ZconvTaskArgs *tasks_dev, int ntasks, int64_t blocks, const void *tw,
+                                   hipStream_t s);
+// Launch geometry of the default variants: columns per strided workgroup and
+// pencil quads per z-pass workgroup.
+int strided_tile_cols(int L, int dbl);
+int zconv_quads_per_block(int L, int dbl);
 
 // The kernel by squared integer distance: ktab[q], q < n (see k_kradial).
 hipError_t launch_kradial(double2 *ktab, int64_t n, double h, double kr, double ki, double self_re, double self_im,

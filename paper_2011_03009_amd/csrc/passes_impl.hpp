@@ -148,13 +148,18 @@ hipError_t zconv_qw(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz,
     return hipGetLastError();
 }
 
+// Pencil quads per z-pass workgroup by default: up to 256 threads and 80 KiB of LDS.
+template <typename R, int L> constexpr int zconv_default_qw() {
+    return (4 * plan_threads(L) <= 128 && 8 * slot_len<R>(L) * (int)sizeof(cx<R>) <= 81920) ? 2 : 1;
+}
+
 // quads: pencil quads per workgroup, 0 for the default (2 when that keeps the
 // workgroup within 256 threads and 80 KiB of LDS, else 1), or 1 / 2 forced
 // (2 falls back to 1 where it does not fit).
 template <typename R, int L>
 hipError_t zconv_impl(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, int quads,
                       hipStream_t s) {
-    constexpr int QW = (4 * plan_threads(L) <= 128 && 8 * slot_len<R>(L) * (int)sizeof(cx<R>) <= 81920) ? 2 : 1;
+    constexpr int QW = zconv_default_qw<R, L>();
     if (quads == 1 || zconv_quads_override() == 1) return zconv_qw<R, L, 1>(buf, khat, Mx, My, Nz, tw, s);
     return zconv_qw<R, L, QW>(buf, khat, Mx, My, Nz, tw, s);
 }
@@ -170,6 +175,40 @@ hipError_t kz_impl(double2 *out, const int64_t H[3], const int64_t N[3], const d
     const int64_t rows = H[0] * H[1];
     hipLaunchKernelGGL(kern, dim3((unsigned)((rows + PW - 1) / PW)), dim3(PW * plan_threads(L)), lds, s, out, H[0],
                        H[1], N[0], N[1], N[2], ktab, static_cast<const double2 *>(tw));
+    return hipGetLastError();
+}
+
+template <typename R, int L, int SG, bool SC>
+hipError_t strided_multi_v(const StridedTaskArgs *tasks, int ntasks, int64_t blocks, const void *tw, hipStream_t s) {
+    constexpr int T = strided_cols<R>(L);
+    auto kern = k_strided_multi<R, L, T, SG, SC>;
+    constexpr size_t lds = strided_lds<R, L, T, false>();
+    static const hipError_t attr = allow_lds(kern, lds);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(T * plan_threads(L)), lds, s, tasks, ntasks,
+                       static_cast<const cx<R> *>(tw));
+    return hipGetLastError();
+}
+
+template <typename R, int L>
+hipError_t strided_multi_impl(const StridedTaskArgs *tasks, int ntasks, int64_t blocks, int sign, int scaled,
+                              const void *tw, hipStream_t s) {
+    if (ntasks < 1 || blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (sign < 0) return strided_multi_v<R, L, -1, false>(tasks, ntasks, blocks, tw, s);
+    if (!scaled) return strided_multi_v<R, L, 1, false>(tasks, ntasks, blocks, tw, s);
+    return strided_multi_v<R, L, 1, true>(tasks, ntasks, blocks, tw, s);
+}
+
+template <typename R, int L>
+hipError_t zconv_multi_impl(const ZconvTaskArgs *tasks, int ntasks, int64_t blocks, const void *tw, hipStream_t s) {
+    if (ntasks < 1 || blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    constexpr int QW = zconv_default_qw<R, L>();
+    auto kern = k_zconv_multi<R, L, QW>;
+    constexpr size_t lds = (size_t)4 * QW * slot_len<R>(L) * sizeof(cx<R>);
+    static const hipError_t attr = allow_lds(kern, lds);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(4 * QW * plan_threads(L)), lds, s, tasks, ntasks,
+                       static_cast<const cx<R> *>(tw));
     return hipGetLastError();
 }
 

@@ -1086,6 +1086,9 @@ struct nvp_batch {
     std::vector<const void *> cap_in;
     std::vector<void *> cap_out;
     bool warm = false;
+    bool grouped = false;        // multi-task launches per pass and transform length
+    void *tasks = nullptr;       // device task tables of the grouped schedule
+    size_t tasks_bytes = 0;
 };
 
 namespace {
@@ -1101,6 +1104,8 @@ void drop_graph(nvp_batch *b) {
 
 void free_batch(nvp_batch *b) {
     drop_graph(b);
+    if (b->tasks) (void)hipFree(b->tasks);
+    b->tasks = nullptr;
     for (auto *p : b->plans) nvp_plan_destroy(p);
     for (auto s : b->streams) (void)hipStreamDestroy(s);
     if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -1119,13 +1124,197 @@ nvp_status run_eager(nvp_batch *b, const void *const *p1, void *const *pn) {
     return NVP_OK;
 }
 
+// ------------------------------------------------------------------ grouped schedule
+
+// One step of the grouped schedule: a problem's source build or whole
+// harmonic, or one multi-task launch of a pass over the problems whose
+// transform length along that pass's axis is L.
+struct GroupStep {
+    int kind = 0;  // 0 source build, 1 strided pass, 2 z pass, 3 whole harmonic (fused source path)
+    int problem = 0, n = 0;
+    int L = 0, sign = 0, scaled = 0;
+    int ntasks = 0;
+    int64_t blocks = 0;
+    size_t offset = 0;  // byte offset of the step's tasks in the task buffer
+};
+
+// The pass kinds of one harmonic, in launch order.
+enum { P_XFWD, P_YFWD, P_ZCONV, P_YINV, P_XINV };
+
+// Builds the grouped schedule for the given buffers and uploads its task
+// tables.  Level by level (harmonic n of every problem that has it): the
+// source builds, then each pass as one launch per transform length.
+nvp_status build_grouped(nvp_batch *b, const void *const *p1, void *const *pn, std::vector<GroupStep> &steps) {
+    nvp_ctx *ctx = b->ctx;
+    const bool dbl = b->plans[0]->prec == NVP_C128;
+    int maxn = 0;
+    for (auto *p : b->plans) maxn = std::max(maxn, p->n_harm);
+    std::vector<unsigned char> host;
+    auto push = [&](const void *data, size_t bytes) {
+        const size_t o = (host.size() + 255) & ~(size_t)255;
+        host.resize(o + bytes);
+        std::memcpy(host.data() + o, data, bytes);
+        return o;
+    };
+    for (int n = 2; n <= maxn; ++n) {
+        std::vector<int> act;
+        for (int i = 0; i < (int)b->plans.size(); ++i) {
+            nvp_plan *p = b->plans[i];
+            if (n > p->n_harm) continue;
+            if (!p->use_source_kernel || p->h[n - 2].src_lds <= 0 || p->h[n - 2].tune.src == 0) {
+                GroupStep g;
+                g.kind = 3;
+                g.problem = i;
+                g.n = n;
+                steps.push_back(g);
+                continue;
+            }
+            act.push_back(i);
+            GroupStep g;
+            g.kind = 0;
+            g.problem = i;
+            g.n = n;
+            steps.push_back(g);
+        }
+        for (int pass = P_XFWD; pass <= P_XINV; ++pass) {
+            std::map<int, std::vector<int>> by_len;
+            for (int i : act) {
+                const Harm &h = b->plans[i]->h[n - 2];
+                const int L = (int)(pass == P_XFWD || pass == P_XINV ? h.M[0] : pass == P_ZCONV ? h.M[2] : h.M[1]);
+                by_len[L].push_back(i);
+            }
+            for (auto &kv : by_len) {
+                const int L = kv.first;
+                GroupStep g;
+                g.L = L;
+                g.ntasks = (int)kv.second.size();
+                if (pass == P_ZCONV) {
+                    g.kind = 2;
+                    const int qw = nvp::zconv_quads_per_block(L, dbl);
+                    std::vector<nvp::ZconvTaskArgs> t;
+                    for (int i : kv.second) {
+                        nvp_plan *p = b->plans[i];
+                        const Harm &h = p->h[n - 2];
+                        nvp::ZconvTaskArgs a{};
+                        a.buf = p->B;
+                        a.khat = h.khat;
+                        a.Mx = h.M[0];
+                        a.My = h.M[1];
+                        a.Hy = h.M[1] / 2 + 1;
+                        a.n_quads = (h.M[0] / 2 + 1) * a.Hy;
+                        a.Nz = (int)h.g.n[2];
+                        a.first = g.blocks;
+                        g.blocks += (a.n_quads + qw - 1) / qw;
+                        t.push_back(a);
+                    }
+                    g.offset = push(t.data(), t.size() * sizeof(t[0]));
+                } else {
+                    g.kind = 1;
+                    g.sign = pass <= P_YFWD ? -1 : 1;
+                    g.scaled = pass == P_XINV;
+                    const int T = nvp::strided_tile_cols(L, dbl);
+                    std::vector<nvp::StridedTaskArgs> t;
+                    for (int i : kv.second) {
+                        nvp_plan *p = b->plans[i];
+                        const Harm &h = p->h[n - 2];
+                        const int64_t Nx = h.g.n[0], Ny = h.g.n[1], Nz = h.g.n[2];
+                        const int64_t Mx = h.M[0], My = h.M[1];
+                        nvp::StridedTaskArgs a{};
+                        int64_t outer = 1;
+                        a.scale = 1.0;
+                        if (pass == P_XFWD) {
+                            a.in = p->A; a.in_os = 0; a.in_ms = Ny * Nz; a.n_in = (int)Nx;
+                            a.out = p->A; a.out_os = 0; a.out_ms = Ny * Nz; a.n_out = (int)Mx;
+                            a.inner = Ny * Nz;
+                        } else if (pass == P_YFWD) {
+                            a.in = p->A; a.in_os = Ny * Nz; a.in_ms = Nz; a.n_in = (int)Ny;
+                            a.out = p->B; a.out_os = My * Nz; a.out_ms = Nz; a.n_out = (int)My;
+                            a.inner = Nz;
+                            outer = Mx;
+                        } else if (pass == P_YINV) {
+                            a.in = p->B; a.in_os = My * Nz; a.in_ms = Nz; a.n_in = (int)My;
+                            a.out = p->A; a.out_os = Ny * Nz; a.out_ms = Nz; a.n_out = (int)Ny;
+                            a.inner = Nz;
+                            outer = Mx;
+                        } else {
+                            a.in = p->A; a.in_os = 0; a.in_ms = Ny * Nz; a.n_in = (int)Mx;
+                            a.out = pn[b->off[i] + n - 2]; a.out_os = 0; a.out_ms = Ny * Nz; a.n_out = (int)Nx;
+                            a.scale = h.Cn / ((double)h.M[0] * (double)h.M[1] * (double)h.M[2]);
+                            a.inner = Ny * Nz;
+                        }
+                        a.tiles = (a.inner + T - 1) / T;
+                        a.first = g.blocks;
+                        g.blocks += a.tiles * outer;
+                        t.push_back(a);
+                    }
+                    g.offset = push(t.data(), t.size() * sizeof(t[0]));
+                }
+                if (g.blocks > 0x7fffffff) return fail(ctx, NVP_E_UNSUPPORTED, "grouped pass exceeds the grid limit");
+                steps.push_back(g);
+            }
+        }
+    }
+    (void)p1;
+    if (b->tasks && b->tasks_bytes < host.size()) {
+        (void)hipFree(b->tasks);
+        b->tasks = nullptr;
+    }
+    if (!b->tasks && !host.empty()) {
+        NVP_HIP(ctx, hipMalloc(&b->tasks, host.size()));
+        b->tasks_bytes = host.size();
+    }
+    if (!host.empty()) NVP_HIP(ctx, hipMemcpy(b->tasks, host.data(), host.size(), hipMemcpyHostToDevice));
+    return NVP_OK;
+}
+
+// Issues the grouped schedule on the context stream.
+nvp_status run_grouped(nvp_batch *b, const std::vector<GroupStep> &steps, const void *const *p1, void *const *pn) {
+    nvp_ctx *ctx = b->ctx;
+    const bool dbl = b->plans[0]->prec == NVP_C128;
+    const unsigned char *tb = static_cast<const unsigned char *>(b->tasks);
+    for (const GroupStep &g : steps) {
+        if (g.kind == 0 || g.kind == 3) {
+            nvp_plan *p = b->plans[g.problem];
+            std::vector<const void *> fields(g.n - 1);
+            fields[0] = p1[g.problem];
+            for (int m = 2; m < g.n; ++m) fields[m - 1] = pn[b->off[g.problem] + m - 2];
+            if (g.kind == 3) {
+                nvp_status st = nvp_execute_harmonic(p, g.n, fields.data(), pn[b->off[g.problem] + g.n - 2]);
+                if (st) return st;
+                continue;
+            }
+            const Harm &h = p->h[g.n - 2];
+            const SourceArgs src = source_args(p, g.n, fields.data());
+            NVP_HIP(ctx, (dbl ? nvp::launch_source_c128 : nvp::launch_source_c64)(src, p->A, (int)h.g.n[1], h.src_lds,
+                                                                                ctx->stream));
+            continue;
+        }
+        const void *tw;
+        nvp_status st = twiddles(ctx, g.L, dbl, &tw);
+        if (st) return st;
+        if (g.kind == 1) {
+            const auto *t = reinterpret_cast<const nvp::StridedTaskArgs *>(tb + g.offset);
+            NVP_HIP(ctx, (dbl ? nvp::launch_strided_multi_c128 : nvp::launch_strided_multi_c64)(
+                             g.L, t, g.ntasks, g.blocks, g.sign, g.scaled, tw, ctx->stream));
+        } else {
+            const auto *t = reinterpret_cast<const nvp::ZconvTaskArgs *>(tb + g.offset);
+            NVP_HIP(ctx, (dbl ? nvp::launch_zconv_multi_c128 : nvp::launch_zconv_multi_c64)(g.L, t, g.ntasks, g.blocks,
+                                                                                          tw, ctx->stream));
+        }
+    }
+    return NVP_OK;
+}
+
 // Records every problem's cascade into one graph: problem i on branch
 // i mod branches, each branch a stream forked from and joined back into the
 // recording stream, so independent problems may run concurrently.
+nvp_status capture_grouped(nvp_batch *b, const void *const *p1, void *const *pn);
+
 nvp_status capture(nvp_batch *b, const void *const *p1, void *const *pn) {
     nvp_ctx *ctx = b->ctx;
-    const int S = std::min<int>(b->branches, (int)b->plans.size());
     if (!b->cap) NVP_HIP(ctx, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    if (b->grouped) return capture_grouped(b, p1, pn);
+    const int S = std::min<int>(b->branches, (int)b->plans.size());
     while ((int)b->streams.size() < S) {
         hipStream_t s;
         NVP_HIP(ctx, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -1172,9 +1361,47 @@ nvp_status capture(nvp_batch *b, const void *const *p1, void *const *pn) {
     return NVP_OK;
 }
 
+// The grouped schedule recorded as one graph on the recording stream.
+nvp_status capture_grouped(nvp_batch *b, const void *const *p1, void *const *pn) {
+    nvp_ctx *ctx = b->ctx;
+    std::vector<GroupStep> steps;
+    nvp_status st = build_grouped(b, p1, pn, steps);
+    if (st) return st;
+    const hipStream_t user = ctx->stream;
+    NVP_HIP(ctx, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    ctx->stream = b->cap;
+    st = run_grouped(b, steps, p1, pn);
+    ctx->stream = user;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (st == NVP_OK && e != hipSuccess) st = hip_fail(ctx, "hipStreamEndCapture", e);
+    if (st != NVP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(ctx, "hipGraphInstantiate", e);
+    }
+    b->g = g;
+    b->ge = ge;
+    b->cap_in.assign(p1, p1 + b->plans.size());
+    b->cap_out.assign(pn, pn + b->n_out);
+    return NVP_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+nvp_status nvp_batch_set_grouped(nvp_batch *b, int enable) {
+    if (!b) return NVP_E_INVALID;
+    if ((enable != 0) != b->grouped) drop_graph(b);
+    b->grouped = enable != 0;
+    return NVP_OK;
+}
 
 nvp_status nvp_plan_autotune(nvp_plan *plan, const char *cache_path, int reps) {
     if (!plan) return NVP_E_INVALID;
@@ -1262,17 +1489,24 @@ nvp_status nvp_batch_execute(nvp_batch *b, const void *const *p1_dev, void *cons
     for (int64_t i = 0; i < b->n_out; ++i)
         if (!pn_dev[i]) return fail(ctx, NVP_E_INVALID, "nvp_batch_execute: null output");
     NVP_HIP(ctx, hipSetDevice(ctx->device));
-    if (!b->graph || !b->warm) {
-        // eager: also the first run of a graph batch, which computes and caches every
-        // kernel spectrum and twiddle table so that the captured graph holds the
+    if (!b->warm || (!b->graph && !b->grouped)) {
+        // eager: also the first run of a graph or grouped batch, which computes and
+        // caches every kernel spectrum and twiddle table so that later runs hold the
         // convolutions only
         nvp_status st = run_eager(b, p1_dev, pn_dev);
         if (st) return st;
         for (auto *p : b->plans)
             for (auto &h : p->h)
-                if (!h.khat_ok) return NVP_OK;  // kernel cache off: stay eager
+                if (!h.khat_ok || !p->cache) return NVP_OK;  // kernel cache off: stay eager
         b->warm = true;
         return NVP_OK;
+    }
+    if (!b->graph) {
+        // grouped launches without a graph
+        std::vector<GroupStep> steps;
+        nvp_status st = build_grouped(b, p1_dev, pn_dev, steps);
+        if (st) return st;
+        return run_grouped(b, steps, p1_dev, pn_dev);
     }
     const bool same = b->ge && std::equal(b->cap_in.begin(), b->cap_in.end(), p1_dev) &&
                       std::equal(b->cap_out.begin(), b->cap_out.end(), pn_dev);

@@ -314,6 +314,10 @@ class Batch:
     def set_graph(self, enable, branches=4):
         _check(_native.lib().nvp_batch_set_graph(self.handle, int(bool(enable)), branches), self.ctx.handle)
 
+    def set_grouped(self, enable):
+        """Multi-task launches per pass and transform length (level by level over the problems)."""
+        _check(_native.lib().nvp_batch_set_grouped(self.handle, int(bool(enable))), self.ctx.handle)
+
     def autotune(self, cache_path=None, reps=3):
         _check(_native.lib().nvp_batch_autotune(self.handle, cache_path.encode() if cache_path else None, reps),
                self.ctx.handle)

@@ -162,6 +162,35 @@ def test_batch_autotune_then_graph(ctx, tmp_path):
     b.close()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("fused", [False, True])
+def test_grouped_batch_matches_eager(ctx, graph, fused, monkeypatch):
+    """Multi-task launches per pass and length: the same bits as per-problem execution.
+    fused: every harmonic takes the fused source path and so runs on its own."""
+    if fused:
+        monkeypatch.setenv("NVP_FUSED_SOURCE", "1")
+    probs = problems(11, 5)
+    # shared transform lengths: problems 0-3 get the same grids as problem 4
+    for i in range(4):
+        probs[i] = dict(probs[4])
+    p1s = inputs(probs, P.NVP_C64, 40)
+    say("case grouped batch graph=%d fused=%d" % (graph, fused))
+    b = P.Batch(ctx, probs, prec=P.NVP_C64, order=3)
+    b.set_graph(False)
+    ref = [[t.clone() for t in o] for o in b.execute(p1s, b.outputs())]
+    b.set_grouped(True)
+    b.set_graph(graph, 4)
+    outs = b.outputs()
+    for r in range(3):
+        for o in outs:
+            for t in o:
+                t.zero_()
+        b.execute(p1s, outs)
+        torch.cuda.synchronize()
+        assert same(outs, ref), r
+    b.close()
+
+
 def test_batch_errors(ctx):
     probs = problems(2, 4)
     bad = dict(probs[1])
