@@ -284,8 +284,11 @@ def main():
     plan.set_kernel_cache(False)
     outs = [torch.empty(tuple(g.n), dtype=torch.complex64, device=dev) for g in gn]
     log("bench: nested cascade, %d warmup + %d steps" % (a.warmup, a.steps))
-    plan.set_timing(True)
+    # the step: kernel spectra on the plan's second stream, overlapped with the convolutions
     ms = time_steps(torch, plan, p1, outs, a.steps, a.warmup, stream)
+    # per-kernel HIP-event times: every launch in line on the plan's stream
+    plan.set_timing(True)
+    ms_seq = time_steps(torch, plan, p1, outs, a.steps, 1, stream)
     timing = plan.get_timing()
     plan.set_timing(False)
     # conv-only rate: kernel spectra cached
@@ -321,6 +324,7 @@ def main():
                    "voxels_per_step": voxels, "grids": [list(map(int, g.n)) for g in gn],
                    "circulants": [[P.circulant_size(int(v)) for v in g.n] for g in gn]},
         "roofline": roof,
+        "sequential": {"ms_per_step": ms_seq, "note": "every launch in line on one stream (the per-kernel timing run)"},
         "conv_only": {"ms_per_step": ms_conv, "voxels_per_s": voxels / (ms_conv * 1e-3),
                       "five_pass_alg_GBs": conv_gbs, "five_pass_frac": conv_gbs / PEAK_HBM_GBS},
         "per_kernel": per_kind,

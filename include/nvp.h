@@ -134,11 +134,20 @@ nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nv
 nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int n_harm,
                             const nvp_grid *g1, const nvp_grid *gn, nvp_prec prec,
                             int transfer_order, nvp_plan **out);
-/* Device bytes held by the plan (work buffers and kernel spectra). */
+/* Device bytes held by the plan (work buffers, kernel spectra, and the scratch
+ * of the overlapped spectra once used). */
 nvp_status nvp_plan_workspace_bytes(const nvp_plan *plan, size_t *bytes);
 /* 1 (default): keep each harmonic's kernel spectrum after its first use;
  * 0: tabulate and transform the kernel again on every execution. */
 nvp_status nvp_plan_set_kernel_cache(nvp_plan *plan, int enable);
+/* 1 (default): nvp_execute_cascade computes the kernel spectra it needs on a
+ * second stream of the plan, concurrently with the harmonics' source builds
+ * and convolutions (each z pass waits for its spectrum; the second stream
+ * first waits for all earlier work of the context stream), using scratch of
+ * its own; 0: spectra computed in line.  Ignored while timing is on and while
+ * the context stream is being captured into a graph; off for the plans of a
+ * batch.  Results are the same either way. */
+nvp_status nvp_plan_set_overlap(nvp_plan *plan, int enable);
 /* One harmonic: fields[m-1] = p_m on its grid for m = 1..n-1; writes p_n. */
 nvp_status nvp_execute_harmonic(nvp_plan *plan, int n, const void *const *fields, void *pn_dev);
 /* The whole cascade: p1 in, pn_dev[i] = p_{i+2} out, computed in order. */

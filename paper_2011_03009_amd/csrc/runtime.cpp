@@ -105,6 +105,14 @@ struct nvp_plan {
     bool timing = false;
     std::vector<TimedEvent> events;
     std::vector<hipEvent_t> pool;
+    // Kernel spectra computed on a side stream, concurrently with the
+    // convolutions (nvp_execute_cascade, spectra not cached, timing off).
+    bool overlap = true;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_start = nullptr;
+    std::vector<hipEvent_t> ev_k;
+    void *kscr = nullptr, *ktab = nullptr;  // FP64 octant scratch and distance table of the side stream
+    size_t bytes_side = 0;
 };
 
 namespace {
@@ -323,7 +331,7 @@ size_t kscratch_bytes(const int64_t M[3]) {
 // y inv, x inv with `scale` into u.
 nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid *g, const int64_t M[3],
                     const void *khat, void *A, void *B, const void *f, const SourceArgs *src, void *u,
-                    double scale, int64_t src_lds = 0, const Tune &tn = Tune{}) {
+                    double scale, int64_t src_lds = 0, const Tune &tn = Tune{}, hipEvent_t kready = nullptr) {
     const int64_t Nx = g->n[0], Ny = g->n[1], Nz = g->n[2];
     const int64_t Mx = M[0], My = M[1], Mz = M[2];
     const bool dbl = prec == NVP_C128;
@@ -367,6 +375,7 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
         a.scale = 1.0; a.inner = Nz; a.outer = Mx; a.sign = -1; a.tile = tn.y_tile;
         NVP_HIP(ctx, strided((int)My, a, twy, ctx->stream));
     }
+    if (kready) NVP_HIP(ctx, hipStreamWaitEvent(ctx->stream, kready, 0));  // the kernel spectrum's side stream
     {
         Timer t(timed, NVP_T_ZCONV);
         NVP_HIP(ctx, (dbl ? nvp::launch_zconv_c128 : nvp::launch_zconv_c64)((int)Mz, B, khat, Mx, My, (int)Nz, twz,
@@ -437,6 +446,18 @@ void axis_table(double dst_o, double dst_h, int64_t dst_n, double src_o, double 
 }
 
 void free_plan_memory(nvp_plan *p) {
+    if (p->side) {
+        (void)hipStreamSynchronize(p->side);
+        (void)hipStreamDestroy(p->side);
+        p->side = nullptr;
+    }
+    if (p->ev_start) (void)hipEventDestroy(p->ev_start);
+    p->ev_start = nullptr;
+    for (auto e : p->ev_k) (void)hipEventDestroy(e);
+    p->ev_k.clear();
+    if (p->kscr) (void)hipFree(p->kscr);
+    if (p->ktab) (void)hipFree(p->ktab);
+    p->kscr = p->ktab = nullptr;
     for (auto &h : p->h)
         if (h.khat) (void)hipFree(h.khat), h.khat = nullptr;
     if (p->A) (void)hipFree(p->A);
@@ -828,7 +849,7 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
 
 nvp_status nvp_plan_workspace_bytes(const nvp_plan *plan, size_t *bytes) {
     if (!plan || !bytes) return NVP_E_INVALID;
-    *bytes = plan->bytes_A + plan->bytes_B + plan->bytes_tables + plan->bytes_khat;
+    *bytes = plan->bytes_A + plan->bytes_B + plan->bytes_tables + plan->bytes_khat + plan->bytes_side;
     return NVP_OK;
 }
 
@@ -837,6 +858,65 @@ nvp_status nvp_plan_set_kernel_cache(nvp_plan *plan, int enable) {
     plan->cache = enable != 0;
     return NVP_OK;
 }
+
+nvp_status nvp_plan_set_overlap(nvp_plan *plan, int enable) {
+    if (!plan) return NVP_E_INVALID;
+    plan->overlap = enable != 0;
+    return NVP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Harmonic n with its kernel spectrum either computed here (kready null) or
+// computed on the side stream, signalled by kready.
+nvp_status run_harmonic(nvp_plan *plan, int n, const void *const *fields, void *pn_dev, hipEvent_t kready) {
+    nvp_ctx *ctx = plan->ctx;
+    Harm &h = plan->h[n - 2];
+    nvp_status st;
+    if (!kready && (!h.khat_ok || !plan->cache)) {
+        if ((st = kernel_spectrum(ctx, plan, h.kr, h.ki, &h.g, h.M, plan->prec, h.khat, plan->B, plan->A))) return st;
+        h.khat_ok = true;
+    }
+    SourceArgs src = source_args(plan, n, fields);
+    const double scale = h.Cn / ((double)h.M[0] * (double)h.M[1] * (double)h.M[2]);
+    const bool tiled_src = plan->use_source_kernel && h.tune.src != 0;
+    return convolve(ctx, plan, plan->prec, &h.g, h.M, h.khat, plan->A, plan->B, nullptr, &src, pn_dev, scale,
+                    tiled_src ? h.src_lds : 0, h.tune, kready);
+}
+
+// Side-stream resources of the overlapped spectra (created on first use).
+nvp_status side_resources(nvp_plan *p) {
+    nvp_ctx *ctx = p->ctx;
+    if (!p->side) NVP_HIP(ctx, hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+    if (!p->ev_start) NVP_HIP(ctx, hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming));
+    while ((int)p->ev_k.size() < p->n_harm - 1) {
+        hipEvent_t e;
+        NVP_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        p->ev_k.push_back(e);
+    }
+    if (!p->kscr) {
+        size_t ks = 0, kt = 0;
+        for (auto &h : p->h) {
+            ks = std::max(ks, kscratch_bytes(h.M));
+            kt = std::max(kt, (size_t)radial_entries(&h.g) * 16);
+        }
+        NVP_HIP(ctx, hipMalloc(&p->kscr, ks));
+        hipError_t e = hipMalloc(&p->ktab, kt);
+        if (e != hipSuccess) {
+            (void)hipFree(p->kscr);
+            p->kscr = nullptr;
+            return hip_fail(ctx, "side-stream scratch", e);
+        }
+        p->bytes_side = ks + kt;
+    }
+    return NVP_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 nvp_status nvp_execute_harmonic(nvp_plan *plan, int n, const void *const *fields, void *pn_dev) {
     if (!plan) return NVP_E_INVALID;
@@ -847,27 +927,49 @@ nvp_status nvp_execute_harmonic(nvp_plan *plan, int n, const void *const *fields
         if (!fields[m - 1] || fields[m - 1] == pn_dev)
             return fail(ctx, NVP_E_INVALID, "nvp_execute_harmonic: null or aliased field");
     NVP_HIP(ctx, hipSetDevice(ctx->device));
-    Harm &h = plan->h[n - 2];
-    nvp_status st;
-    if (!h.khat_ok || !plan->cache) {
-        if ((st = kernel_spectrum(ctx, plan, h.kr, h.ki, &h.g, h.M, plan->prec, h.khat, plan->B, plan->A))) return st;
-        h.khat_ok = true;
-    }
-    SourceArgs src = source_args(plan, n, fields);
-    const double scale = h.Cn / ((double)h.M[0] * (double)h.M[1] * (double)h.M[2]);
-    const bool tiled_src = plan->use_source_kernel && h.tune.src != 0;
-    return convolve(ctx, plan, plan->prec, &h.g, h.M, h.khat, plan->A, plan->B, nullptr, &src, pn_dev, scale,
-                    tiled_src ? h.src_lds : 0, h.tune);
+    return run_harmonic(plan, n, fields, pn_dev, nullptr);
 }
 
 nvp_status nvp_execute_cascade(nvp_plan *plan, const void *p1_dev, void *const *pn_dev) {
     if (!plan) return NVP_E_INVALID;
-    if (!p1_dev || !pn_dev) return fail(plan->ctx, NVP_E_INVALID, "nvp_execute_cascade: null buffer");
+    nvp_ctx *ctx = plan->ctx;
+    if (!p1_dev || !pn_dev) return fail(ctx, NVP_E_INVALID, "nvp_execute_cascade: null buffer");
+    for (int n = 2; n <= plan->n_harm; ++n)
+        if (!pn_dev[n - 2]) return fail(ctx, NVP_E_INVALID, "nvp_execute_cascade: null output");
+        else if (pn_dev[n - 2] == p1_dev) return fail(ctx, NVP_E_INVALID, "nvp_execute_cascade: aliased output");
+    NVP_HIP(ctx, hipSetDevice(ctx->device));
+    std::vector<hipEvent_t> kready(plan->n_harm, nullptr);
+    bool need = false;
+    for (auto &h : plan->h) need = need || !h.khat_ok || !plan->cache;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    NVP_HIP(ctx, hipStreamIsCapturing(ctx->stream, &cs));
+    if (plan->overlap && !plan->timing && need && cs == hipStreamCaptureStatusNone) {
+        // every kernel spectrum the cascade needs, on the side stream after all
+        // earlier work of the context stream (which may still read the spectra)
+        nvp_status st = side_resources(plan);
+        if (st) return st;
+        NVP_HIP(ctx, hipEventRecord(plan->ev_start, ctx->stream));
+        NVP_HIP(ctx, hipStreamWaitEvent(plan->side, plan->ev_start, 0));
+        const hipStream_t user = ctx->stream;
+        ctx->stream = plan->side;
+        for (int n = 2; n <= plan->n_harm && st == NVP_OK; ++n) {
+            Harm &h = plan->h[n - 2];
+            if (h.khat_ok && plan->cache) continue;
+            st = kernel_spectrum(ctx, nullptr, h.kr, h.ki, &h.g, h.M, plan->prec, h.khat, plan->kscr, plan->ktab);
+            if (st == NVP_OK) {
+                hipError_t e = hipEventRecord(plan->ev_k[n - 2], plan->side);
+                if (e != hipSuccess) st = hip_fail(ctx, "hipEventRecord", e);
+                kready[n - 1] = plan->ev_k[n - 2];
+                h.khat_ok = true;
+            }
+        }
+        ctx->stream = user;
+        if (st) return st;
+    }
     std::vector<const void *> fields(plan->n_harm);
     fields[0] = p1_dev;
     for (int n = 2; n <= plan->n_harm; ++n) {
-        if (!pn_dev[n - 2]) return fail(plan->ctx, NVP_E_INVALID, "nvp_execute_cascade: null output");
-        nvp_status st = nvp_execute_harmonic(plan, n, fields.data(), pn_dev[n - 2]);
+        nvp_status st = run_harmonic(plan, n, fields.data(), pn_dev[n - 2], kready[n - 1]);
         if (st) return st;
         fields[n - 1] = pn_dev[n - 2];
     }
@@ -1442,6 +1544,7 @@ nvp_status nvp_batch_create(nvp_ctx *ctx, int count, const nvp_problem *problems
             delete b;
             return fail(ctx, st, msg);
         }
+        p->overlap = false;  // a batch overlaps whole problems on its own streams
         b->plans.push_back(p);
         b->off.push_back(b->n_out);
         b->n_out += pr.n_harm - 1;

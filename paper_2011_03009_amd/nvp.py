@@ -214,6 +214,10 @@ class CascadePlan:
     def set_kernel_cache(self, enable):
         _check(_native.lib().nvp_plan_set_kernel_cache(self.handle, int(bool(enable))))
 
+    def set_overlap(self, enable):
+        """Kernel spectra on a second stream, concurrently with the convolutions (default on)."""
+        _check(_native.lib().nvp_plan_set_overlap(self.handle, int(bool(enable))))
+
     def set_timing(self, enable):
         _check(_native.lib().nvp_plan_set_timing(self.handle, int(bool(enable))))
 

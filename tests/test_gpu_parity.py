@@ -165,6 +165,35 @@ def test_tiny_nested_cascade_matches_oracle(ctx, order, prec, short_x, fused, mo
 
 
 @pytest.mark.parametrize("prec", [P.NVP_C128, P.NVP_C64])
+def test_overlapped_spectra_match_in_line(ctx, prec):
+    """Kernel spectra on the plan's second stream (the default) against spectra computed in line:
+    the same bits, spectra recomputed on every call, with other work queued between calls."""
+    focus = (40e-3, 0.0, 0.0)
+    c0 = WATER["c0"]
+    g1 = oracle.grid_from_counts(focus, oracle.spacing(1, F0, c0), (24, 20, 18), (12, 10, 9))
+    gn = [oracle.grid_from_counts(focus, oracle.spacing(n, F0, c0), (40 + 8 * n, 36, 30), (24, 18, 15))
+          for n in range(2, 6)]
+    p1 = dev(fields.smooth_field(g1.n, 3) * 1e6, prec)
+    say("case overlapped spectra prec=%d" % prec)
+    plan = P.CascadePlan(ctx, WATER, F0, g1, gn, prec=prec, order=3)
+    plan.set_kernel_cache(False)
+    plan.set_overlap(False)
+    ref = [t.clone() for t in plan.execute(p1)]
+    plan.set_overlap(True)
+    outs = [torch.empty_like(t) for t in ref]
+    junk = torch.randn(1 << 20, device="cuda")
+    for r in range(3):
+        for t in outs:
+            t.zero_()
+        plan.execute(p1, outs)
+        junk = junk * 1.0001 + 1.0
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(outs, ref)), r
+    assert plan.workspace_bytes() > 0
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", [P.NVP_C128, P.NVP_C64])
 def test_single_harmonic_with_stand_in_fields(ctx, prec):
     """Harmonic 5 from seeded stand-ins for p1..p4 on coarser, offset grids (cubic transfer)."""
     focus, g1, gn = nested_grids()
