@@ -134,9 +134,24 @@ nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nv
 nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int n_harm,
                             const nvp_grid *g1, const nvp_grid *gn, nvp_prec prec,
                             int transfer_order, nvp_plan **out);
-/* Device bytes held by the plan (work buffers, kernel spectra, and the scratch
- * of the overlapped spectra once used). */
+/* Device bytes held by the plan: its tables and kernel spectra, plus its own
+ * work buffers unless a caller workspace replaces them. */
 nvp_status nvp_plan_workspace_bytes(const nvp_plan *plan, size_t *bytes);
+/* Size of the plan's transient work buffers (the two pass buffers and the
+ * scratch of the overlapped kernel spectra): the least workspace that
+ * nvp_plan_set_workspace accepts. */
+nvp_status nvp_plan_work_bytes(const nvp_plan *plan, size_t *bytes);
+/* Caller-owned work buffers.  dev: device memory on the context's device,
+ * 256-byte aligned, of bytes >= nvp_plan_work_bytes; the plan waits for its
+ * queued work, frees its own work buffers and from then on runs in
+ * [dev, dev + bytes).  The caller keeps that memory alive, and free of other
+ * use while the plan's work may run, until nvp_plan_destroy or the next call.
+ * Plans that share one workspace must not run concurrently.  dev null: the
+ * plan allocates work buffers of its own again.  Tables and kernel spectra
+ * stay plan-owned.  NVP_E_INVALID for a short or misaligned workspace (the
+ * plan unchanged); NVP_E_NOMEM if dev is null and the allocation fails (the
+ * plan then has no work buffers and its executions return NVP_E_STATE). */
+nvp_status nvp_plan_set_workspace(nvp_plan *plan, void *dev, size_t bytes);
 /* 1 (default): keep each harmonic's kernel spectrum after its first use;
  * 0: tabulate and transform the kernel again on every execution. */
 nvp_status nvp_plan_set_kernel_cache(nvp_plan *plan, int enable);

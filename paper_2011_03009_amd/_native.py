@@ -50,6 +50,8 @@ SIGNATURES = {
     "nvp_plan_workspace_bytes": (_st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "nvp_plan_set_kernel_cache": (_st, [_vp, _i]),
     "nvp_plan_set_overlap": (_st, [_vp, _i]),
+    "nvp_plan_work_bytes": (_st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "nvp_plan_set_workspace": (_st, [_vp, _vp, ctypes.c_size_t]),
     "nvp_execute_harmonic": (_st, [_vp, _i, ctypes.POINTER(_vp), _vp]),
     "nvp_execute_cascade": (_st, [_vp, _vp, ctypes.POINTER(_vp)]),
     "nvp_plan_destroy": (_st, [_vp]),

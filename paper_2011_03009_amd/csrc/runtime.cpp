@@ -113,6 +113,8 @@ struct nvp_plan {
     std::vector<hipEvent_t> ev_k;
     void *kscr = nullptr, *ktab = nullptr;  // FP64 octant scratch and distance table of the side stream
     size_t bytes_side = 0;
+    // false: A, B, kscr and ktab live in a caller-owned workspace
+    bool own_work = true;
 };
 
 namespace {
@@ -445,6 +447,42 @@ void axis_table(double dst_o, double dst_h, int64_t dst_n, double src_o, double 
     }
 }
 
+// The transient work buffers: the two pass buffers and the second stream's
+// spectrum scratch (freed here only when the plan owns them).
+void release_work(nvp_plan *p) {
+    if (p->own_work) {
+        if (p->kscr) (void)hipFree(p->kscr);
+        if (p->ktab) (void)hipFree(p->ktab);
+        if (p->A) (void)hipFree(p->A);
+        if (p->B) (void)hipFree(p->B);
+    }
+    p->kscr = p->ktab = p->A = p->B = nullptr;
+    p->bytes_side = 0;
+    p->own_work = true;
+}
+
+// Sizes of the second stream's FP64 octant scratch and distance table.
+void side_sizes(const nvp_plan *p, size_t *ks, size_t *kt) {
+    *ks = *kt = 0;
+    for (auto &h : p->h) {
+        *ks = std::max(*ks, kscratch_bytes(h.M));
+        *kt = std::max(*kt, (size_t)radial_entries(&h.g) * 16);
+    }
+}
+
+// Offsets of A, B, kscr and ktab inside a caller workspace; returns its size.
+size_t work_layout(const nvp_plan *p, size_t off[4]) {
+    size_t ks, kt;
+    side_sizes(p, &ks, &kt);
+    const size_t sz[4] = {p->bytes_A, p->bytes_B, ks, kt};
+    size_t o = 0;
+    for (int i = 0; i < 4; ++i) {
+        off[i] = o;
+        o += (sz[i] + 255) / 256 * 256;
+    }
+    return o;
+}
+
 void free_plan_memory(nvp_plan *p) {
     if (p->side) {
         (void)hipStreamSynchronize(p->side);
@@ -455,15 +493,11 @@ void free_plan_memory(nvp_plan *p) {
     p->ev_start = nullptr;
     for (auto e : p->ev_k) (void)hipEventDestroy(e);
     p->ev_k.clear();
-    if (p->kscr) (void)hipFree(p->kscr);
-    if (p->ktab) (void)hipFree(p->ktab);
-    p->kscr = p->ktab = nullptr;
+    release_work(p);
     for (auto &h : p->h)
         if (h.khat) (void)hipFree(h.khat), h.khat = nullptr;
-    if (p->A) (void)hipFree(p->A);
-    if (p->B) (void)hipFree(p->B);
     if (p->tables) (void)hipFree(p->tables);
-    p->A = p->B = p->tables = nullptr;
+    p->tables = nullptr;
     for (auto &e : p->events) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
@@ -849,7 +883,50 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
 
 nvp_status nvp_plan_workspace_bytes(const nvp_plan *plan, size_t *bytes) {
     if (!plan || !bytes) return NVP_E_INVALID;
-    *bytes = plan->bytes_A + plan->bytes_B + plan->bytes_tables + plan->bytes_khat + plan->bytes_side;
+    *bytes = plan->bytes_tables + plan->bytes_khat;
+    if (plan->own_work) *bytes += plan->bytes_A + plan->bytes_B + plan->bytes_side;
+    return NVP_OK;
+}
+
+nvp_status nvp_plan_work_bytes(const nvp_plan *plan, size_t *bytes) {
+    if (!plan || !bytes) return NVP_E_INVALID;
+    size_t off[4];
+    *bytes = work_layout(plan, off);
+    return NVP_OK;
+}
+
+nvp_status nvp_plan_set_workspace(nvp_plan *plan, void *dev, size_t bytes) {
+    if (!plan) return NVP_E_INVALID;
+    nvp_ctx *ctx = plan->ctx;
+    size_t off[4];
+    const size_t need = work_layout(plan, off);
+    if (dev && bytes < need)
+        return fail(ctx, NVP_E_INVALID, "nvp_plan_set_workspace: " + std::to_string(bytes) + " bytes, the plan needs " +
+                                            std::to_string(need));
+    if (dev && (reinterpret_cast<uintptr_t>(dev) & 255))
+        return fail(ctx, NVP_E_INVALID, "nvp_plan_set_workspace: workspace not 256-byte aligned");
+    NVP_HIP(ctx, hipSetDevice(ctx->device));
+    // queued work of the plan may still use the current buffers
+    NVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (plan->side) NVP_HIP(ctx, hipStreamSynchronize(plan->side));
+    const size_t bA = plan->bytes_A, bB = plan->bytes_B;
+    release_work(plan);
+    if (dev) {
+        char *w = static_cast<char *>(dev);
+        plan->A = w + off[0];
+        plan->B = w + off[1];
+        plan->kscr = w + off[2];
+        plan->ktab = w + off[3];
+        plan->own_work = false;
+        return NVP_OK;
+    }
+    hipError_t e = hipMalloc(&plan->A, bA);
+    if (e == hipSuccess) e = hipMalloc(&plan->B, bB);
+    if (e != hipSuccess) {
+        if (plan->A) (void)hipFree(plan->A);
+        plan->A = nullptr;
+        return hip_fail(ctx, "nvp_plan_set_workspace: allocation", e);
+    }
     return NVP_OK;
 }
 
@@ -897,11 +974,8 @@ nvp_status side_resources(nvp_plan *p) {
         p->ev_k.push_back(e);
     }
     if (!p->kscr) {
-        size_t ks = 0, kt = 0;
-        for (auto &h : p->h) {
-            ks = std::max(ks, kscratch_bytes(h.M));
-            kt = std::max(kt, (size_t)radial_entries(&h.g) * 16);
-        }
+        size_t ks, kt;
+        side_sizes(p, &ks, &kt);
         NVP_HIP(ctx, hipMalloc(&p->kscr, ks));
         hipError_t e = hipMalloc(&p->ktab, kt);
         if (e != hipSuccess) {
@@ -926,6 +1000,7 @@ nvp_status nvp_execute_harmonic(nvp_plan *plan, int n, const void *const *fields
     for (int m = 1; m < n; ++m)
         if (!fields[m - 1] || fields[m - 1] == pn_dev)
             return fail(ctx, NVP_E_INVALID, "nvp_execute_harmonic: null or aliased field");
+    if (!plan->A || !plan->B) return fail(ctx, NVP_E_STATE, "nvp_execute_harmonic: the plan has no work buffers");
     NVP_HIP(ctx, hipSetDevice(ctx->device));
     return run_harmonic(plan, n, fields, pn_dev, nullptr);
 }
@@ -937,6 +1012,7 @@ nvp_status nvp_execute_cascade(nvp_plan *plan, const void *p1_dev, void *const *
     for (int n = 2; n <= plan->n_harm; ++n)
         if (!pn_dev[n - 2]) return fail(ctx, NVP_E_INVALID, "nvp_execute_cascade: null output");
         else if (pn_dev[n - 2] == p1_dev) return fail(ctx, NVP_E_INVALID, "nvp_execute_cascade: aliased output");
+    if (!plan->A || !plan->B) return fail(ctx, NVP_E_STATE, "nvp_execute_cascade: the plan has no work buffers");
     NVP_HIP(ctx, hipSetDevice(ctx->device));
     std::vector<hipEvent_t> kready(plan->n_harm, nullptr);
     bool need = false;

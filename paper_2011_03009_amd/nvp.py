@@ -211,6 +211,23 @@ class CascadePlan:
         _check(_native.lib().nvp_plan_workspace_bytes(self.handle, ctypes.byref(b)))
         return b.value
 
+    def work_bytes(self):
+        """Least size of a caller workspace (the plan's transient work buffers)."""
+        b = ctypes.c_size_t()
+        _check(_native.lib().nvp_plan_work_bytes(self.handle, ctypes.byref(b)))
+        return b.value
+
+    def set_workspace(self, ws):
+        """Run in the caller's device memory `ws` (a tensor of at least work_bytes() bytes, kept alive
+        here), or in work buffers of the plan's own again (ws None)."""
+        if ws is None:
+            _check(_native.lib().nvp_plan_set_workspace(self.handle, None, 0), self.ctx.handle)
+        else:
+            nbytes = ws.numel() * ws.element_size()
+            _check(_native.lib().nvp_plan_set_workspace(self.handle, ctypes.c_void_p(ws.data_ptr()), nbytes),
+                   self.ctx.handle)
+        self._ws = ws
+
     def set_kernel_cache(self, enable):
         _check(_native.lib().nvp_plan_set_kernel_cache(self.handle, int(bool(enable))))
 

@@ -193,6 +193,40 @@ def test_overlapped_spectra_match_in_line(ctx, prec):
     plan.close()
 
 
+def test_caller_workspace_matches_plan_owned(ctx):
+    """A plan run in a caller workspace (and back in buffers of its own) gives the same bits;
+    short and misaligned workspaces are refused and leave the plan as it was."""
+    focus, g1, gn = nested_grids()
+    p1 = dev(fields.smooth_field(g1.n, 4) * 1e6, P.NVP_C64)
+    say("case caller workspace")
+    plan = P.CascadePlan(ctx, WATER, F0, g1, [gn[n] for n in range(2, 6)], prec=P.NVP_C64, order=3)
+    plan.set_kernel_cache(False)
+    ref = [t.clone() for t in plan.execute(p1)]
+    held = plan.workspace_bytes()
+    need = plan.work_bytes()
+    assert 0 < need
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.NvpError) as e:
+        plan.set_workspace(ws[: need - 1])
+    assert e.value.status == 1
+    with pytest.raises(P.NvpError) as e:
+        plan.set_workspace(ws[1:])
+    assert e.value.status == 1
+    ws.fill_(0xFF)  # NaN patterns: the plan must not read what it has not written
+    plan.set_workspace(ws[:need])
+    assert plan.workspace_bytes() < held
+    for overlap in (True, False):
+        plan.set_overlap(overlap)
+        outs = plan.execute(p1)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(outs, ref)), overlap
+    plan.set_workspace(None)
+    outs = plan.execute(p1)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(outs, ref))
+    plan.close()
+
+
 @pytest.mark.parametrize("prec", [P.NVP_C128, P.NVP_C64])
 def test_single_harmonic_with_stand_in_fields(ctx, prec):
     """Harmonic 5 from seeded stand-ins for p1..p4 on coarser, offset grids (cubic transfer)."""
