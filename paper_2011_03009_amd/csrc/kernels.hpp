@@ -358,13 +358,15 @@ k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t i
 }
 
 // Transfer + source build as a kernel of its own (writes f_n, read by a plain
-// forward x pass afterwards).  One workgroup per target tile of SX x SY x SZ
+// forward x pass afterwards).  One workgroup per target tile of TX x TY x TZ
 // voxels (z fastest); for every field that needs interpolating it loads the
 // source block the tile's stencils touch into LDS once (coalesced along z),
-// then interpolates along z, y and x in turn inside LDS; fields on the target
-// grid are read directly.  Each thread keeps its voxels' interpolated values
-// in registers and finally writes sum_m v_m v_{n-m}.  The host checks that
-// the source blocks of every tile fit the LDS budget given at launch.
+// interpolates along z inside LDS, then along y and x in registers (a thread
+// owns one (y, z) column of the tile); fields on the target grid are read
+// directly.  Two workgroup barriers per field.  Each thread keeps its voxels'
+// interpolated values in registers and finally writes sum_m v_m v_{n-m}.  The
+// host checks that the source blocks of every tile fit the LDS budget given
+// at launch and that their x spans fit the registers.
 template <typename R, int K, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(TY *TZ)
 k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems) {
@@ -416,7 +418,7 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
         const Block bk = block_of(g);
         const int sx0 = bk.sx0, sy0 = bk.sy0, sz0 = bk.sz0, SX = bk.SX, SY = bk.SY, SZ = bk.SZ;
         const int rows = SX * SY;
-        cx<R> *S = lds;                         // [SX][SY][SZ], later T2 [SX][TY][TZ]
+        cx<R> *S = lds;                         // [SX][SY][SZ]
         cx<R> *T1 = lds + (lds_elems - (int64_t)rows * TZ);  // [SX][SY][TZ]
         // the tile's z and y stencils: one per thread (z = tz, y = ty), loaded
         // before the block so that their latency overlaps its loads
@@ -483,27 +485,37 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
             T1[row * TZ + tz] = acc;
         }
         __syncthreads();
-        // y interpolation: T2[sx][y][z] for this thread's (y, z)
-        cx<R> *T2 = S;
-        for (int sx = 0; sx < SX; ++sx) {
-            cx<R> acc = czero<R>();
+        // y interpolation of this thread's (y, z) for every source x-row of
+        // the block, kept in registers: the x stencils of a tile span at most
+        // TX - 1 + K rows (the host checks it)
+        constexpr int SXM = TX - 1 + K;
+        cx<R> t2[SXM];
 #pragma unroll
-            for (int c = 0; c < K; ++c) acc = cadd<R>(acc, cscale<R>(T1[((sx * SY) + oy + c) * TZ + tz], wy[c]));
-            T2[(sx * TY + ty) * TZ + tz] = acc;
+        for (int sx = 0; sx < SXM; ++sx) {
+            cx<R> acc = czero<R>();
+            if (sx < SX) {
+#pragma unroll
+                for (int c = 0; c < K; ++c)
+                    acc = cadd<R>(acc, cscale<R>(T1[((sx * SY) + oy + c) * TZ + tz], wy[c]));
+            }
+            t2[sx] = acc;
         }
-        __syncthreads();
+        // x interpolation: the stencil offset of target row a is the same for
+        // the whole workgroup, so the branch on it is uniform
 #pragma unroll
         for (int a = 0; a < TX; ++a) {
-            const int ix = ix0 + a;
-            if (ix < Nx) {
+            if (ix0 + a < Nx) {
+                const int o = __builtin_amdgcn_readfirstlane(ox[a]);
                 cx<R> acc = czero<R>();
 #pragma unroll
-                for (int b = 0; b < K; ++b)
-                    acc = cadd<R>(acc, cscale<R>(T2[((ox[a] + b) * TY + ty) * TZ + tz], wx[a][b]));
+                for (int q = 0; q < TX; ++q)
+                    if (o == q) {
+#pragma unroll
+                        for (int b = 0; b < K; ++b) acc = cadd<R>(acc, cscale<R>(t2[q + b], wx[a][b]));
+                    }
                 v[i][a] = acc;
             }
         }
-        __syncthreads();
     }
     if (!inyz) return;
 #pragma unroll

@@ -830,7 +830,8 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
         }
     }
     // Tiled source kernel: the largest source block any tile touches, per axis,
-    // over the fields that need interpolating; used when its LDS fits 96 KiB.
+    // over the fields that need interpolating; used when its LDS fits 96 KiB
+    // and the x span of every tile's stencils fits TX - 1 + K rows.
     for (auto &h : p->h) {
         int64_t msx = 0, msy = 0, msz = 0;
         bool any = false;
@@ -850,10 +851,9 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
             }
         }
         h.src_lds = 0;
-        const int64_t blk = msx * msy * msz, t2 = msx * T[1] * T[2];
-        const int64_t elems = (blk > t2 ? blk : t2) + msx * msy * T[2];
+        const int64_t elems = msx * msy * msz + msx * msy * T[2];
         if (!any) h.src_lds = 1;  // every field already on the target grid: no staging
-        else if (elems * (int64_t)csize(prec) <= 98304) h.src_lds = elems;
+        else if (elems * (int64_t)csize(prec) <= 98304 && msx <= T[0] - 1 + K) h.src_lds = elems;
     }
     hipError_t e = hipSuccess;
     if (tbytes) e = hipMalloc(&p->tables, tbytes);
