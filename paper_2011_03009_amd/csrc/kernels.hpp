@@ -367,6 +367,11 @@ k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t i
 // interpolated values in registers and finally writes sum_m v_m v_{n-m}.  The
 // host checks that the source blocks of every tile fit the LDS budget given
 // at launch and that their x spans fit the registers.
+// floor(a / b) for 0 <= a < 2^22 and b >= 1, given inv_b = 1/b in float:
+// (a + 1/2) / b lies at least 1/(2b) from an integer, far more than the
+// rounding of the float product.
+__device__ __forceinline__ int div_small(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
+
 template <typename R, int K, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(TY *TZ)
 k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems) {
@@ -377,6 +382,11 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
     const int ix1 = min(ix0 + TX, Nx), iy1 = min(iy0 + TY, Ny), iz1 = min(iz0 + TZ, Nz);
     const int iy = iy0 + ty, iz = iz0 + tz;
     const bool inyz = iy < Ny && iz < Nz;
+    // element offsets in 32 bits: the host checks that every grid involved
+    // has fewer than 2^32 elements
+    auto at = [](const FieldDev<R> &g, int x, int y, int z) {
+        return g.p + ((uint32_t)x * (uint32_t)g.s0 + (uint32_t)y * (uint32_t)g.s1 + (uint32_t)z);
+    };
     cx<R> v[NVP_MAX_FIELDS][TX];
 #pragma unroll
     for (int i = 0; i < NVP_MAX_FIELDS; ++i)
@@ -412,12 +422,13 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
         if (g.identity) {
 #pragma unroll
             for (int a = 0; a < TX; ++a)
-                if (inyz && ix0 + a < Nx) v[i][a] = g.p[(ix0 + a) * g.s0 + (int64_t)iy * g.s1 + iz];
+                if (inyz && ix0 + a < Nx) v[i][a] = *at(g, ix0 + a, iy, iz);
             continue;
         }
         const Block bk = block_of(g);
         const int sx0 = bk.sx0, sy0 = bk.sy0, sz0 = bk.sz0, SX = bk.SX, SY = bk.SY, SZ = bk.SZ;
         const int rows = SX * SY;
+        const float inv_sy = 1.0f / (float)SY;
         cx<R> *S = lds;                         // [SX][SY][SZ]
         cx<R> *T1 = lds + (lds_elems - (int64_t)rows * TZ);  // [SX][SY][TZ]
         // the tile's z and y stencils: one per thread (z = tz, y = ty), loaded
@@ -452,8 +463,8 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
             }
         } else {
             for (int row = ty; row < rows; row += TY) {
-                const int sx = row / SY, sy = row - sx * SY;
-                const cx<R> *sp = g.p + (int64_t)(sx0 + sx) * g.s0 + (int64_t)(sy0 + sy) * g.s1 + sz0;
+                const int sx = div_small(row, inv_sy), sy = row - sx * SY;
+                const cx<R> *sp = at(g, sx0 + sx, sy0 + sy, sz0);
                 for (int sz = tz; sz < SZ; sz += TZ) S[row * SZ + sz] = sp[sz];
             }
         }
@@ -465,9 +476,8 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
 #pragma unroll
                 for (int r = 0; r < PR; ++r) {
                     const int row = ty + r * TY;
-                    const int sx = row / nb.SY, sy = row - sx * nb.SY;
-                    const cx<R> *sp =
-                        gn.p + (int64_t)(nb.sx0 + sx) * gn.s0 + (int64_t)(nb.sy0 + sy) * gn.s1 + nb.sz0;
+                    const int sx = div_small(row, 1.0f / (float)nb.SY), sy = row - sx * nb.SY;
+                    const cx<R> *sp = at(gn, nb.sx0 + sx, nb.sy0 + sy, nb.sz0);
 #pragma unroll
                     for (int z = 0; z < PZ; ++z) {
                         const int sz = tz + z * TZ;
@@ -525,7 +535,7 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
         cx<R> w[NVP_MAX_FIELDS];
 #pragma unroll
         for (int i = 0; i < NVP_MAX_FIELDS; ++i) w[i] = v[i][a];
-        out[((int64_t)ix * Ny + iy) * Nz + iz] = src.products(w);
+        out[((uint32_t)ix * (uint32_t)Ny + (uint32_t)iy) * (uint32_t)Nz + (uint32_t)iz] = src.products(w);
     }
 }
 

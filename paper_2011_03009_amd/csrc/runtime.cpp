@@ -830,12 +830,18 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
         }
     }
     // Tiled source kernel: the largest source block any tile touches, per axis,
-    // over the fields that need interpolating; used when its LDS fits 96 KiB
-    // and the x span of every tile's stencils fits TX - 1 + K rows.
+    // over the fields that need interpolating; used when its LDS fits 96 KiB,
+    // the x span of every tile's stencils fits TX - 1 + K rows and every grid
+    // involved has fewer than 2^32 elements.
     for (auto &h : p->h) {
         int64_t msx = 0, msy = 0, msz = 0;
         bool any = false;
         const int64_t T[3] = {NVP_SRC_TX, NVP_SRC_TY, NVP_SRC_TZ};
+        bool small = true;  // every grid involved below 2^32 elements (32-bit offsets)
+        for (int m = 1; m <= h.n; ++m) {
+            const nvp_grid &gm = m == 1 ? p->g1 : p->h[m - 2].g;
+            small = small && gm.n[0] * gm.n[1] * gm.n[2] < (int64_t(1) << 32);
+        }
         for (int m = 1; m < h.n; ++m) {
             if (h.f[m - 1].identity) continue;
             any = true;
@@ -852,7 +858,8 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
         }
         h.src_lds = 0;
         const int64_t elems = msx * msy * msz + msx * msy * T[2];
-        if (!any) h.src_lds = 1;  // every field already on the target grid: no staging
+        if (!small) h.src_lds = 0;
+        else if (!any) h.src_lds = 1;  // every field already on the target grid: no staging
         else if (elems * (int64_t)csize(prec) <= 98304 && msx <= T[0] - 1 + K) h.src_lds = elems;
     }
     hipError_t e = hipSuccess;
