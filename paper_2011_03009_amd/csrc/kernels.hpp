@@ -571,15 +571,21 @@ __device__ __forceinline__ void zconv_block(cx<R> *__restrict__ buf, const cx<R>
     cx<R> *my = lds + slot * SL;
     const PencilSlot<R> ref{my};
     cx<R> v[E];
-    // the pencil's upper half is zero (Mz >= 2 Nz - 1) and only its lower half is kept
-    F::template load0<true>(v, t, [&](int m) { return (act && m < Nz) ? pen[m] : czero<R>(); });
+    // the pencil's upper half is zero (Mz >= 2 Nz - 1) and only its lower half
+    // is kept.  Loads need no guard but m < Nz: a quad past the last maps to
+    // pencil (0, 0) and kernel row (0, 0), which exist, and an inactive
+    // pencil's results are never stored.
+    if (Nz == L / 2)
+        F::template load0<true>(v, t, [&](int m) { return pen[m]; });
+    else
+        F::template load0<true>(v, t, [&](int m) { return m < Nz ? pen[m] : czero<R>(); });
     // the spectrum values this thread multiplies by, loaded before the forward
     // transform so that their latency overlaps it
     cx<R> kv[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int k = F::out_index(t, i);
-        kv[i] = valid ? krow[k <= L / 2 ? k : L - k] : czero<R>();
+        kv[i] = krow[k <= L / 2 ? k : L - k];
     }
     auto twf = [&](int e) { return tw[e]; };
     F::template compute_keep<-1, true>(v, t, twf, ref);
