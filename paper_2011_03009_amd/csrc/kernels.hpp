@@ -574,8 +574,10 @@ __device__ __forceinline__ void zconv_block(cx<R> *__restrict__ buf, const cx<R>
     // the pencil's upper half is zero (Mz >= 2 Nz - 1) and only its lower half
     // is kept.  Loads need no guard but m < Nz: a quad past the last maps to
     // pencil (0, 0) and kernel row (0, 0), which exist, and an inactive
-    // pencil's results are never stored.
-    if (Nz == L / 2)
+    // pencil's results are never stored.  With an even first radix the first
+    // stage reads only elements below L/2, so for Nz = L/2 none is guarded.
+    constexpr bool EVEN0 = 2 * F::K0 == plan_for(L).r[0];
+    if (EVEN0 && Nz == L / 2)
         F::template load0<true>(v, t, [&](int m) { return pen[m]; });
     else
         F::template load0<true>(v, t, [&](int m) { return m < Nz ? pen[m] : czero<R>(); });
