@@ -165,6 +165,35 @@ def cpu_baseline(cfg, g1_p, gn_p, p1_dev, budget_s, order):
                       "voxel (%.1f s)" % (n_t, order, t_fixed, t_sum)}
 
 
+def incident_bench(P, torch, ctx, cfg, g1, p1_ref, stream, reps):
+    """The incident field p_1 (Section 3.2 monopole sum) by the HIP kernel on the cascade's p1 grid.
+
+    Timed with HIP events on the context stream; the output is compared with
+    the FP64 p1 input that the cascade ran on (generated by torch).
+    """
+    import numpy as np
+    from workload import bowl
+    W, f0 = cfg["medium"], cfg["f0"]
+    k1 = P.wavenumber(W, f0, 1)
+    pts = torch.from_numpy(bowl.bowl_points(cfg["R"], cfg["l"], cfg["n_points"], cfg["seed"])).to(p1_ref.device)
+    s = bowl.rayleigh_scale(cfg["R"], cfg["l"], k1, cfg["p0"], cfg["n_points"])
+    out = P.incident_field(ctx, k1, s, pts, g1, prec=P.NVP_C64)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        P.incident_field(ctx, k1, s, pts, g1, prec=P.NVP_C64, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ref = p1_ref.to(torch.complex128)
+    diff = float(torch.linalg.vector_norm(out.to(torch.complex128) - ref) / torch.linalg.vector_norm(ref))
+    vox = nsz(g1)
+    return {"ms": ms, "voxels": vox, "points": int(cfg["n_points"]), "pairs_per_s": vox * cfg["n_points"] / (ms * 1e-3),
+            "rel_l2_vs_fp64_input": diff, "dtype": "c64 (FP64 distances and phases, FP32 sin/cos/exp, FP64 sums)"}
+
+
 def batch_bench(P, torch, ctx, W, steps, log):
     """The batched workload: 64 seeded transducers, harmonic boxes from the trained box predictor.
 
@@ -330,6 +359,10 @@ def main():
         "per_kernel": per_kind,
     }
     del plan
+
+    log("bench: incident field p1 (%d points on 128^3)" % cfg["n_points"])
+    result["incident_field"] = incident_bench(P, torch, ctx, cfg, g1, p1, stream, 5)
+    log("bench: incident %s" % result["incident_field"])
 
     if not a.no_uniform:
         log("bench: uniform 640^3 cascade")

@@ -113,6 +113,27 @@ nvp_status nvp_transfer_axis(double dst_origin, double dst_h, int64_t dst_n, dou
  * M >= 2 n - 1 (the embedding of Section 3.1 is exact for any such M). */
 nvp_status nvp_circulant_size(int64_t n, int64_t *m);
 
+/* ---- the incident field ---------------------------------------------------- */
+
+/* The incident (first-harmonic) field of a transducer modelled as n_points
+ * equal-weight point sources on its surface (Section 3.2, incident-field
+ * equation), at the voxel centres x_i = origin + (ix, iy, iz) h of grid g:
+ *   out[i] = (s_re + i s_im) * sum_j exp(i k r_ij) / (4 pi r_ij),  r_ij = |x_i - p_j|,
+ * k = k_re + i k_im with k_im >= 0 (outgoing, decaying waves).  The caller
+ * folds the weights and the source strength into the scale s (a bowl of area
+ * A with surface pressure p0: s = -2 i k p0 A / n_points).
+ *   points_dev: n_points x 3 doubles (x, y, z), device memory, caller-owned;
+ *   out_dev: g->n[0]*g->n[1]*g->n[2] complex values [Nx][Ny][Nz] in prec,
+ *            device memory, caller-owned, written in full.
+ * complex64: distances, phases and the phase reduction in FP64, sine and
+ * cosine of the reduced phase, decay and 1/r in FP32, sums in FP64 (relative
+ * L2 error ~6e-8 at the paper's scale); complex128: FP64 throughout.  A voxel centre on a point (r = 0) receives a non-finite value.
+ * Enqueued on the context stream.  NVP_E_INVALID: null pointers,
+ * n_points < 1, a bad grid or precision, non-finite k or s, k_im < 0. */
+nvp_status nvp_incident_field(nvp_ctx *ctx, double k_re, double k_im, double s_re, double s_im,
+                              const double *points_dev, int64_t n_points, const nvp_grid *g, void *out_dev,
+                              nvp_prec prec);
+
 /* ---- the raw operator ---------------------------------------------------- */
 
 /* u = -sum_j K(x_i - x_j) f_j on grid g (eqs. vol_pot_approx and quad), any

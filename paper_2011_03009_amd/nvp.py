@@ -171,6 +171,23 @@ class Context:
             pass
 
 
+def incident_field(ctx, k, scale, points, g, prec=NVP_C64, out=None):
+    """scale * sum_j exp(i k r) / (4 pi r) over the points (float64 CUDA tensor [n, 3]) at the centres of g."""
+    g = grid(g)
+    n = tuple(g.n)
+    if not isinstance(points, torch.Tensor) or points.device.type != "cuda" or points.dtype != torch.float64 \
+            or not points.is_contiguous() or points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must be a contiguous float64 CUDA tensor of shape (n, 3)")
+    dtype = torch.complex128 if prec == NVP_C128 else torch.complex64
+    if out is None:
+        out = torch.empty(n, dtype=dtype, device=points.device)
+    _need(out, dtype, n[0] * n[1] * n[2], "out")
+    k, scale = complex(k), complex(scale)
+    _check(_native.lib().nvp_incident_field(ctx.handle, k.real, k.imag, scale.real, scale.imag, _ptr(points),
+                                            points.shape[0], ctypes.byref(g), _ptr(out), prec), ctx.handle)
+    return out
+
+
 def volume_potential(ctx, k, g, f, out=None):
     """u = -sum_j K(x_i - x_j) f_j on grid g (complex64 or complex128 f of shape g.n)."""
     g = grid(g)

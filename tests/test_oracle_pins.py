@@ -196,6 +196,35 @@ def test_bowl_field_focus_exact_and_oneil_on_axis():
     assert abs(abs(ref) / 1e6 - 9.3406 * math.exp(-k.imag * l)) < 1e-4
 
 
+def test_incident_oracle_focus_exact_and_oneil_on_axis():
+    """The oracle's monopole sum: exact at the focus for any cap point set, O'Neil on the axis."""
+    R, l = 7.5e-3, 15e-3
+    k = oracle.wavenumber(1, F0, WATER)
+    p0 = 1e6
+    h = bowl.cap_height(R, l)
+    ref = -1j * k * h * p0 * np.exp(1j * k * l)
+    xs = np.linspace(l / 2, 1.5 * l, 41)
+    xs = xs[np.abs(xs - l) > 1e-4]
+    exact = bowl.oneil_on_axis(xs, R, l, k, p0)
+    errs = []
+    for n_p in (256, 1024, 4096):
+        pts = bowl.bowl_points(R, l, n_p, seed=3)
+        s = bowl.rayleigh_scale(R, l, k, p0, n_p)
+        pf = oracle.incident_at(pts, k, s, [[l, 0.0, 0.0]])[0]
+        assert abs(pf - ref) <= 1e-13 * abs(ref)
+        tg = np.stack([xs, np.zeros_like(xs), np.zeros_like(xs)], axis=1)
+        errs.append(np.max(np.abs(oracle.incident_at(pts, k, s, tg) - exact)) / abs(ref))
+    assert errs[0] < 1e-4
+    assert errs[1] < errs[0] / 8 and errs[2] < errs[1] / 8, errs
+    # the grid form evaluates the same sum at the grid's centres
+    g = oracle.grid_from_counts((l, 0.0, 0.0), 1e-4, (3, 2, 4), (1, 1, 2))
+    pts = bowl.bowl_points(R, l, 64, seed=1)
+    s = bowl.rayleigh_scale(R, l, k, p0, 64)
+    f = oracle.incident_field(pts, k, s, g)
+    assert f.shape == (3, 2, 4)
+    assert abs(f[1, 1, 2] - ref) <= 1e-13 * abs(ref)
+
+
 # ---------------------------------------------------------------- grids
 
 def test_grid_builder_reproduces_printed_voxel_counts():

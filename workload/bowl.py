@@ -51,6 +51,12 @@ def bowl_points(R, l, n_points, seed=0):
     return pts
 
 
+def rayleigh_scale(R, l, k1, p0, n_points):
+    """Scale s of the monopole sum s * sum_j exp(i k r_j) / (4 pi r_j) that makes it the Rayleigh
+    integral of a baffled cap of surface pressure p0: s = -2 i k p0 A / n_points."""
+    return -2j * complex(k1) * p0 * cap_area(R, l) / n_points
+
+
 def incident_field(points, R, l, k1, p0, xs, ys, zs, device="cpu", chunk=4096):
     """p1 on the tensor grid xs x ys x zs (1-D float64 coordinate arrays).
 
@@ -60,9 +66,8 @@ def incident_field(points, R, l, k1, p0, xs, ys, zs, device="cpu", chunk=4096):
     """
     dev = torch.device(device)
     n_p = points.shape[0]
-    A = cap_area(R, l)
     k1 = complex(k1)
-    pref = -2j * k1 * p0 * (A / n_p) / (4.0 * math.pi)
+    pref = rayleigh_scale(R, l, k1, p0, n_p) / (4.0 * math.pi)
     P = torch.as_tensor(points, dtype=torch.float64, device=dev)
     X = torch.as_tensor(np.asarray(xs, dtype=np.float64), device=dev)
     Y = torch.as_tensor(np.asarray(ys, dtype=np.float64), device=dev)
