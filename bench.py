@@ -194,6 +194,81 @@ def incident_bench(P, torch, ctx, cfg, g1, p1_ref, stream, reps):
             "rel_l2_vs_fp64_input": diff, "dtype": "c64 (FP64 distances and phases, FP32 sin/cos/exp, FP64 sums)"}
 
 
+def paper_workload_bench(P, torch, ctx, stream, reps, log):
+    """The paper's own workload (its timing table): the H101 bowl (1.1 MHz, l 63.2 mm, R 32 mm)
+    in water at 100 W radiated power, 4096 points, harmonics 2..5 at lambda_n / 6 on the
+    rule-of-thumb nested boxes (post-focal d = 10.5 mm), linear transfer, complex64.
+
+    p_1 is the GPU monopole sum on the reference window at lambda_1 / 6, scaled to 100 W by the
+    disc-power integral; the cascade then recomputes its kernel spectra on every run.
+    """
+    import math
+    from workload import bowl, configs
+    W = configs.WATER
+    f0, l, R, d, n_p, power = 1.1e6, 63.2e-3, 32e-3, 10.5e-3, 4096, 100.0
+    focus = (l, 0.0, 0.0)
+    dev = torch.device("cuda", 0)
+    g1, _ = P.grid_from_box(focus, *P.rule_of_thumb_box(2, l, R, d), P.spacing(W, f0, 1))
+    gn = [P.grid_from_box(focus, *P.rule_of_thumb_box(n, l, R, d), P.spacing(W, f0, n))[0] for n in range(2, 6)]
+    k1 = P.wavenumber(W, f0, 1)
+    pts = torch.from_numpy(bowl.bowl_points(R, l, n_p, 0)).to(dev)
+    s_raw = bowl.cap_area(R, l) / n_p  # the unnormalised field (A / n_p) sum_j G_k
+    centre = (bowl.cap_height(R, l), 0.0, 0.0)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pw = P.radiated_power(ctx, k1, s_raw, pts, centre, R, W["rho0"], W["c0"], 256, 256)
+    t_power = time.perf_counter() - t0
+    s = s_raw * math.sqrt(power / pw)
+    p1 = P.incident_field(ctx, k1, s, pts, g1, prec=P.NVP_C64)
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record(stream)
+    P.incident_field(ctx, k1, s, pts, g1, prec=P.NVP_C64, out=p1)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms_p1 = a.elapsed_time(b)
+    plan = P.CascadePlan(ctx, W, f0, g1, gn, prec=P.NVP_C64, order=1)
+    plan.set_kernel_cache(False)
+    outs = plan.execute(p1)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        plan.execute(p1, outs)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms_cascade = a.elapsed_time(b) / reps
+    per = []
+    fields = [p1]
+    for n in range(2, 6):
+        a.record(stream)
+        plan.execute_harmonic(n, fields, outs[n - 2])
+        b.record(stream)
+        torch.cuda.synchronize()
+        per.append(a.elapsed_time(b))
+        fields.append(outs[n - 2])
+    i_f = [int(round((focus[ax] - g1.origin[ax]) / g1.h)) for ax in range(3)]
+    focal = [abs(complex(p1[i_f[0], i_f[1], i_f[2]].item()))]
+    for g, o in zip(gn, outs):
+        j = [int(round((focus[ax] - g.origin[ax]) / g.h)) for ax in range(3)]
+        focal.append(abs(complex(o[j[0], j[1], j[2]].item())))
+    vox = [nsz(g) for g in gn]
+    res = {"workload": "H101 in water, 100 W, 4096 points, p2..p5 on rule-of-thumb boxes (d 10.5 mm) at "
+                       "lambda_n/6, linear transfer, complex64, kernel spectra recomputed",
+           "p1_grid": [int(v) for v in g1.n], "grids": [[int(v) for v in g.n] for g in gn],
+           "circulants": [[P.circulant_size(int(v)) for v in g.n] for g in gn], "voxels": vox,
+           "radiated_power_W_before_scaling": pw, "power_integral_s": t_power, "p1_ms": ms_p1,
+           "cascade_ms": ms_cascade, "harmonic_ms": per, "total_ms": ms_p1 + ms_cascade + t_power * 1e3,
+           "voxels_per_s": sum(vox) / (ms_cascade * 1e-3), "focal_pressure_Pa": focal,
+           "plan_device_bytes": plan.workspace_bytes(),
+           "paper_cpu_total_s": 4991.0, "paper_cpu_note": "1h23m11s on 2x 14-core Xeon E5-2690 v4 (context)"}
+    plan.close()
+    return res
+
+
 def batch_bench(P, torch, ctx, W, steps, log):
     """The batched workload: 64 seeded transducers, harmonic boxes from the trained box predictor.
 
@@ -269,6 +344,7 @@ def batch_bench(P, torch, ctx, W, steps, log):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper's H101 workload")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--order", type=int, default=3, choices=[1, 3])
@@ -363,6 +439,14 @@ def main():
     log("bench: incident field p1 (%d points on 128^3)" % cfg["n_points"])
     result["incident_field"] = incident_bench(P, torch, ctx, cfg, g1, p1, stream, 5)
     log("bench: incident %s" % result["incident_field"])
+
+    if not a.no_paper:
+        log("bench: the paper's H101 workload")
+        try:
+            result["paper_workload"] = paper_workload_bench(P, torch, ctx, stream, 2, log)
+        except Exception as exc:  # recorded, so that the rest of the benchmark still reports
+            result["paper_workload"] = {"error": repr(exc)}
+        log("bench: paper workload %s" % result["paper_workload"])
 
     if not a.no_uniform:
         log("bench: uniform 640^3 cascade")

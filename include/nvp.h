@@ -134,6 +134,26 @@ nvp_status nvp_incident_field(nvp_ctx *ctx, double k_re, double k_im, double s_r
                               const double *points_dev, int64_t n_points, const nvp_grid *g, void *out_dev,
                               nvp_prec prec);
 
+/* The same sum at n_targets arbitrary points: targets_dev n_targets x 3
+ * doubles (device, caller-owned); out_dev n_targets complex values in prec. */
+nvp_status nvp_incident_at(nvp_ctx *ctx, double k_re, double k_im, double s_re, double s_im,
+                           const double *points_dev, int64_t n_points, const double *targets_dev,
+                           int64_t n_targets, void *out_dev, nvp_prec prec);
+/* Power radiated through the disc of the given radius centred at centre[3]
+ * in the plane x = centre[0] (the transducer axis is the x axis), for the
+ * field of nvp_incident_field with the same k, scale and points (Section 3.2,
+ * the radiated-power integral over a disc covering the open end of a bowl):
+ *   power = 1/(2 rho0 c0) * int_0^{2 pi} int_0^radius |p(r, theta)|^2 r dr dtheta,
+ * by the midpoint rule with n_r x n_theta nodes (1..4096 each), the field
+ * evaluated in complex128.  The paper's normalisation to a prescribed power
+ * P0 multiplies the scale by sqrt(P0 / power).  Synchronous: waits for the
+ * context stream; allocates n_r * n_theta * 40 bytes of device scratch for
+ * the call.  NVP_E_INVALID for bad arguments as nvp_incident_field and for
+ * non-positive radius, rho0 or c0. */
+nvp_status nvp_radiated_power(nvp_ctx *ctx, double k_re, double k_im, double s_re, double s_im,
+                              const double *points_dev, int64_t n_points, const double centre[3], double radius,
+                              double rho0, double c0, int n_r, int n_theta, double *power);
+
 /* ---- the raw operator ---------------------------------------------------- */
 
 /* u = -sum_j K(x_i - x_j) f_j on grid g (eqs. vol_pot_approx and quad), any
@@ -151,7 +171,7 @@ nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nv
  * paper recommends); target centres are clamped into the source grid's hull,
  * and a field on the very grid it is needed on is used as is.  Every axis
  * of a source grid needs at least transfer_order + 1 voxels, and every axis
- * a circulant length (nvp_circulant_size; up to 640 voxels in this build). */
+ * a circulant length (nvp_circulant_size; up to 768 voxels in this build). */
 nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int n_harm,
                             const nvp_grid *g1, const nvp_grid *gn, nvp_prec prec,
                             int transfer_order, nvp_plan **out);

@@ -10,4 +10,4 @@ Parity status of each function is stated in its docstring; none is
 """
 
 from .core import *  # noqa: F401,F403
-from .incident import incident_at, incident_field  # noqa: F401
+from .incident import incident_at, incident_field, radiated_power  # noqa: F401

@@ -41,3 +41,24 @@ def incident_field(points, k, scale, grid, chunk=1024):
     X, Y, Z = np.meshgrid(grid.coords(0), grid.coords(1), grid.coords(2), indexing="ij")
     T = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
     return incident_at(points, k, scale, T, chunk).reshape(tuple(grid.n))
+
+
+def radiated_power(points, k, scale, centre, radius, rho0, c0, n_r, n_theta):
+    """Power through the disc of `radius` centred at `centre` in the plane x = centre[0]:
+
+        1 / (2 rho0 c0) * int_0^{2 pi} int_0^radius |p(r, theta)|^2 r dr dtheta
+
+    (Section 3.2, the radiated-power integral over a disc covering the open
+    end of the bowl; the printed integrand lacks the area element r and the
+    modulus, read here as |p|^2 r), by the midpoint rule with n_r x n_theta
+    nodes.  Used to scale p_1 to a prescribed power P0 by sqrt(P0 / power).
+    """
+    dr = radius / n_r
+    dth = 2.0 * math.pi / n_theta
+    r = (np.arange(n_r) + 0.5) * dr
+    th = (np.arange(n_theta) + 0.5) * dth
+    R_, T_ = np.meshgrid(r, th, indexing="ij")
+    tg = np.stack([np.full(R_.size, float(centre[0])), centre[1] + (R_ * np.cos(T_)).ravel(),
+                   centre[2] + (R_ * np.sin(T_)).ravel()], axis=1)
+    p = incident_at(points, k, scale, tg).reshape(n_r, n_theta)
+    return float(np.sum(np.abs(p) ** 2 * R_) * dr * dth / (2.0 * rho0 * c0))

@@ -10,7 +10,10 @@ namespace nvp {
 template <typename R> constexpr int strided_cols(int L) {
     const int lo = sizeof(R) == 4 ? 16 : 8, hi = sizeof(R) == 4 ? 64 : 32;
     const int t = 256 / plan_threads(L);
-    return t < lo ? lo : (t > hi ? hi : t);
+    int c = t < lo ? lo : (t > hi ? hi : t);
+    // the workgroup's columns must fit the 160 KiB of LDS
+    while (c > 1 && (size_t)c * L * sizeof(cx<R>) > 163840) c /= 2;
+    return c;
 }
 
 // Pencils per workgroup of the contiguous FP64 kernel: about 256 threads,

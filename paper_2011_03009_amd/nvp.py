@@ -175,9 +175,7 @@ def incident_field(ctx, k, scale, points, g, prec=NVP_C64, out=None):
     """scale * sum_j exp(i k r) / (4 pi r) over the points (float64 CUDA tensor [n, 3]) at the centres of g."""
     g = grid(g)
     n = tuple(g.n)
-    if not isinstance(points, torch.Tensor) or points.device.type != "cuda" or points.dtype != torch.float64 \
-            or not points.is_contiguous() or points.dim() != 2 or points.shape[1] != 3:
-        raise ValueError("points must be a contiguous float64 CUDA tensor of shape (n, 3)")
+    _points(points)
     dtype = torch.complex128 if prec == NVP_C128 else torch.complex64
     if out is None:
         out = torch.empty(n, dtype=dtype, device=points.device)
@@ -186,6 +184,40 @@ def incident_field(ctx, k, scale, points, g, prec=NVP_C64, out=None):
     _check(_native.lib().nvp_incident_field(ctx.handle, k.real, k.imag, scale.real, scale.imag, _ptr(points),
                                             points.shape[0], ctypes.byref(g), _ptr(out), prec), ctx.handle)
     return out
+
+
+def _points(points, what="points"):
+    if not isinstance(points, torch.Tensor) or points.device.type != "cuda" or points.dtype != torch.float64 \
+            or not points.is_contiguous() or points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("%s must be a contiguous float64 CUDA tensor of shape (n, 3)" % what)
+    return points
+
+
+def incident_at(ctx, k, scale, points, targets, prec=NVP_C64, out=None):
+    """The incident_field sum at arbitrary targets (float64 CUDA tensor [m, 3])."""
+    _points(points)
+    _points(targets, "targets")
+    dtype = torch.complex128 if prec == NVP_C128 else torch.complex64
+    if out is None:
+        out = torch.empty(targets.shape[0], dtype=dtype, device=points.device)
+    _need(out, dtype, targets.shape[0], "out")
+    k, scale = complex(k), complex(scale)
+    _check(_native.lib().nvp_incident_at(ctx.handle, k.real, k.imag, scale.real, scale.imag, _ptr(points),
+                                         points.shape[0], _ptr(targets), targets.shape[0], _ptr(out), prec),
+           ctx.handle)
+    return out
+
+
+def radiated_power(ctx, k, scale, points, centre, radius, rho0, c0, n_r=512, n_theta=512):
+    """Power through the disc x = centre[0] of the given radius (midpoint rule, n_r x n_theta nodes)."""
+    _points(points)
+    k, scale = complex(k), complex(scale)
+    c = (ctypes.c_double * 3)(*[float(v) for v in centre])
+    out = ctypes.c_double()
+    _check(_native.lib().nvp_radiated_power(ctx.handle, k.real, k.imag, scale.real, scale.imag, _ptr(points),
+                                            points.shape[0], c, float(radius), float(rho0), float(c0), int(n_r),
+                                            int(n_theta), ctypes.byref(out)), ctx.handle)
+    return out.value
 
 
 def volume_potential(ctx, k, g, f, out=None):

@@ -80,11 +80,12 @@ def test_transfer_tables_bit_exact_indices(order):
 
 
 def test_circulant_sizes():
-    for n in (1, 2, 7, 8, 9, 16, 17, 32, 48, 80, 96, 100, 128, 160, 200, 256, 320, 384, 448, 512, 640):
+    for n in (1, 2, 7, 8, 9, 16, 17, 32, 48, 80, 96, 100, 128, 160, 200, 256, 320, 384, 448, 512, 640, 641, 768):
         m = P.circulant_size(n)
         assert m >= 2 * n - 1 and m % 2 == 0
+    assert P.circulant_size(640) == 1280 and P.circulant_size(641) == 1536
     with pytest.raises(P.NvpError):
-        P.circulant_size(641)
+        P.circulant_size(769)
 
 
 def test_host_calls_reject_invalid_arguments():

@@ -106,3 +106,41 @@ def test_point_on_a_voxel_centre_and_errors(ctx):
     assert e.value.status == 1
     with pytest.raises(ValueError):
         P.incident_field(ctx, 1.0, 1.0, d[:, :2].contiguous(), g)
+
+
+@pytest.mark.parametrize("prec", [P.NVP_C128, P.NVP_C64])
+def test_arbitrary_targets(ctx, prec):
+    R, l, f0 = 32e-3, 63.2e-3, 1.1e6
+    k = oracle.wavenumber(1, f0, WATER)
+    pts = bowl.bowl_points(R, l, 777, seed=4)
+    s = bowl.rayleigh_scale(R, l, k, 1e5, 777)
+    rng = np.random.default_rng(5)
+    tg = np.stack([rng.uniform(5e-3, 80e-3, 333), rng.uniform(-30e-3, 30e-3, 333), rng.uniform(-30e-3, 30e-3, 333)], 1)
+    say("case incident targets prec=%d" % prec)
+    got = P.incident_at(ctx, k, s, torch.from_numpy(pts).to("cuda"), torch.from_numpy(tg).to("cuda"), prec=prec)
+    torch.cuda.synchronize()
+    ref = oracle.incident_at(pts, k, s, tg)
+    assert oracle.rel_l2(got.to(torch.complex128).cpu().numpy(), ref) < TOL[prec]
+
+
+def test_radiated_power_and_normalisation(ctx):
+    """The H101 bowl (l 63.2 mm, R 32 mm): the disc power of the GPU matches the oracle's on the same
+    nodes, and scaling the field by sqrt(P0 / power) gives P0 = 100 W."""
+    R, l, f0 = 32e-3, 63.2e-3, 1.1e6
+    k = oracle.wavenumber(1, f0, WATER)
+    n_p = 512
+    pts = bowl.bowl_points(R, l, n_p, seed=0)
+    s = bowl.cap_area(R, l) / n_p
+    centre = (bowl.cap_height(R, l), 0.0, 0.0)
+    d = torch.from_numpy(pts).to("cuda")
+    say("case radiated power")
+    got = P.radiated_power(ctx, k, s, d, centre, R, WATER["rho0"], WATER["c0"], 48, 64)
+    ref = oracle.radiated_power(pts, k, s, centre, R, WATER["rho0"], WATER["c0"], 48, 64)
+    assert abs(got / ref - 1.0) < 1e-11
+    s100 = s * math.sqrt(100.0 / got)
+    again = P.radiated_power(ctx, k, s100, d, centre, R, WATER["rho0"], WATER["c0"], 48, 64)
+    assert abs(again - 100.0) < 1e-9
+    with pytest.raises(P.NvpError):
+        P.radiated_power(ctx, k, s, d, centre, -R, WATER["rho0"], WATER["c0"], 48, 64)
+    with pytest.raises(P.NvpError):
+        P.radiated_power(ctx, k, s, d, centre, R, WATER["rho0"], WATER["c0"], 0, 64)

@@ -225,6 +225,25 @@ def test_incident_oracle_focus_exact_and_oneil_on_axis():
     assert abs(f[1, 1, 2] - ref) <= 1e-13 * abs(ref)
 
 
+def test_radiated_power_of_an_axial_monopole():
+    """One monopole on the axis, a from the disc plane, lossless k: the disc integral of |p|^2 r
+    is |s|^2 ln(1 + R^2 / a^2) / (16 pi), so the power is that over 2 rho0 c0.  The midpoint
+    rule converges to it at second order."""
+    a, R, rho0, c0 = 4e-3, 10e-3, 998.0, 1487.0
+    k, s = 4647.9, 3.0 - 2.0j
+    pts = np.array([[-a, 0.0, 0.0]])
+    exact = abs(s) ** 2 * math.log(1.0 + (R / a) ** 2) / (16.0 * math.pi) / (2.0 * rho0 * c0)
+    errs = []
+    for n_r in (16, 32, 64):
+        errs.append(abs(oracle.radiated_power(pts, k, s, (0.0, 0.0, 0.0), R, rho0, c0, n_r, 8) / exact - 1.0))
+    assert errs[2] < 1e-3
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
+    # the power scales with |s|^2 and does not depend on the phase of s
+    p1 = oracle.radiated_power(pts, k, s, (0.0, 0.0, 0.0), R, rho0, c0, 32, 8)
+    p2 = oracle.radiated_power(pts, k, 2j * s, (0.0, 0.0, 0.0), R, rho0, c0, 32, 8)
+    assert abs(p2 / p1 - 4.0) < 1e-12
+
+
 # ---------------------------------------------------------------- grids
 
 def test_grid_builder_reproduces_printed_voxel_counts():
