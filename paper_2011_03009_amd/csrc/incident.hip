@@ -101,34 +101,6 @@ k_incident_at(const double *__restrict__ pts, int n_p, const double *__restrict_
 
 }  // namespace
 
-extern "C" nvp_status nvp_incident_field(nvp_ctx *ctx, double k_re, double k_im, double s_re, double s_im,
-                                         const double *points_dev, int64_t n_points, const nvp_grid *g,
-                                         void *out_dev, nvp_prec prec) {
-    if (!ctx) return NVP_E_INVALID;
-    if (!points_dev || !g || !out_dev || n_points < 1 || n_points > INT32_MAX ||
-        (prec != NVP_C64 && prec != NVP_C128))
-        return nvp::ctx_fail(ctx, NVP_E_INVALID, "nvp_incident_field: bad argument");
-    if (!std::isfinite(k_re) || !std::isfinite(k_im) || k_im < 0.0 || !std::isfinite(s_re) || !std::isfinite(s_im))
-        return nvp::ctx_fail(ctx, NVP_E_INVALID, "nvp_incident_field: k must be finite with Im k >= 0, scale finite");
-    if (!(g->h > 0.0) || !std::isfinite(g->h) || g->n[0] < 1 || g->n[1] < 1 || g->n[2] < 1 ||
-        g->n[0] >= (1 << 30) || g->n[1] >= (1 << 30) || g->n[2] >= (1 << 30) || !std::isfinite(g->origin[0]) ||
-        !std::isfinite(g->origin[1]) || !std::isfinite(g->origin[2]))
-        return nvp::ctx_fail(ctx, NVP_E_INVALID, "nvp_incident_field: bad grid");
-    const int64_t N = g->n[0] * g->n[1] * g->n[2];
-    const int64_t blocks = (N + kBlock - 1) / kBlock;
-    if (blocks > INT32_MAX) return nvp::ctx_fail(ctx, NVP_E_UNSUPPORTED, "nvp_incident_field: grid too large");
-    hipError_t e = hipSetDevice(nvp::ctx_device(ctx));
-    if (e != hipSuccess) return nvp::ctx_hip_fail(ctx, "hipSetDevice", e);
-    const hipStream_t s = nvp::ctx_stream(ctx);
-    auto kern = prec == NVP_C128 ? k_incident<true> : k_incident<false>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlock), 0, s, points_dev, (int)n_points, g->origin[0],
-                       g->origin[1], g->origin[2], g->h, (int)g->n[1], (int)g->n[2], N, k_re, k_im, s_re, s_im,
-                       out_dev);
-    e = hipGetLastError();
-    if (e != hipSuccess) return nvp::ctx_hip_fail(ctx, "k_incident launch", e);
-    return NVP_OK;
-}
-
 namespace {
 
 bool points_ok(nvp_ctx *ctx, double k_re, double k_im, double s_re, double s_im, const double *points_dev,
@@ -161,6 +133,36 @@ struct DevMem {
 };
 
 }  // namespace
+
+extern "C" nvp_status nvp_incident_field(nvp_ctx *ctx, double k_re, double k_im, double s_re, double s_im,
+                                         const double *points_dev, int64_t n_points, const nvp_grid *g,
+                                         void *out_dev, nvp_prec prec) {
+    if (!ctx) return NVP_E_INVALID;
+    nvp_status st = NVP_OK;
+    if (!points_ok(ctx, k_re, k_im, s_re, s_im, points_dev, n_points, "nvp_incident_field", &st)) return st;
+    if (!g || !out_dev || (prec != NVP_C64 && prec != NVP_C128))
+        return nvp::ctx_fail(ctx, NVP_E_INVALID, "nvp_incident_field: bad argument");
+    if (!(g->h > 0.0) || !std::isfinite(g->h) || g->n[0] < 1 || g->n[1] < 1 || g->n[2] < 1 ||
+        g->n[0] >= (1 << 30) || g->n[1] >= (1 << 30) || g->n[2] >= (1 << 30) || !std::isfinite(g->origin[0]) ||
+        !std::isfinite(g->origin[1]) || !std::isfinite(g->origin[2]))
+        return nvp::ctx_fail(ctx, NVP_E_INVALID, "nvp_incident_field: bad grid");
+    // one thread per voxel: at most 2^31 - 1 workgroups of kBlock threads
+    if ((double)g->n[0] * (double)g->n[1] * (double)g->n[2] > (double)INT32_MAX * kBlock)
+        return nvp::ctx_fail(ctx, NVP_E_UNSUPPORTED, "nvp_incident_field: grid too large");
+    const int64_t N = g->n[0] * g->n[1] * g->n[2];
+    const int64_t blocks = (N + kBlock - 1) / kBlock;
+    hipError_t e = hipSetDevice(nvp::ctx_device(ctx));
+    if (e != hipSuccess) return nvp::ctx_hip_fail(ctx, "hipSetDevice", e);
+    const hipStream_t s = nvp::ctx_stream(ctx);
+    auto kern = prec == NVP_C128 ? k_incident<true> : k_incident<false>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlock), 0, s, points_dev, (int)n_points, g->origin[0],
+                       g->origin[1], g->origin[2], g->h, (int)g->n[1], (int)g->n[2], N, k_re, k_im, s_re, s_im,
+                       out_dev);
+    e = hipGetLastError();
+    if (e != hipSuccess) return nvp::ctx_hip_fail(ctx, "k_incident launch", e);
+    return NVP_OK;
+}
+
 
 extern "C" nvp_status nvp_incident_at(nvp_ctx *ctx, double k_re, double k_im, double s_re, double s_im,
                                       const double *points_dev, int64_t n_points, const double *targets_dev,
