@@ -171,7 +171,7 @@ nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nv
  * paper recommends); target centres are clamped into the source grid's hull,
  * and a field on the very grid it is needed on is used as is.  Every axis
  * of a source grid needs at least transfer_order + 1 voxels, and every axis
- * a circulant length (nvp_circulant_size; up to 768 voxels in this build). */
+ * a circulant length (nvp_circulant_size; up to 1024 voxels in this build). */
 nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int n_harm,
                             const nvp_grid *g1, const nvp_grid *gn, nvp_prec prec,
                             int transfer_order, nvp_plan **out);

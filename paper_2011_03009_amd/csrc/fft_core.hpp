@@ -248,6 +248,7 @@ __host__ __device__ constexpr PlanDesc plan_for(int L) {
     case 1024: return PlanDesc{3, {16, 8, 8, 0, 0, 0}, 32};
     case 1280: return PlanDesc{4, {5, 8, 8, 4, 0, 0}, 40};
     case 1536: return PlanDesc{4, {3, 8, 8, 8, 0, 0}, 24};
+    case 2048: return PlanDesc{3, {16, 16, 8, 0, 0, 0}, 32};
     default: return PlanDesc{0, {0, 0, 0, 0, 0, 0}, 0};
     }
 }

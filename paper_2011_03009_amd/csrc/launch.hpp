@@ -9,7 +9,7 @@
 // Transform lengths with a compiled radix plan.
 #define NVP_FOR_EACH_LENGTH(X) \
     X(16) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(448) X(512) X(640) X(768) X(896) \
-    X(1024) X(1280) X(1536)
+    X(1024) X(1280) X(1536) X(2048)
 
 namespace nvp {
 

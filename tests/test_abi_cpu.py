@@ -80,12 +80,13 @@ def test_transfer_tables_bit_exact_indices(order):
 
 
 def test_circulant_sizes():
-    for n in (1, 2, 7, 8, 9, 16, 17, 32, 48, 80, 96, 100, 128, 160, 200, 256, 320, 384, 448, 512, 640, 641, 768):
+    for n in (1, 2, 7, 8, 9, 16, 17, 32, 48, 80, 96, 100, 128, 160, 200, 256, 320, 384, 448, 512, 640, 641, 768,
+              769, 1024):
         m = P.circulant_size(n)
         assert m >= 2 * n - 1 and m % 2 == 0
-    assert P.circulant_size(640) == 1280 and P.circulant_size(641) == 1536
+    assert P.circulant_size(640) == 1280 and P.circulant_size(641) == 1536 and P.circulant_size(769) == 2048
     with pytest.raises(P.NvpError):
-        P.circulant_size(769)
+        P.circulant_size(1025)
 
 
 def test_host_calls_reject_invalid_arguments():

@@ -22,7 +22,7 @@ WATER = configs.WATER
 F0 = 1.1e6
 TOL = {P.NVP_C64: 1e-5, P.NVP_C128: 1e-12}
 DT = {P.NVP_C64: torch.complex64, P.NVP_C128: torch.complex128}
-LENGTHS = [16, 32, 48, 64, 96, 128, 160, 192, 256, 320, 384, 448, 512, 640, 768, 896, 1024, 1280, 1536]
+LENGTHS = [16, 32, 48, 64, 96, 128, 160, 192, 256, 320, 384, 448, 512, 640, 768, 896, 1024, 1280, 1536, 2048]
 
 
 def say(*a):

@@ -1,0 +1,55 @@
+"""The truncation-convergence study of Section 5 (paper_2011_03009_amd.truncation_study), small.
+
+A 7.5 mm / 15 mm bowl at 1.1 MHz in water, 2 W, harmonics 2..3: the axis
+error of the cut sources must fall as the localisation boxes grow, reach
+rounding level for the loosest box, and the reported fractions must be
+fractions of the reference domain.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from workload import bowl, configs
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2011_03009_amd")
+TS = pytest.importorskip("paper_2011_03009_amd.truncation_study")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context(0)
+    yield c
+    c.sync()
+    c.close()
+
+
+def test_small_study(ctx):
+    T = dict(f0=1.1e6, l=15e-3, R=7.5e-3)
+    pts = torch.from_numpy(bowl.bowl_points(T["R"], T["l"], 1024, 0)).to("cuda")
+    q0 = tuple(-0.5 * i for i in range(1, 17))
+    say("case truncation study (small bowl)")
+    recs = TS.study(ctx, T, configs.WATER, 2.0, 3e-3, pts, n_max=3, q0=q0, log=say)
+    assert [r["n"] for r in recs] == [2, 3]
+    for r in recs:
+        e, f = r["err"], r["fractions"]
+        assert np.all((f >= 0) & (f <= 1))
+        assert np.all(np.diff(f[:, 0]) >= -1e-12)  # looser thresholds, larger boxes
+        assert e[-1] < 1e-4 and e[0] > 10 * e[-1]
+        assert 0 < r["need_x"] <= 1 and 0 < r["need_yz"] <= 1
+        assert 0 < r["size_x"] <= 1 and 0 < r["size_yz"] <= 1
+        assert r["rel_norm"] > 0
+    # the power normalisation: the scale radiates 2 W
+    s = TS.normalised_incident(ctx, T, configs.WATER, 2.0, pts)
+    pw = P.radiated_power(ctx, P.wavenumber(configs.WATER, T["f0"], 1), s, pts, (TS.cap_height(T), 0.0, 0.0),
+                          T["R"], configs.WATER["rho0"], configs.WATER["c0"], 256, 256)
+    assert abs(pw - 2.0) < 1e-9

@@ -13,6 +13,8 @@ beta = 3.5, and the water attenuation of the paper's medium table
 """
 
 WATER = dict(c0=1487.0, rho0=998.0, beta=3.5, alpha0_db=0.2, eta=2.0)
+# Liver as the paper's table of media gives it (alpha0 in dB/m at 1 MHz, power-law exponent eta).
+LIVER = dict(c0=1590.0, rho0=1060.0, beta=4.4, alpha0_db=90.0, eta=1.1)
 
 # The two transducers of the paper's transducer table (f0 in Hz, lengths in m).
 H101 = dict(f0=1.1e6, l=63.2e-3, R=32e-3)
