@@ -163,6 +163,25 @@ nvp_status nvp_radiated_power(nvp_ctx *ctx, double k_re, double k_im, double s_r
 nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nvp_grid *g,
                                 const void *f_dev, void *u_dev, nvp_prec prec);
 
+
+/* Volume integral equation of an inhomogeneous medium (Section 7, the
+ * equations of the harmonics in an inhomogeneous domain): with background
+ * wavenumber kb (Im kb >= 0) and contrast q_j = k(x_j)^2 - kb^2 per voxel,
+ *   p_i - sum_j K_kb(x_i - x_j) q_j p_j = rhs_i   on grid g,
+ * K the midpoint-rule kernel of nvp_volume_potential.  Solved by BiCGStab
+ * with that operator: p_dev holds the initial guess on entry and the solution
+ * on return; stops when the recursive residual falls to tol * ||rhs|| or after
+ * max_iter iterations.  *iters receives the iterations taken and *relres the
+ * true relative residual ||rhs - A p|| / ||rhs|| of the returned p (check it:
+ * reaching max_iter is not an error).  q_dev, rhs_dev, p_dev: N complex values
+ * in prec (device, caller-owned; p may not alias q or rhs).  Synchronous:
+ * every inner product waits for the context stream.  Allocates 8 N complex
+ * values for the call; uses the context's volume-potential cache.
+ * NVP_E_INVALID: bad arguments; NVP_E_STATE: a breakdown of the recurrence. */
+nvp_status nvp_vie_solve(nvp_ctx *ctx, double kb_re, double kb_im, const nvp_grid *g, const void *q_dev,
+                         const void *rhs_dev, void *p_dev, nvp_prec prec, double tol, int max_iter, int *iters,
+                         double *relres);
+
 /* ---- the nested-mesh cascade (Section 6) ----------------------------------- */
 
 /* Plan harmonics 2..n_harm.  g1: grid of the incident field p_1 (Section 3.2);

@@ -11,3 +11,4 @@ Parity status of each function is stated in its docstring; none is
 
 from .core import *  # noqa: F401,F403
 from .incident import incident_at, incident_field, radiated_power  # noqa: F401
+from .vie import dense_operator, vie_solve  # noqa: F401

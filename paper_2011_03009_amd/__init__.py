@@ -8,4 +8,4 @@ from . import nvp  # noqa: F401
 from .nvp import (NVP_C64, NVP_C128, Batch, BoxNet, CascadePlan, Context, NvpError, box_potential,  # noqa: F401
                   incident_at, incident_field, radiated_power,
                   cascade_constant, circulant_size, grid, grid_from_box, grid_from_counts, qbox,
-                  rule_of_thumb_box, spacing, volume_potential, wavenumber)
+                  rule_of_thumb_box, spacing, vie_solve, volume_potential, wavenumber)

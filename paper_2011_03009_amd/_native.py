@@ -46,6 +46,8 @@ SIGNATURES = {
     "nvp_circulant_size": (_st, [_i64, _i64p]),
     "nvp_volume_potential": (_st, [_vp, _d, _d, ctypes.POINTER(Grid), _vp, _vp, _i]),
     "nvp_incident_field": (_st, [_vp, _d, _d, _d, _d, _vp, ctypes.c_int64, ctypes.POINTER(Grid), _vp, _i]),
+    "nvp_vie_solve": (_st, [_vp, _d, _d, ctypes.POINTER(Grid), _vp, _vp, _vp, _i, _d, _i, ctypes.POINTER(_i),
+                            ctypes.POINTER(_d)]),
     "nvp_incident_at": (_st, [_vp, _d, _d, _d, _d, _vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _i]),
     "nvp_radiated_power": (_st, [_vp, _d, _d, _d, _d, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), _d, _d, _d,
                                  _i, _i, ctypes.POINTER(ctypes.c_double)]),

@@ -1,0 +1,225 @@
+// Volume integral equations of an inhomogeneous medium (Section 7, the
+// equations for the harmonics in an inhomogeneous domain): with the
+// background wavenumber kb and the contrast q(y) = k(y)^2 - kb^2,
+//     p(x) - int G_kb(x, y) q(y) p(y) dy = rhs(x),
+// discretised with the same midpoint-rule kernel as the volume potential:
+//     p_i - sum_j K_kb(x_i - x_j) q_j p_j = rhs_i.
+// Solved by BiCGStab (van der Vorst's stabilised bi-conjugate gradients) with
+// the library's FFT volume potential as the operator.  The vector updates
+// and the inner products (accumulated in FP64) are the kernels below; the
+// scalar recurrences run on the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/nvp.h"
+
+namespace nvp {
+int ctx_device(const nvp_ctx *c);
+hipStream_t ctx_stream(const nvp_ctx *c);
+nvp_status ctx_fail(nvp_ctx *c, nvp_status s, const char *msg);
+nvp_status ctx_hip_fail(nvp_ctx *c, const char *what, hipError_t e);
+}  // namespace nvp
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kDotBlocks = 1024;
+
+template <typename V> struct Real;
+template <> struct Real<float2> { using type = float; };
+template <> struct Real<double2> { using type = double; };
+
+template <typename V> __device__ __forceinline__ V mk(double x, double y) {
+    using R = typename Real<V>::type;
+    return V{(R)x, (R)y};
+}
+
+// out = q * x
+template <typename V>
+__global__ void __launch_bounds__(kBlock) k_mul(V *__restrict__ out, const V *__restrict__ q, const V *__restrict__ x,
+                                                int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const V a = q[i], b = x[i];
+    out[i] = V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// out = a + al * b + be * c; a null operand counts as zero.  out may be any
+// of the operands (each element is read before it is written).
+template <typename V>
+__global__ void __launch_bounds__(kBlock) k_lin3(V *out, const V *a, const V *b, const V *c, double2 al, double2 be,
+                                                 int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const V A = a ? a[i] : mk<V>(0.0, 0.0), B = b ? b[i] : mk<V>(0.0, 0.0), C = c ? c[i] : mk<V>(0.0, 0.0);
+    const V p = mk<V>(al.x, al.y), r = mk<V>(be.x, be.y);
+    out[i] = V{A.x + p.x * B.x - p.y * B.y + r.x * C.x - r.y * C.y, A.y + p.x * B.y + p.y * B.x + r.x * C.y + r.y * C.x};
+}
+
+// Partial sums of conj(a_i) b_i in FP64, one per workgroup (grid-stride).
+template <typename V>
+__global__ void __launch_bounds__(kBlock) k_dot(const V *__restrict__ a, const V *__restrict__ b, int64_t n,
+                                                double2 *__restrict__ part) {
+    __shared__ double sr[kBlock], si[kBlock];
+    double re = 0.0, im = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const double ax = a[i].x, ay = a[i].y, bx = b[i].x, by = b[i].y;
+        re += ax * bx + ay * by;
+        im += ax * by - ay * bx;
+    }
+    sr[threadIdx.x] = re;
+    si[threadIdx.x] = im;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sr[threadIdx.x] += sr[threadIdx.x + w];
+            si[threadIdx.x] += si[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(sr[0], si[0]);
+}
+
+using cd = std::complex<double>;
+
+struct DevMem {
+    void *p = nullptr;
+    ~DevMem() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+// The solver's state for one call: vectors of n complex values of type V.
+template <typename V> struct Solver {
+    nvp_ctx *ctx;
+    hipStream_t s;
+    int64_t n;
+    double kr, ki;
+    const nvp_grid *g;
+    nvp_prec prec;
+    const V *q;
+    double2 *part;  // kDotBlocks partial sums
+    V *tmp, *u;     // operator scratch
+    nvp_status st = NVP_OK;
+
+    unsigned blocks() const { return (unsigned)((n + kBlock - 1) / kBlock); }
+    bool ok(hipError_t e, const char *what) {
+        if (e != hipSuccess && st == NVP_OK) st = nvp::ctx_hip_fail(ctx, what, e);
+        return st == NVP_OK;
+    }
+    bool lin3(V *out, const V *a, const V *b, const V *c, cd al, cd be) {
+        hipLaunchKernelGGL(k_lin3<V>, dim3(blocks()), dim3(kBlock), 0, s, out, a, b, c,
+                           make_double2(al.real(), al.imag()), make_double2(be.real(), be.imag()), n);
+        return ok(hipGetLastError(), "k_lin3");
+    }
+    // y = A x = x - V[q x] = x + u, with u = -V[q x] the raw operator's output
+    bool apply(V *y, const V *x) {
+        hipLaunchKernelGGL(k_mul<V>, dim3(blocks()), dim3(kBlock), 0, s, tmp, q, x, n);
+        if (!ok(hipGetLastError(), "k_mul")) return false;
+        const nvp_status e = nvp_volume_potential(ctx, kr, ki, g, tmp, u, prec);
+        if (e != NVP_OK) {
+            st = e;
+            return false;
+        }
+        return lin3(y, x, u, nullptr, 1.0, 0.0);
+    }
+    bool dot(const V *a, const V *b, cd *out) {
+        const unsigned nb = (unsigned)std::min<int64_t>(kDotBlocks, blocks());
+        hipLaunchKernelGGL(k_dot<V>, dim3(nb), dim3(kBlock), 0, s, a, b, n, part);
+        if (!ok(hipGetLastError(), "k_dot")) return false;
+        std::vector<double2> h(nb);
+        if (!ok(hipMemcpyAsync(h.data(), part, nb * sizeof(double2), hipMemcpyDeviceToHost, s), "dot copy")) return false;
+        if (!ok(hipStreamSynchronize(s), "dot sync")) return false;
+        double re = 0.0, im = 0.0;
+        for (const double2 &v : h) re += v.x, im += v.y;
+        *out = cd(re, im);
+        return true;
+    }
+    bool norm(const V *a, double *out) {
+        cd d;
+        if (!dot(a, a, &d)) return false;
+        *out = std::sqrt(std::max(0.0, d.real()));
+        return true;
+    }
+};
+
+template <typename V>
+nvp_status bicgstab(nvp_ctx *ctx, double kr, double ki, const nvp_grid *g, nvp_prec prec, const void *q_dev,
+                    const void *rhs_dev, void *p_dev, double tol, int max_iter, int *iters, double *relres) {
+    const int64_t n = g->n[0] * g->n[1] * g->n[2];
+    DevMem mem;
+    hipError_t e = hipMalloc(&mem.p, 8 * n * sizeof(V) + kDotBlocks * sizeof(double2));
+    if (e != hipSuccess) return nvp::ctx_hip_fail(ctx, "nvp_vie_solve: work vectors", e);
+    V *w = static_cast<V *>(mem.p);
+    V *r = w, *rh = w + n, *pv = w + 2 * n, *v = w + 3 * n, *sv = w + 4 * n, *t = w + 5 * n;
+    Solver<V> S{ctx, nvp::ctx_stream(ctx), n, kr, ki, g, prec, static_cast<const V *>(q_dev),
+                reinterpret_cast<double2 *>(w + 8 * n), w + 6 * n, w + 7 * n};
+    const V *b = static_cast<const V *>(rhs_dev);
+    V *x = static_cast<V *>(p_dev);
+    *iters = 0;
+    double bn = 0.0, rn = 0.0;
+    if (!S.norm(b, &bn)) return S.st;
+    if (bn == 0.0) {  // the solution is zero
+        S.lin3(x, nullptr, nullptr, nullptr, 0.0, 0.0);
+        *relres = 0.0;
+        return S.st;
+    }
+    // r = b - A x, rh = r
+    if (!S.apply(t, x) || !S.lin3(r, b, t, nullptr, -1.0, 0.0) || !S.lin3(rh, r, nullptr, nullptr, 0.0, 0.0) ||
+        !S.lin3(pv, nullptr, nullptr, nullptr, 0.0, 0.0) || !S.lin3(v, nullptr, nullptr, nullptr, 0.0, 0.0) ||
+        !S.norm(r, &rn))
+        return S.st;
+    cd rho = 1.0, alpha = 1.0, omega = 1.0;
+    int it = 0;
+    while (rn / bn > tol && it < max_iter) {
+        ++it;
+        cd rho1;
+        if (!S.dot(rh, r, &rho1)) return S.st;
+        if (std::abs(rho1) == 0.0 || std::abs(omega) == 0.0)
+            return nvp::ctx_fail(ctx, NVP_E_STATE, "nvp_vie_solve: BiCGStab breakdown");
+        const cd beta = (rho1 / rho) * (alpha / omega);
+        cd rv;
+        if (!S.lin3(pv, r, pv, v, beta, -beta * omega) || !S.apply(v, pv) || !S.dot(rh, v, &rv)) return S.st;
+        if (std::abs(rv) == 0.0) return nvp::ctx_fail(ctx, NVP_E_STATE, "nvp_vie_solve: BiCGStab breakdown");
+        alpha = rho1 / rv;
+        double sn;
+        if (!S.lin3(sv, r, v, nullptr, -alpha, 0.0) || !S.norm(sv, &sn)) return S.st;
+        if (sn / bn <= tol) {
+            if (!S.lin3(x, x, pv, nullptr, alpha, 0.0)) return S.st;
+            rn = sn;
+            break;
+        }
+        cd ts, tt;
+        if (!S.apply(t, sv) || !S.dot(t, sv, &ts) || !S.dot(t, t, &tt)) return S.st;
+        omega = tt.real() > 0.0 ? ts / tt : cd(0.0);
+        if (!S.lin3(x, x, pv, sv, alpha, omega) || !S.lin3(r, sv, t, nullptr, -omega, 0.0) || !S.norm(r, &rn))
+            return S.st;
+        rho = rho1;
+    }
+    *iters = it;
+    // the true residual of the returned solution
+    if (!S.apply(t, x) || !S.lin3(r, b, t, nullptr, -1.0, 0.0) || !S.norm(r, &rn)) return S.st;
+    *relres = rn / bn;
+    return NVP_OK;
+}
+
+}  // namespace
+
+extern "C" nvp_status nvp_vie_solve(nvp_ctx *ctx, double kb_re, double kb_im, const nvp_grid *g, const void *q_dev,
+                                    const void *rhs_dev, void *p_dev, nvp_prec prec, double tol, int max_iter,
+                                    int *iters, double *relres) {
+    if (!ctx) return NVP_E_INVALID;
+    if (!g || !q_dev || !rhs_dev || !p_dev || !iters || !relres || p_dev == q_dev || p_dev == rhs_dev ||
+        !(tol > 0.0) || !std::isfinite(tol) || max_iter < 1 || (prec != NVP_C64 && prec != NVP_C128) ||
+        g->n[0] < 1 || g->n[1] < 1 || g->n[2] < 1)
+        return nvp::ctx_fail(ctx, NVP_E_INVALID, "nvp_vie_solve: bad argument");
+    hipError_t e = hipSetDevice(nvp::ctx_device(ctx));
+    if (e != hipSuccess) return nvp::ctx_hip_fail(ctx, "hipSetDevice", e);
+    return prec == NVP_C128
+               ? bicgstab<double2>(ctx, kb_re, kb_im, g, prec, q_dev, rhs_dev, p_dev, tol, max_iter, iters, relres)
+               : bicgstab<float2>(ctx, kb_re, kb_im, g, prec, q_dev, rhs_dev, p_dev, tol, max_iter, iters, relres);
+}

@@ -220,6 +220,25 @@ def radiated_power(ctx, k, scale, points, centre, radius, rho0, c0, n_r=512, n_t
     return out.value
 
 
+def vie_solve(ctx, kb, g, q, rhs, p=None, tol=1e-10, max_iter=500):
+    """Solve p - sum_j K_kb(x_i - x_j) q_j p_j = rhs on grid g (BiCGStab); p: initial guess (zeros if None).
+    Returns (p, iterations, true relative residual)."""
+    g = grid(g)
+    n = tuple(g.n)
+    numel = n[0] * n[1] * n[2]
+    _need(q, q.dtype, numel, "q")
+    _need(rhs, q.dtype, numel, "rhs")
+    if p is None:
+        p = torch.zeros(n, dtype=q.dtype, device=q.device)
+    _need(p, q.dtype, numel, "p")
+    kb = complex(kb)
+    it, rr = ctypes.c_int(), ctypes.c_double()
+    _check(_native.lib().nvp_vie_solve(ctx.handle, kb.real, kb.imag, ctypes.byref(g), _ptr(q), _ptr(rhs), _ptr(p),
+                                       prec_of(q.dtype), float(tol), int(max_iter), ctypes.byref(it),
+                                       ctypes.byref(rr)), ctx.handle)
+    return p, it.value, rr.value
+
+
 def volume_potential(ctx, k, g, f, out=None):
     """u = -sum_j K(x_i - x_j) f_j on grid g (complex64 or complex128 f of shape g.n)."""
     g = grid(g)

@@ -244,6 +244,30 @@ def test_radiated_power_of_an_axial_monopole():
     assert abs(p2 / p1 - 4.0) < 1e-12
 
 
+def test_vie_oracle_identity_and_born_series():
+    """No contrast: p = rhs.  Contrast eps q: p = rhs + eps V[q rhs] + eps^2 V[q V[q rhs]] + O(eps^3),
+    V the direct-sum volume potential."""
+    n, h = (5, 4, 6), 1e-4
+    kb = 2 * 4647.91 + 0.3j
+    rng = np.random.default_rng(3)
+    rhs = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    q = (rng.standard_normal(n) + 1j * rng.standard_normal(n)) * abs(kb) ** 2
+    assert np.allclose(oracle.vie_solve(np.zeros(n, complex), rhs, h, kb), rhs, rtol=0, atol=1e-14)
+    b1 = oracle.conv_direct(q * rhs, h, kb)
+    b2 = oracle.conv_direct(q * b1, h, kb)
+    errs = []
+    for eps in (1e-2, 5e-3, 2.5e-3):
+        p = oracle.vie_solve(eps * q, rhs, h, kb)
+        r = (p - rhs - eps * b1 - eps ** 2 * b2) / np.max(np.abs(b2))
+        errs.append(np.max(np.abs(r)) / eps ** 2)
+    # the remainder after two Born terms is O(eps^3): it halves with eps (relative to eps^2)
+    assert errs[1] < 0.6 * errs[0] and errs[2] < 0.6 * errs[1], errs
+    # the dense operator is the direct sum
+    f = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    D = oracle.dense_operator(kb, h, n)
+    assert np.allclose(D @ f.reshape(-1), oracle.conv_direct(f, h, kb).reshape(-1), rtol=1e-13, atol=0)
+
+
 # ---------------------------------------------------------------- grids
 
 def test_grid_builder_reproduces_printed_voxel_counts():
