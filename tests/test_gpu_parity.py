@@ -328,8 +328,8 @@ def test_error_codes(ctx):
         P.CascadePlan(ctx, WATER, F0, g, [g], order=2)
     assert e.value.status == 4
     with pytest.raises(P.NvpError) as e:
-        P.volume_potential(ctx, 9000.0, grid_of((700, 2, 2)), torch.zeros((700, 2, 2), dtype=torch.complex64,
-                                                                          device="cuda"))
+        P.volume_potential(ctx, 9000.0, grid_of((1100, 2, 2)), torch.zeros((1100, 2, 2), dtype=torch.complex64,
+                                                                           device="cuda"))
     assert e.value.status == 4
     small = grid_of((3, 8, 8))
     with pytest.raises(P.NvpError) as e:
