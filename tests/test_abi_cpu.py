@@ -103,3 +103,20 @@ def test_host_calls_reject_invalid_arguments():
     assert L.nvp_transfer_axis(0.0, 1.0, 4, 0.0, 1.0, 8, 2, b, w) == 1  # unsupported order
     assert L.nvp_ctx_create(0, None, None) == 1
     assert L.nvp_status_str(4) == b"unsupported"
+
+
+def test_h101_nested_grids_match_the_paper():
+    """The rule-of-thumb boxes of H101 (1.1 MHz, l 63.2 mm, R 32 mm, d 10.5 mm) at lambda_n / 6 in water:
+    the paper prints 1.86, 2.01, 2.15 and 2.30 x 10^8 voxels for p2..p5, and 2.9 x 10^9 for one mesh
+    of the reference domain at lambda_5 / 6."""
+    W = dict(c0=1487.0, rho0=998.0, beta=3.5, alpha0_db=0.2, eta=2.0)
+    f0, l, R, d = 1.1e6, 63.2e-3, 32e-3, 10.5e-3
+    counts = []
+    for n in range(2, 6):
+        g, _ = P.grid_from_box((l, 0.0, 0.0), *P.rule_of_thumb_box(n, l, R, d), P.spacing(W, f0, n))
+        counts.append(int(g.n[0]) * int(g.n[1]) * int(g.n[2]))
+    assert [round(c / 1e8, 2) for c in counts] == [1.86, 2.01, 2.16, 2.31]
+    for printed, c in zip((1.86e8, 2.01e8, 2.15e8, 2.30e8), counts):
+        assert abs(c / printed - 1.0) < 0.005
+    g, _ = P.grid_from_box((l, 0.0, 0.0), *P.rule_of_thumb_box(2, l, R, d), P.spacing(W, f0, 5))
+    assert abs(int(g.n[0]) * int(g.n[1]) * int(g.n[2]) / 2.9e9 - 1.0) < 0.01
