@@ -644,11 +644,19 @@ k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, 
     stage_table<double>(twl, tw, NT);
     __syncthreads();
     auto twf = [&](int e) { return twl[e]; };
-#pragma unroll 1
-    for (int k = t; k < HZ; k += F::P) {
-        double2 v = make_double2(0.0, 0.0);
-        if (act && i < Nx && jj < Ny && k < Nz) v = ktab[i * i + jj * jj + (int64_t)k * k];
-        my[padded<double>(k)] = v;
+    // all of this thread's gathers in flight before the first store
+    constexpr int NK = (HZ + F::P - 1) / F::P;
+    double2 g[NK];
+#pragma unroll
+    for (int q = 0; q < NK; ++q) {
+        const int k = t + q * F::P;
+        g[q] = (act && i < Nx && jj < Ny && k < Nz && k < HZ) ? ktab[i * i + jj * jj + (int64_t)k * k]
+                                                             : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < NK; ++q) {
+        const int k = t + q * F::P;
+        if (k < HZ) my[padded<double>(k)] = g[q];
     }
     wave_sync();
     F::template run<-1, true>(
