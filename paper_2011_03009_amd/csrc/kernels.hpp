@@ -436,13 +436,16 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
         const int zz = iz0 + tz, yy = iy0 + ty;
         const bool okz = zz < Nz, oky = yy < Ny;
         const int oz = okz ? g.b[2][zz] - sz0 : 0, oy = oky ? g.b[1][yy] - sy0 : 0;
-        R wz[K], wy[K], wx[TX][K];
+        // a voxel's K weights are contiguous and aligned to their size (the
+        // host aligns each table to 256 bytes): one vector load each
+        struct alignas(sizeof(R) * K) Wk {
+            R v[K];
+        };
+        R wx[TX][K];
         int ox[TX];
-#pragma unroll
-        for (int d = 0; d < K; ++d) {
-            wz[d] = okz ? g.w[2][zz * K + d] : R(0);
-            wy[d] = oky ? g.w[1][yy * K + d] : R(0);
-        }
+        const Wk wzv = okz ? *reinterpret_cast<const Wk *>(g.w[2] + zz * K) : Wk{};
+        const Wk wyv = oky ? *reinterpret_cast<const Wk *>(g.w[1] + yy * K) : Wk{};
+        const R *wz = wzv.v, *wy = wyv.v;
 #pragma unroll
         for (int a = 0; a < TX; ++a) {
             const bool okx = ix0 + a < Nx;
