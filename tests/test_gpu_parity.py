@@ -316,6 +316,29 @@ def test_uniform_size_volume_potential_sampled(ctx):
     assert oracle.rel_l2(got, ref) < 1e-5
 
 
+@pytest.mark.parametrize("n", [(716, 568, 568), (890, 735, 735)])
+def test_largest_paper_meshes_volume_potential_sampled(ctx, n):
+    """The largest meshes of the paper's own runs, complex64: H101's p5 box (716 x 568^2, circulant
+    1536 x 1280^2) and H131's p5 reference domain of Section 5 (890 x 735^2, circulant 2048 x 1536^2)."""
+    h = oracle.spacing(5, F0, WATER["c0"])
+    c = tuple(v // 2 for v in n)
+    g = grid_of(n, h=h, origin=tuple(-ci * h for ci in c))
+    say("case largest mesh vp n=%s" % (n,))
+    ax = [np.exp(-0.5 * ((np.arange(s) - 0.55 * s) / (0.25 * s)) ** 2) * np.exp(0.2j * np.arange(s)) for s in n]
+    fx = [torch.from_numpy(a).to("cuda") for a in ax]
+    f_dev = (fx[0][:, None, None] * fx[1][None, :, None] * fx[2][None, None, :]).to(torch.complex64).contiguous()
+    k = oracle.wavenumber(5, F0, WATER)
+    u = P.volume_potential(ctx, k, g, f_dev)
+    t = sample_targets(n, c, 8, 9)
+    got = u.reshape(-1)[torch.from_numpy(t).to("cuda")].to(torch.complex128).cpu().numpy()
+    del u
+    f_host = f_dev.to(torch.complex128).cpu().numpy()
+    del f_dev
+    torch.cuda.empty_cache()
+    ref = -oracle.conv_direct(f_host, h, k, targets=t)
+    assert oracle.rel_l2(got, ref) < 1e-5
+
+
 # ------------------------------------------------------------------ error paths
 
 def test_error_codes(ctx):
