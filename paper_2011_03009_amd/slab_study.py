@@ -28,8 +28,9 @@ KIDNEY_TABLE = dict(c0=1570.0, beta=4.7, alpha0_db=10.0, eta=1.0)
 
 
 def _slab_range(g, lo, hi):
+    """x-index range [a, b) of the voxel centres with lo <= x < hi."""
     x = g.origin[0] + np.arange(int(g.n[0])) * g.h
-    idx = np.nonzero((x >= lo) & (x <= hi))[0]
+    idx = np.nonzero((x >= lo) & (x < hi))[0]
     return (int(idx[0]), int(idx[-1]) + 1) if idx.size else (0, 0)
 
 

@@ -53,3 +53,17 @@ def test_small_study(ctx):
     pw = P.radiated_power(ctx, P.wavenumber(configs.WATER, T["f0"], 1), s, pts, (TS.cap_height(T), 0.0, 0.0),
                           T["R"], configs.WATER["rho0"], configs.WATER["c0"], 256, 256)
     assert abs(pw - 2.0) < 1e-9
+
+
+def test_slab_study_without_a_layer_is_the_homogeneous_cascade(ctx):
+    """With a layer of zero width there is no contrast: the volume-integral solves return their
+    right-hand sides, i.e. p1 is the incident field and p2 = C_2 V[f_2] is the cascade's p2."""
+    SS = pytest.importorskip("paper_2011_03009_amd.slab_study")
+    T = TS.H131
+    pts = torch.from_numpy(bowl.bowl_points(T["R"], T["l"], 1024, 0)).to("cuda")
+    say("case slab study, no layer")
+    rows = SS.slab(ctx, configs.WATER, pts, width=0.0, n_max=2, log=say)
+    for r in rows:
+        assert r["iterations"] <= 1
+        assert abs(r["focal_slab"] / r["focal_water"] - 1.0) < 1e-5
+        assert abs(r["axis_max_slab"] / r["axis_max_water"] - 1.0) < 1e-5
