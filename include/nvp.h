@@ -216,10 +216,10 @@ nvp_status nvp_plan_set_workspace(nvp_plan *plan, void *dev, size_t bytes);
  * 0: tabulate and transform the kernel again on every execution. */
 nvp_status nvp_plan_set_kernel_cache(nvp_plan *plan, int enable);
 /* 1 (default): nvp_execute_cascade computes the kernel spectra it needs on a
- * second stream of the plan, concurrently with the harmonics' source builds
- * and convolutions (each z pass waits for its spectrum; the second stream
- * first waits for all earlier work of the context stream), using scratch of
- * its own; 0: spectra computed in line.  Ignored while timing is on and while
+ * second stream of the plan, each from the moment the context stream reaches
+ * its harmonic (after all earlier work there), concurrently with that
+ * harmonic's source build and forward x and y passes; the z pass waits for
+ * it.  The second stream uses scratch of its own.  0: spectra computed in line.  Ignored while timing is on and while
  * the context stream is being captured into a graph; off for the plans of a
  * batch.  Results are the same either way. */
 nvp_status nvp_plan_set_overlap(nvp_plan *plan, int enable);

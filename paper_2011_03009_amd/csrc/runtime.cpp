@@ -1021,38 +1021,38 @@ nvp_status nvp_execute_cascade(nvp_plan *plan, const void *p1_dev, void *const *
         else if (pn_dev[n - 2] == p1_dev) return fail(ctx, NVP_E_INVALID, "nvp_execute_cascade: aliased output");
     if (!plan->A || !plan->B) return fail(ctx, NVP_E_STATE, "nvp_execute_cascade: the plan has no work buffers");
     NVP_HIP(ctx, hipSetDevice(ctx->device));
-    std::vector<hipEvent_t> kready(plan->n_harm, nullptr);
     bool need = false;
     for (auto &h : plan->h) need = need || !h.khat_ok || !plan->cache;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     NVP_HIP(ctx, hipStreamIsCapturing(ctx->stream, &cs));
-    if (plan->overlap && !plan->timing && need && cs == hipStreamCaptureStatusNone) {
-        // every kernel spectrum the cascade needs, on the side stream after all
-        // earlier work of the context stream (which may still read the spectra)
+    const bool ovl = plan->overlap && !plan->timing && need && cs == hipStreamCaptureStatusNone;
+    if (ovl) {
         nvp_status st = side_resources(plan);
-        if (st) return st;
-        NVP_HIP(ctx, hipEventRecord(plan->ev_start, ctx->stream));
-        NVP_HIP(ctx, hipStreamWaitEvent(plan->side, plan->ev_start, 0));
-        const hipStream_t user = ctx->stream;
-        ctx->stream = plan->side;
-        for (int n = 2; n <= plan->n_harm && st == NVP_OK; ++n) {
-            Harm &h = plan->h[n - 2];
-            if (h.khat_ok && plan->cache) continue;
-            st = kernel_spectrum(ctx, nullptr, h.kr, h.ki, &h.g, h.M, plan->prec, h.khat, plan->kscr, plan->ktab);
-            if (st == NVP_OK) {
-                hipError_t e = hipEventRecord(plan->ev_k[n - 2], plan->side);
-                if (e != hipSuccess) st = hip_fail(ctx, "hipEventRecord", e);
-                kready[n - 1] = plan->ev_k[n - 2];
-                h.khat_ok = true;
-            }
-        }
-        ctx->stream = user;
         if (st) return st;
     }
     std::vector<const void *> fields(plan->n_harm);
     fields[0] = p1_dev;
     for (int n = 2; n <= plan->n_harm; ++n) {
-        nvp_status st = run_harmonic(plan, n, fields.data(), pn_dev[n - 2], kready[n - 1]);
+        Harm &h = plan->h[n - 2];
+        hipEvent_t kready = nullptr;
+        if (ovl && (!h.khat_ok || !plan->cache)) {
+            // harmonic n's kernel spectrum on the side stream, from the moment the
+            // context stream reaches harmonic n (after all its earlier work, which
+            // may still read the spectrum), concurrently with the source build
+            // and the forward x and y passes; the z pass waits for it
+            NVP_HIP(ctx, hipEventRecord(plan->ev_start, ctx->stream));
+            NVP_HIP(ctx, hipStreamWaitEvent(plan->side, plan->ev_start, 0));
+            const hipStream_t user = ctx->stream;
+            ctx->stream = plan->side;
+            nvp_status st =
+                kernel_spectrum(ctx, nullptr, h.kr, h.ki, &h.g, h.M, plan->prec, h.khat, plan->kscr, plan->ktab);
+            ctx->stream = user;
+            if (st) return st;
+            NVP_HIP(ctx, hipEventRecord(plan->ev_k[n - 2], plan->side));
+            kready = plan->ev_k[n - 2];
+            h.khat_ok = true;
+        }
+        nvp_status st = run_harmonic(plan, n, fields.data(), pn_dev[n - 2], kready);
         if (st) return st;
         fields[n - 1] = pn_dev[n - 2];
     }
