@@ -411,7 +411,7 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
     // latency overlaps the work; a larger block is loaded when it is reached.
     // (complex64 only: complex128 values would spill registers)
     constexpr bool PIPE = sizeof(R) == 4;
-    constexpr int PR = PIPE ? 10 : 1, PZ = PIPE ? 1 : 1;
+    constexpr int PR = PIPE ? 10 : 1, PZ = 1;
     cx<R> pre[PR][PZ];
     int pre_field = -1;
     auto fits = [&](const Block &b) { return PIPE && b.SX * b.SY <= PR * TY && b.SZ <= PZ * TZ; };
