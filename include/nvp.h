@@ -45,6 +45,11 @@ typedef int32_t nvp_status;
 #define NVP_E_HIP 3         /* a HIP runtime call or kernel launch failed */
 #define NVP_E_UNSUPPORTED 4 /* valid request outside what this build handles (an axis beyond the compiled circulant lengths) */
 #define NVP_E_STATE 5       /* call out of order (e.g. timing read while disabled) */
+/* Fault injection for tests: with the environment variable
+ * NVP_DEVICE_ALLOC_LIMIT set to a byte count, every device allocation of the
+ * runtime (plans, batches, the volume-potential cache, twiddle tables, the
+ * autotuner's scratch) larger than that fails as out of memory; calls then
+ * return NVP_E_NOMEM and keep no partial state. */
 
 typedef enum { NVP_C64 = 0, NVP_C128 = 1 } nvp_prec;
 

@@ -131,6 +131,22 @@ nvp_status fail(nvp_ctx *ctx, nvp_status s, const std::string &msg) {
     return s;
 }
 
+// Device allocations of the runtime.  Fault injection for tests: with
+// NVP_DEVICE_ALLOC_LIMIT set (bytes), any single allocation larger than that
+// fails as out of memory, so that every allocation failure path can be
+// exercised with valid sizes.
+hipError_t dev_malloc(void **p, size_t bytes) {
+    if (const char *lim = getenv("NVP_DEVICE_ALLOC_LIMIT")) {
+        char *end = nullptr;
+        const unsigned long long cap = strtoull(lim, &end, 10);
+        if (end != lim && bytes > cap) {
+            *p = nullptr;
+            return hipErrorOutOfMemory;
+        }
+    }
+    return hipMalloc(p, bytes);
+}
+
 nvp_status hip_fail(nvp_ctx *ctx, const char *what, hipError_t e) {
     return fail(ctx, e == hipErrorOutOfMemory ? NVP_E_NOMEM : NVP_E_HIP,
                 std::string(what) + ": " + hipGetErrorString(e));
@@ -201,7 +217,7 @@ nvp_status twiddles(nvp_ctx *ctx, int L, bool dbl, const void **out) {
     const size_t cnt = hd.size() / 2;
     void *dev = nullptr;
     const size_t bytes = cnt * (dbl ? 16 : 8);
-    NVP_HIP(ctx, hipMalloc(&dev, bytes));
+    NVP_HIP(ctx, dev_malloc((void **)&dev, bytes));
     hipError_t err;
     if (dbl) {
         err = hipMemcpy(dev, hd.data(), bytes, hipMemcpyHostToDevice);
@@ -703,9 +719,9 @@ nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nv
         if (c.A) (void)hipFree(c.A);
         if (c.B) (void)hipFree(c.B);
         c = VpCache{};
-        hipError_t e1 = hipMalloc(&c.khat, khat_bytes(M, prec));
-        hipError_t e2 = hipMalloc(&c.A, bytesA(g, M, prec));
-        hipError_t e3 = hipMalloc(&c.B, bytesB(g, M, prec));
+        hipError_t e1 = dev_malloc((void **)&c.khat, khat_bytes(M, prec));
+        hipError_t e2 = dev_malloc((void **)&c.A, bytesA(g, M, prec));
+        hipError_t e3 = dev_malloc((void **)&c.B, bytesB(g, M, prec));
         if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
             if (c.khat) (void)hipFree(c.khat);
             if (c.A) (void)hipFree(c.A);
@@ -863,12 +879,12 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
         else if (elems * (int64_t)csize(prec) <= 98304 && msx <= T[0] - 1 + K) h.src_lds = elems;
     }
     hipError_t e = hipSuccess;
-    if (tbytes) e = hipMalloc(&p->tables, tbytes);
-    if (e == hipSuccess) e = hipMalloc(&p->A, maxA);
-    if (e == hipSuccess) e = hipMalloc(&p->B, maxB);
+    if (tbytes) e = dev_malloc((void **)&p->tables, tbytes);
+    if (e == hipSuccess) e = dev_malloc((void **)&p->A, maxA);
+    if (e == hipSuccess) e = dev_malloc((void **)&p->B, maxB);
     for (auto &h : p->h) {
         if (e != hipSuccess) break;
-        e = hipMalloc(&h.khat, khat_bytes(h.M, prec));
+        e = dev_malloc((void **)&h.khat, khat_bytes(h.M, prec));
         p->bytes_khat += khat_bytes(h.M, prec);
     }
     if (e == hipSuccess && tbytes) e = hipMemcpy(p->tables, host.data(), tbytes, hipMemcpyHostToDevice);
@@ -927,8 +943,8 @@ nvp_status nvp_plan_set_workspace(nvp_plan *plan, void *dev, size_t bytes) {
         plan->own_work = false;
         return NVP_OK;
     }
-    hipError_t e = hipMalloc(&plan->A, bA);
-    if (e == hipSuccess) e = hipMalloc(&plan->B, bB);
+    hipError_t e = dev_malloc((void **)&plan->A, bA);
+    if (e == hipSuccess) e = dev_malloc((void **)&plan->B, bB);
     if (e != hipSuccess) {
         if (plan->A) (void)hipFree(plan->A);
         plan->A = nullptr;
@@ -983,8 +999,8 @@ nvp_status side_resources(nvp_plan *p) {
     if (!p->kscr) {
         size_t ks, kt;
         side_sizes(p, &ks, &kt);
-        NVP_HIP(ctx, hipMalloc(&p->kscr, ks));
-        hipError_t e = hipMalloc(&p->ktab, kt);
+        NVP_HIP(ctx, dev_malloc((void **)&p->kscr, ks));
+        hipError_t e = dev_malloc((void **)&p->ktab, kt);
         if (e != hipSuccess) {
             (void)hipFree(p->kscr);
             p->kscr = nullptr;
@@ -1186,14 +1202,14 @@ nvp_status autotune_plan(nvp_plan *plan, std::map<std::string, Tune> &cache, int
             break;
         }
         void *q = nullptr;
-        NVP_HIP(ctx, hipMalloc(&q, elems * cs));
+        NVP_HIP(ctx, dev_malloc((void **)&q, elems * cs));
         mem.p.push_back(q);
         NVP_HIP(ctx, hipMemsetAsync(q, 0, elems * cs, ctx->stream));
         fields[m - 1] = q;
         if (m >= 2) out_elems = std::max(out_elems, elems);
     }
     void *out = nullptr;
-    NVP_HIP(ctx, hipMalloc(&out, out_elems * cs));
+    NVP_HIP(ctx, dev_malloc((void **)&out, out_elems * cs));
     mem.p.push_back(out);
     hipEvent_t e0, e1;
     NVP_HIP(ctx, hipEventCreate(&e0));
@@ -1445,7 +1461,7 @@ nvp_status build_grouped(nvp_batch *b, const void *const *p1, void *const *pn, s
         b->tasks = nullptr;
     }
     if (!b->tasks && !host.empty()) {
-        NVP_HIP(ctx, hipMalloc(&b->tasks, host.size()));
+        NVP_HIP(ctx, dev_malloc((void **)&b->tasks, host.size()));
         b->tasks_bytes = host.size();
     }
     if (!host.empty()) NVP_HIP(ctx, hipMemcpy(b->tasks, host.data(), host.size(), hipMemcpyHostToDevice));

@@ -341,6 +341,43 @@ def test_largest_paper_meshes_volume_potential_sampled(ctx, n):
 
 # ------------------------------------------------------------------ error paths
 
+def test_allocation_failures_keep_no_state(ctx, monkeypatch):
+    """Forced device allocation failures (NVP_DEVICE_ALLOC_LIMIT): NVP_E_NOMEM, nothing held after,
+    and the same calls succeed once the limit is lifted."""
+    focus = (40e-3, 0.0, 0.0)
+    c0 = WATER["c0"]
+    g1 = oracle.grid_from_counts(focus, oracle.spacing(1, F0, c0), (24, 20, 18), (12, 10, 9))
+    gn = [oracle.grid_from_counts(focus, oracle.spacing(n, F0, c0), (48, 40, 40), (24, 20, 20)) for n in (2, 3)]
+    p1 = dev(fields.smooth_field(g1.n, 3) * 1e6, P.NVP_C64)
+    f = dev(fields.random_field((20, 18, 33), 7), P.NVP_C64)
+    g = grid_of((20, 18, 33))
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    say("case forced allocation failures")  # a wavenumber no other test uses: the context's cache misses
+    # limit 0: every allocation fails; 1 MiB: the plan's tables fit but its work buffers do not
+    for limit in ("0", "1048576"):
+        monkeypatch.setenv("NVP_DEVICE_ALLOC_LIMIT", limit)
+        with pytest.raises(P.NvpError) as e:
+            P.CascadePlan(ctx, WATER, F0, g1, gn, prec=P.NVP_C64, order=3)
+        assert e.value.status == 2
+    monkeypatch.setenv("NVP_DEVICE_ALLOC_LIMIT", "0")
+    with pytest.raises(P.NvpError) as e:
+        P.volume_potential(ctx, 9123.0 + 1j, g, f)
+    assert e.value.status == 2
+    monkeypatch.delenv("NVP_DEVICE_ALLOC_LIMIT")
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] >= free0 - (8 << 20)  # nothing new held (a cache may have been freed)
+    plan = P.CascadePlan(ctx, WATER, F0, g1, gn, prec=P.NVP_C64, order=3)
+    a = [t.clone() for t in plan.execute(p1)]
+    b = plan.execute(p1)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(a, b)) and all(bool(torch.isfinite(x).all()) for x in a)
+    plan.close()
+    u = P.volume_potential(ctx, 9123.0 + 1j, g, f)
+    torch.cuda.synchronize()
+    ref = -oracle.conv_direct(f.to(torch.complex128).cpu().numpy(), g.h, 9123.0 + 1j)
+    assert oracle.rel_l2(host(u), ref) < 1e-5
+
 def test_error_codes(ctx):
     g = grid_of((8, 8, 8))
     f = torch.zeros((8, 8, 8), dtype=torch.complex64, device="cuda")
