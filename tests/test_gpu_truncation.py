@@ -67,3 +67,15 @@ def test_slab_study_without_a_layer_is_the_homogeneous_cascade(ctx):
         assert r["iterations"] <= 1
         assert abs(r["focal_slab"] / r["focal_water"] - 1.0) < 1e-5
         assert abs(r["axis_max_slab"] / r["axis_max_water"] - 1.0) < 1e-5
+
+
+def test_h131_second_harmonic_needs_the_whole_axial_length(ctx):
+    """The paper's observation for H131 at 100 W in water: below 1% error the domain of p2 must
+    reach all the way to the transducer (x fraction 1), while about three quarters of the width
+    suffice (the paper reads 0.74)."""
+    T = TS.H131
+    pts = torch.from_numpy(bowl.bowl_points(T["R"], T["l"], 4096, 0)).to("cuda")
+    say("case H131 p2 truncation")
+    (r,) = TS.study(ctx, T, configs.WATER, 100.0, TS.H131_D, pts, n_max=2, log=say)
+    assert r["size_x"] == 1.0
+    assert 0.6 < r["size_yz"] < 0.9
