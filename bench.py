@@ -160,13 +160,15 @@ def cpu_baseline(cfg, g1_p, gn_p, p1_dev, budget_s, order):
     dt = t_fixed + t_sum
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": n_t / dt, "unit": "voxels/s", "cores": cores, "kind": "oracle",
+            "circulant_fft": cpu_method_baseline(cfg, g1_p, gn_p, p1_dev, order),
             "sample": "p2 at %d random voxels of the 256^3 grid: transfer (order %d) and source term of the whole "
                       "grid (%.1f s) plus the FP64 direct midpoint sum over all 16.8M source voxels per sampled "
                       "voxel (%.1f s)" % (n_t, order, t_fixed, t_sum)}
 
 
 def cpu_method_baseline(cfg, g1_p, gn_p, p1_dev, order):
-    """The paper's method on the host CPU: p2 on its 256^3 grid through the oracle's circulant FFT.
+    """Part of the CPU-baseline leg: the paper's method on the host CPU, p2 on its 256^3 grid through
+    the oracle's circulant FFT.
 
     Transfer of p1 and the source term, the FP64 kernel embedded in a 512^3 circulant, and
     three scipy.fft transforms, complex128, with the box's share of host threads.  The same
@@ -504,11 +506,9 @@ def main():
         result["batched"] = batch_bench(P, torch, ctx, W, 5, log)
 
     if not a.no_cpu:
-        log("bench: oracle CPU baseline")
+        log("bench: oracle CPU baseline (direct sum, and the circulant FFT of p2)")
         result["cpu_baseline"] = cpu_baseline(cfg, g1, gn, p1, a.cpu_budget, a.order)
-        log("bench: the method on the CPU (circulant FFT, p2)")
-        result["cpu_method_baseline"] = cpu_method_baseline(cfg, g1, gn, p1, a.order)
-        log("bench: cpu method %s" % result["cpu_method_baseline"])
+        log("bench: cpu baseline %s" % result["cpu_baseline"])
     ctx.close()
     print(json.dumps(result), flush=True)
 
