@@ -87,6 +87,9 @@ def test_circulant_sizes():
     assert P.circulant_size(640) == 1280 and P.circulant_size(641) == 1536 and P.circulant_size(769) == 2048
     with pytest.raises(P.NvpError):
         P.circulant_size(1025)
+    for n in (0, -3):  # empty or negative axes
+        with pytest.raises(P.NvpError):
+            P.circulant_size(n)
 
 
 def test_host_calls_reject_invalid_arguments():

@@ -395,3 +395,11 @@ def test_error_codes(ctx):
     with pytest.raises(P.NvpError) as e:
         P.CascadePlan(ctx, WATER, F0, small, [g], order=3)  # source axis shorter than the cubic stencil
     assert e.value.status == 1
+    empty = oracle.Grid((0.0, 0.0, 0.0), 1e-4, (0, 4, 4))
+    for call in (lambda: P.CascadePlan(ctx, WATER, F0, g, [empty]),
+                 lambda: P.CascadePlan(ctx, WATER, F0, empty, [g]),
+                 lambda: P.volume_potential(ctx, 9000.0, empty, torch.zeros((0, 4, 4), dtype=torch.complex64,
+                                                                             device="cuda"))):
+        with pytest.raises(P.NvpError) as e:
+            call()
+        assert e.value.status == 1
