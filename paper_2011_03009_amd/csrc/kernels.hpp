@@ -563,11 +563,19 @@ __device__ __forceinline__ void zconv_block(cx<R> *__restrict__ buf, const cx<R>
     constexpr int SL = slot_len<R>(L);
     cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
     const int tid = threadIdx.x, t = tid % F::P, slot = tid / F::P, j = slot & 3;
-    const int64_t quad = block * QW + (slot >> 2);
-    const bool valid = quad < n_quads;
-    const int64_t kx = valid ? quad / Hy : 0, ky = valid ? quad % Hy : 0;
-    const int64_t px = (j & 1) ? (Mx - kx) % Mx : kx;
-    const int64_t py = (j & 2) ? (My - ky) % My : ky;
+    // The workgroup's first quad is split into (kx, ky) once, with a 32-bit
+    // division on workgroup-uniform values (the host keeps the quad count
+    // below 2^31); a slot's own quad follows with at most one carry, since
+    // QW <= 2 <= Hy.  The mirrored index M - k needs no division either:
+    // k = 0 mirrors onto itself.
+    const uint32_t hy = (uint32_t)Hy, q0 = (uint32_t)block * (uint32_t)QW, sq = (uint32_t)(slot >> 2);
+    const uint32_t kx0 = q0 / hy;
+    const bool valid = (int64_t)(q0 + sq) < n_quads;
+    uint32_t ukx = kx0, uky = q0 - kx0 * hy + sq;
+    if (uky >= hy) uky -= hy, ++ukx;
+    const int64_t kx = valid ? ukx : 0, ky = valid ? uky : 0;
+    const int64_t px = ((j & 1) && kx) ? Mx - kx : kx;
+    const int64_t py = ((j & 2) && ky) ? My - ky : ky;
     const bool act = valid && !(((j & 1) && px == kx) || ((j & 2) && py == ky));
     cx<R> *pen = buf + (px * My + py) * (int64_t)Nz;
     const cx<R> *krow = khat + (kx * Hy + ky) * octant_row(L);
@@ -641,7 +649,13 @@ k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, 
     const int tid = threadIdx.x, t = tid % F::P, c = tid / F::P;
     const int64_t row = (int64_t)blockIdx.x * PW + c;
     const bool act = row < Hx * Hy;
-    const int64_t i = act ? row / Hy : 0, jj = act ? row % Hy : 0;
+    // (i, j) of the row: the workgroup's first row is split with one 32-bit
+    // division on uniform values (the host keeps Hx Hy below 2^31), then
+    // carried forward by c
+    const uint32_t hy = (uint32_t)Hy, r0 = blockIdx.x * (uint32_t)PW, i0 = r0 / hy;
+    uint32_t ui = i0, uj = r0 - i0 * hy + (uint32_t)c;
+    while (uj >= hy) uj -= hy, ++ui;
+    const int64_t i = act ? ui : 0, jj = act ? uj : 0;
     cx<double> *my = lds + c * SL;
     cx<double> *twl = lds + PW * SL;
     stage_table<double>(twl, tw, NT);

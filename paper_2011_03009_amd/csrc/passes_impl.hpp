@@ -145,6 +145,7 @@ hipError_t zconv_qw(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz,
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
     const int64_t Hx = Mx / 2 + 1, Hy = My / 2 + 1, nq = Hx * Hy;
+    if (nq > 0x7fffffff - QW) return hipErrorInvalidValue;  // quad indices are 32-bit in the kernel
     hipLaunchKernelGGL(kern, dim3((unsigned)((nq + QW - 1) / QW)), dim3(4 * QW * plan_threads(L)), lds, s,
                        static_cast<cx<R> *>(buf), static_cast<const cx<R> *>(khat), Mx, My, Nz, Hy, nq,
                        static_cast<const cx<R> *>(tw));
@@ -176,6 +177,7 @@ hipError_t kz_impl(double2 *out, const int64_t H[3], const int64_t N[3], const d
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
     const int64_t rows = H[0] * H[1];
+    if (rows > 0x7fffffff - PW) return hipErrorInvalidValue;  // row indices are 32-bit in the kernel
     hipLaunchKernelGGL(kern, dim3((unsigned)((rows + PW - 1) / PW)), dim3(PW * plan_threads(L)), lds, s, out, H[0],
                        H[1], N[0], N[1], N[2], ktab, static_cast<const double2 *>(tw));
     return hipGetLastError();
