@@ -12,3 +12,5 @@ Parity status of each function is stated in its docstring; none is
 from .core import *  # noqa: F401,F403
 from .incident import incident_at, incident_field, radiated_power  # noqa: F401
 from .vie import dense_operator, vie_solve  # noqa: F401
+from .quadrature import (conv_circulant_corrected, conv_direct_corrected, corrected_weights,  # noqa: F401
+                         gaussian_potential, lattice_zeta, volume_potential_corrected)

@@ -332,16 +332,27 @@ def source_term(n, v):
     return f
 
 
-def harmonic(n, fields, grid, f0, medium, order, method="direct", targets=None, M=None):
+def harmonic(n, fields, grid, f0, medium, order, method="direct", targets=None, M=None, rule="ball"):
     """p_n on `grid` from lower harmonics fields = {m: (array, Grid)} for m = 1..n-1.
 
     method "direct": the definition; "fft": the circulant cross-check;
-    targets (direct only): flat indices of the voxels to evaluate.
+    targets (direct only): flat indices of the voxels to evaluate;
+    rule "ball": equation "quad" of the paper, "corrected": the corrected
+    quadrature of oracle/quadrature.py (every voxel).
     """
     v = {m: transfer(fields[m][0], fields[m][1], grid, order) for m in range(1, n)}
     f = source_term(n, v)
     k = wavenumber(n, f0, medium)
     C = cascade_constant(n, f0, medium)
+    if rule == "corrected":
+        from . import quadrature
+        if targets is not None:
+            raise ValueError("the corrected rule evaluates every voxel")
+        if method == "direct":
+            return C * quadrature.conv_direct_corrected(f, grid.h, k)
+        return C * quadrature.conv_circulant_corrected(f, grid.h, k, M=M)
+    if rule != "ball":
+        raise ValueError("rule must be 'ball' or 'corrected'")
     if method == "direct":
         return C * conv_direct(f, grid.h, k, targets=targets)
     if targets is not None:
@@ -349,12 +360,12 @@ def harmonic(n, fields, grid, f0, medium, order, method="direct", targets=None, 
     return C * conv_circulant(f, grid.h, k, M=M)
 
 
-def cascade(p1, g1, grids, f0, medium, order, method="fft"):
+def cascade(p1, g1, grids, f0, medium, order, method="fft", rule="ball"):
     """Harmonics 2..max(grids) in order; grids = {n: Grid}.  Returns {n: array}."""
     fields = {1: (np.asarray(p1, dtype=np.complex128), g1)}
     out = {}
     for n in sorted(grids):
-        p = harmonic(n, fields, grids[n], f0, medium, order, method=method)
+        p = harmonic(n, fields, grids[n], f0, medium, order, method=method, rule=rule)
         fields[n] = (p, grids[n])
         out[n] = p
     return out
