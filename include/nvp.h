@@ -84,6 +84,30 @@ nvp_status nvp_ctx_destroy(nvp_ctx *ctx);
 /* Waits for the context's stream; reports asynchronous HIP errors. */
 nvp_status nvp_ctx_sync(nvp_ctx *ctx);
 
+/* ---- quadrature rule ------------------------------------------------------ */
+
+/* The rule by which the volume potential is discretised (Section 3.1).
+ * NVP_QUAD_BALL, the default, is the paper's equation "quad": the midpoint
+ * rule on every other voxel, the integral over the equal-volume ball on the
+ * target's own.  NVP_QUAD_CORRECTED is the higher-order rule that the paper
+ * leaves open there: the midpoint sum over the other voxels with the error of
+ * G's singularity removed by weights on the target voxel and its six face
+ * neighbours (a corrected trapezoidal rule for singular integrands, with the
+ * Epstein zeta values of the cubic lattice Z(1/2), Z(-1/2)):
+ *   K(0)        = h^2 (Z(-1/2) - Z(1/2)) / (4 pi) + i k h^3 / (4 pi) + k^2 h^4 Z(-1/2) / (8 pi),
+ *   K(face) adds  -h^2 Z(-1/2) / (24 pi)  to the midpoint value h^3 G(h).
+ * It costs nothing extra: the operator stays a convolution. */
+#define NVP_QUAD_BALL 0
+#define NVP_QUAD_CORRECTED 1
+/* Rule of every volume potential, box potential, VIE solve and plan made
+ * with this context from now on (a plan keeps the rule it was made with).
+ * NVP_E_INVALID for another value. */
+nvp_status nvp_ctx_set_quadrature(nvp_ctx *ctx, int rule);
+/* Host only: w[0] + i w[1] = the self-voxel value K(0) of `rule`, w[2] + i
+ * w[3] = what the rule adds at the six face neighbours (0 for the ball rule).
+ * NVP_E_INVALID for a bad rule, k = 0, non-finite k or h <= 0. */
+nvp_status nvp_quadrature_weights(int rule, double k_re, double k_im, double h, double w[4]);
+
 /* ---- constants and grids (host only) ------------------------------------ */
 
 /* k_n = 2 pi n f0 / c0 + i alpha(n f0)  (Section 2, eq. power_law with n w). */
@@ -162,9 +186,10 @@ nvp_status nvp_radiated_power(nvp_ctx *ctx, double k_re, double k_im, double s_r
 /* ---- the raw operator ---------------------------------------------------- */
 
 /* u = -sum_j K(x_i - x_j) f_j on grid g (eqs. vol_pot_approx and quad), any
- * complex wavenumber k with Im k >= 0.  f_dev and u_dev are device buffers
- * of g->n[0]*g->n[1]*g->n[2] complex elements (may not alias).  The context
- * keeps the kernel spectrum of the last (k, g, prec) for reuse. */
+ * complex wavenumber k with Im k >= 0, K of the context's quadrature rule.
+ * f_dev and u_dev are device buffers of g->n[0]*g->n[1]*g->n[2] complex
+ * elements (may not alias).  The context keeps the kernel spectrum of the
+ * last (rule, k, g, prec) for reuse. */
 nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nvp_grid *g,
                                 const void *f_dev, void *u_dev, nvp_prec prec);
 
@@ -195,7 +220,8 @@ nvp_status nvp_vie_solve(nvp_ctx *ctx, double kb_re, double kb_im, const nvp_gri
  * paper recommends); target centres are clamped into the source grid's hull,
  * and a field on the very grid it is needed on is used as is.  Every axis
  * of a source grid needs at least transfer_order + 1 voxels, and every axis
- * a circulant length (nvp_circulant_size; up to 1024 voxels in this build). */
+ * a circulant length (nvp_circulant_size; up to 1024 voxels in this build).
+ * The plan discretises with the context's quadrature rule at creation. */
 nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int n_harm,
                             const nvp_grid *g1, const nvp_grid *gn, nvp_prec prec,
                             int transfer_order, nvp_plan **out);
@@ -260,8 +286,8 @@ nvp_status nvp_qbox(nvp_ctx *ctx, const int64_t n[3], const void *f_dev, nvp_pre
 /* Truncated potentials at one voxel (the sums of eq. quad restricted to
  * boxes, for the truncation-convergence sweeps of Section 5): out[2i] + i
  * out[2i+1] = -sum over voxels j inside box i of K(x_t - x_j) f_j, with the
- * kernel of Section 3.1 for wavenumber k and the self voxel from its ball
- * integral, FP64 kernel and accumulation.  t: target voxel index on g; box:
+ * kernel of Section 3.1 for wavenumber k under the context's quadrature
+ * rule, FP64 kernel and accumulation.  t: target voxel index on g; box:
  * host, count * 6 int64 as in nvp_qbox, each non-empty box inside the grid
  * (a box with hi < lo on an axis is empty and sums to 0); out: host, 2 count
  * doubles.  count <= 32.  Waits for the result. */

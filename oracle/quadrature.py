@@ -120,10 +120,12 @@ def _local_correction(f, h, k):
     return out + w_face * nb
 
 
-def conv_direct_corrected(f, h, k):
-    """out_i = sum_j K_c(x_i - x_j) f_j with the corrected kernel, every voxel: the paper's
-    direct sum plus the local correction."""
-    return conv_direct(f, h, k) + _local_correction(f, h, k)
+def conv_direct_corrected(f, h, k, targets=None):
+    """out_i = sum_j K_c(x_i - x_j) f_j with the corrected kernel: the paper's direct sum plus
+    the local correction.  targets: flat C-order indices, or None for every voxel."""
+    if targets is None:
+        return conv_direct(f, h, k) + _local_correction(f, h, k)
+    return conv_direct(f, h, k, targets=targets) + _local_correction(f, h, k).ravel()[np.asarray(targets)]
 
 
 def conv_circulant_corrected(f, h, k, M=None):

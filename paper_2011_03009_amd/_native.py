@@ -36,6 +36,8 @@ SIGNATURES = {
     "nvp_ctx_create": (_st, [_i, _vp, ctypes.POINTER(_vp)]),
     "nvp_ctx_destroy": (_st, [_vp]),
     "nvp_ctx_sync": (_st, [_vp]),
+    "nvp_ctx_set_quadrature": (_st, [_vp, _i]),
+    "nvp_quadrature_weights": (_st, [_i, _d, _d, _d, _dp]),
     "nvp_wavenumber": (_st, [ctypes.POINTER(Medium), _d, _i, _dp, _dp]),
     "nvp_cascade_constant": (_st, [ctypes.POINTER(Medium), _d, _i, _dp]),
     "nvp_spacing": (_st, [ctypes.POINTER(Medium), _d, _i, _i, _dp]),

@@ -9,9 +9,10 @@ namespace nvp {
 // The kernel of equation "quad" depends on a voxel offset d only through the
 // integer |d|^2: ktab[q] = h^3 G_k(sqrt(q) h) for q >= 1, and the self value
 // for q = 0, in FP64.  The octant rows below read it, so each distinct
-// distance is evaluated once instead of once per offset.
+// distance is evaluated once instead of once per offset.  `face` is added at
+// q = 1, the six face neighbours (the corrected quadrature's face weight).
 __global__ void __launch_bounds__(256) k_kradial(double2 *__restrict__ ktab, int64_t n, double h, double kr, double ki,
-                                                 double2 self) {
+                                                 double2 self, double2 face) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     if (q == 0) {
@@ -22,13 +23,13 @@ __global__ void __launch_bounds__(256) k_kradial(double2 *__restrict__ ktab, int
     const double mag = h * h * h * exp(-ki * d) / (4.0 * M_PI * d);
     double sn, cs;
     sincos(kr * d, &sn, &cs);
-    ktab[q] = make_double2(mag * cs, mag * sn);
+    ktab[q] = q == 1 ? make_double2(mag * cs + face.x, mag * sn + face.y) : make_double2(mag * cs, mag * sn);
 }
 
 hipError_t launch_kradial(double2 *ktab, int64_t n, double h, double kr, double ki, double self_re, double self_im,
-                          hipStream_t s) {
+                          double face_re, double face_im, hipStream_t s) {
     hipLaunchKernelGGL(k_kradial, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ktab, n, h, kr, ki,
-                       make_double2(self_re, self_im));
+                       make_double2(self_re, self_im), make_double2(face_re, face_im));
     return hipGetLastError();
 }
 

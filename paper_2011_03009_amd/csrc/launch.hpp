@@ -119,9 +119,10 @@ hipError_t launch_zconv_multi_c128(int L, const ZconvTaskArgs *tasks_dev, int nt
 int strided_tile_cols(int L, int dbl);
 int zconv_quads_per_block(int L, int dbl);
 
-// The kernel by squared integer distance: ktab[q], q < n (see k_kradial).
+// The kernel by squared integer distance: ktab[q], q < n (see k_kradial);
+// (face_re, face_im) is added to the entry q = 1 (zero for the paper's rule).
 hipError_t launch_kradial(double2 *ktab, int64_t n, double h, double kr, double ki, double self_re, double self_im,
-                          hipStream_t s);
+                          double face_re, double face_im, hipStream_t s);
 // Kernel tabulation (gathered from ktab) fused with the first (z) FP64 pass of
 // the kernel spectrum; writes the octant [Hx][Hy][Hz] (rows octant_row(L)
 // apart) at `out`.

@@ -19,7 +19,8 @@ int ctx_device(const nvp_ctx *c);
 hipStream_t ctx_stream(const nvp_ctx *c);
 nvp_status ctx_fail(nvp_ctx *c, nvp_status s, const char *msg);
 nvp_status ctx_hip_fail(nvp_ctx *c, const char *what, hipError_t e);
-void ctx_self_cell(double kr, double ki, double h, double *re, double *im);
+void ctx_quad_weights(const nvp_ctx *c, double kr, double ki, double h, double *sr, double *si, double *fr,
+                      double *fi);
 }  // namespace nvp
 
 using nvp::ctx_fail;
@@ -107,8 +108,8 @@ nvp_status nvp_box_potential(nvp_ctx *ctx, double k_re, double k_im, const nvp_g
             hb[q * 6 + a] = hi >= lo ? (int)lo : 0;
             hb[q * 6 + 3 + a] = hi >= lo ? (int)hi : -1;
         }
-    double sr, si;
-    nvp::ctx_self_cell(k_re, k_im, g->h, &sr, &si);
+    double sr, si, fr, fi;  // self voxel and face-neighbour addition of the context's quadrature rule
+    nvp::ctx_quad_weights(ctx, k_re, k_im, g->h, &sr, &si, &fr, &fi);
     LRN_HIP(ctx, hipSetDevice(nvp::ctx_device(ctx)));
     hipStream_t s = nvp::ctx_stream(ctx);
     DevBuf buf;
@@ -118,8 +119,8 @@ nvp_status nvp_box_potential(nvp_ctx *ctx, double k_re, double k_im, const nvp_g
     double2 *out_dev = reinterpret_cast<double2 *>(static_cast<char *>(buf.p) + wbytes);
     int *box_dev = reinterpret_cast<int *>(static_cast<char *>(buf.p) + wbytes + obytes);
     LRN_HIP(ctx, hipMemcpyAsync(box_dev, hb, count * 6 * sizeof(int), hipMemcpyHostToDevice, s));
-    LRN_HIP(ctx, nvp::boxsum_launch(f_dev, prec == NVP_C128, g->n, ti, g->h, k_re, k_im, sr, si, box_dev, count, work,
-                                    out_dev, s));
+    LRN_HIP(ctx, nvp::boxsum_launch(f_dev, prec == NVP_C128, g->n, ti, g->h, k_re, k_im, sr, si, fr, fi, box_dev,
+                                    count, work, out_dev, s));
     LRN_HIP(ctx, hipMemcpyAsync(out, out_dev, obytes, hipMemcpyDeviceToHost, s));
     LRN_HIP(ctx, hipStreamSynchronize(s));
     return NVP_OK;

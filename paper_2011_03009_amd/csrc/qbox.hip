@@ -100,7 +100,8 @@ namespace {
 template <typename T>
 __global__ void __launch_bounds__(256) k_boxsum(const T *__restrict__ f, int n1, int n2, int t0, int t1, int t2,
                                                 double h, double kr, double ki, double s_re, double s_im,
-                                                const int *__restrict__ box, double2 *__restrict__ part) {
+                                                double f_re, double f_im, const int *__restrict__ box,
+                                                double2 *__restrict__ part) {
     __shared__ double2 red[256];
     const int q = blockIdx.y;
     const int lx = box[q * 6 + 0], ly = box[q * 6 + 1], lz = box[q * 6 + 2];
@@ -123,6 +124,10 @@ __global__ void __launch_bounds__(256) k_boxsum(const T *__restrict__ f, int n1,
             sincos(kr * r, &sn, &cs);
             kre = mag * cs;
             kim = mag * sn;
+            if (abs(x - t0) + abs(y - t1) + abs(z - t2) == 1) {
+                kre += f_re;
+                kim += f_im;
+            }
         }
         const T v = f[((int64_t)x * n1 + y) * n2 + z];
         const double vr = (double)v.x, vi = (double)v.y;
@@ -156,15 +161,15 @@ __global__ void k_boxsum_final(const double2 *__restrict__ part, int blocks, int
 }  // namespace
 
 hipError_t boxsum_launch(const void *f, bool dbl, const int64_t n[3], const int t[3], double h, double kr, double ki,
-                         double s_re, double s_im, const int *box_dev, int count, double2 *work, double2 *out_dev,
-                         hipStream_t s) {
+                         double s_re, double s_im, double f_re, double f_im, const int *box_dev, int count,
+                         double2 *work, double2 *out_dev, hipStream_t s) {
     const int blocks = NVP_BOXSUM_BLOCKS;
     if (dbl)
         hipLaunchKernelGGL(k_boxsum<double2>, dim3(blocks, count), dim3(256), 0, s, (const double2 *)f, (int)n[1],
-                           (int)n[2], t[0], t[1], t[2], h, kr, ki, s_re, s_im, box_dev, work);
+                           (int)n[2], t[0], t[1], t[2], h, kr, ki, s_re, s_im, f_re, f_im, box_dev, work);
     else
         hipLaunchKernelGGL(k_boxsum<float2>, dim3(blocks, count), dim3(256), 0, s, (const float2 *)f, (int)n[1],
-                           (int)n[2], t[0], t[1], t[2], h, kr, ki, s_re, s_im, box_dev, work);
+                           (int)n[2], t[0], t[1], t[2], h, kr, ki, s_re, s_im, f_re, f_im, box_dev, work);
     hipLaunchKernelGGL(k_boxsum_final, dim3(1), dim3(64), 0, s, work, blocks, count, out_dev);
     return hipGetLastError();
 }

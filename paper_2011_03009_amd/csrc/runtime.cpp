@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -37,6 +38,7 @@ struct Twiddle {
 
 struct VpCache {
     bool valid = false;
+    int quad = -1;
     double kr = 0, ki = 0;
     nvp_grid g{};
     int prec = -1;
@@ -53,6 +55,7 @@ struct nvp_ctx {
     std::vector<Twiddle> tw;
     VpCache vp;
     size_t max_lds = 0;
+    int quad = NVP_QUAD_BALL;  // quadrature rule of plans and potentials created from now on
 };
 
 namespace {
@@ -91,6 +94,7 @@ struct TimedEvent {
 
 struct nvp_plan {
     nvp_ctx *ctx = nullptr;
+    int quad = NVP_QUAD_BALL;  // the context's rule when the plan was made
     nvp_prec prec = NVP_C64;
     int order = 1;
     nvp_medium med{};
@@ -249,6 +253,37 @@ void self_cell(double kr, double ki, double h, double *re, double *im) {
     *im = (ni * k2r - nr * k2i) / den;
 }
 
+// Epstein zeta function of the cubic lattice, Z(s) = sum over n in Z^3 \ {0}
+// of |n|^{-2s} (continued analytically), at s = 1/2 and s = -1/2.
+constexpr double kZetaHalf = -2.8372974794806196;
+constexpr double kZetaMinusHalf = -0.26659627871839353;
+
+// Self-voxel kernel value and the addition at the six face neighbours of
+// quadrature rule `rule`: the paper's equal-volume ball (equation "quad",
+// nothing added at the faces), or the corrected lattice rule.  The corrected
+// rule keeps the midpoint sum over the other voxels and removes the error of
+// G's singular Taylor terms 1/(4 pi r) and -k^2 r/(8 pi) (and restores the
+// constant term ik/(4 pi) at the target) by the lattice-zeta weights
+//   self = h^2 (Z(-1/2) - Z(1/2)) / (4 pi) + i k h^3 / (4 pi) + k^2 h^4 Z(-1/2) / (8 pi),
+//   face = -h^2 Z(-1/2) / (24 pi)
+// (a corrected trapezoidal rule for singular integrands; the face weight is
+// the 7-point Laplacian of the h^4 term).
+void quad_weights(int rule, double kr, double ki, double h, double *sr, double *si, double *fr, double *fi) {
+    if (rule != NVP_QUAD_CORRECTED) {
+        self_cell(kr, ki, h, sr, si);
+        *fr = *fi = 0.0;
+        return;
+    }
+    const std::complex<double> k(kr, ki), I(0.0, 1.0);
+    const double h2 = h * h, c4 = 4.0 * kPi;
+    const std::complex<double> w = h2 * (kZetaMinusHalf - kZetaHalf) / c4 + I * k * (h2 * h) / c4 +
+                                   k * k * (h2 * h2) * kZetaMinusHalf / (2.0 * c4);
+    *sr = w.real();
+    *si = w.imag();
+    *fr = -h2 * kZetaMinusHalf / (6.0 * c4);
+    *fi = 0.0;
+}
+
 nvp_status check_grid_lengths(nvp_ctx *ctx, const nvp_grid *g, int64_t M[3]) {
     for (int a = 0; a < 3; ++a) {
         M[a] = circulant_len(g->n[a]);
@@ -300,19 +335,19 @@ int64_t radial_entries(const nvp_grid *g) {
 // [Mx/2+1][My/2+1][Mz/2+1] (rows padded to octant_row(Mz)) in the plan
 // precision at `khat`.  `scratch` holds the FP64 octant during the three
 // passes, `ktab` the kernel by squared distance (radial_entries(g) FP64 values).
-nvp_status kernel_spectrum(nvp_ctx *ctx, nvp_plan *timed, double kr, double ki, const nvp_grid *g,
+nvp_status kernel_spectrum(nvp_ctx *ctx, nvp_plan *timed, int quad, double kr, double ki, const nvp_grid *g,
                            const int64_t M[3], nvp_prec prec, void *khat, void *scratch, void *ktab) {
     const int64_t H[3] = {M[0] / 2 + 1, M[1] / 2 + 1, M[2] / 2 + 1};
-    double sr, si;  // self voxel
-    self_cell(kr, ki, g->h, &sr, &si);
+    double sr, si, fr, fi;  // self voxel, face-neighbour addition
+    quad_weights(quad, kr, ki, g->h, &sr, &si, &fr, &fi);
     const void *tw;
     nvp_status st;
     // z: tabulation fused with the FFT of the even extension of each octant row
     if ((st = twiddles(ctx, (int)M[2], true, &tw))) return st;
     {
         Timer t(timed, NVP_T_KTAB);
-        NVP_HIP(ctx, nvp::launch_kradial(static_cast<double2 *>(ktab), radial_entries(g), g->h, kr, ki, sr, si,
-                                         ctx->stream));
+        NVP_HIP(ctx, nvp::launch_kradial(static_cast<double2 *>(ktab), radial_entries(g), g->h, kr, ki, sr, si, fr,
+                                         fi, ctx->stream));
         NVP_HIP(ctx, nvp::launch_kz((int)M[2], static_cast<double2 *>(scratch), H, g->n,
                                     static_cast<const double2 *>(ktab), tw, ctx->stream));
     }
@@ -560,7 +595,10 @@ int ctx_device(const nvp_ctx *c) { return c->device; }
 hipStream_t ctx_stream(const nvp_ctx *c) { return c->stream; }
 nvp_status ctx_fail(nvp_ctx *c, nvp_status s, const char *msg) { return fail(c, s, msg); }
 nvp_status ctx_hip_fail(nvp_ctx *c, const char *what, hipError_t e) { return hip_fail(c, what, e); }
-void ctx_self_cell(double kr, double ki, double h, double *re, double *im) { self_cell(kr, ki, h, re, im); }
+void ctx_quad_weights(const nvp_ctx *c, double kr, double ki, double h, double *sr, double *si, double *fr,
+                      double *fi) {
+    quad_weights(c->quad, kr, ki, h, sr, si, fr, fi);
+}
 
 }  // namespace nvp
 
@@ -598,6 +636,22 @@ nvp_status nvp_ctx_create(int device, void *hip_stream, nvp_ctx **out) {
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->max_lds = prop.sharedMemPerBlock;
     *out = c;
+    return NVP_OK;
+}
+
+nvp_status nvp_ctx_set_quadrature(nvp_ctx *ctx, int rule) {
+    if (!ctx) return NVP_E_INVALID;
+    if (rule != NVP_QUAD_BALL && rule != NVP_QUAD_CORRECTED)
+        return fail(ctx, NVP_E_INVALID, "nvp_ctx_set_quadrature: unknown rule");
+    ctx->quad = rule;
+    return NVP_OK;
+}
+
+nvp_status nvp_quadrature_weights(int rule, double k_re, double k_im, double h, double w[4]) {
+    if (!w || (rule != NVP_QUAD_BALL && rule != NVP_QUAD_CORRECTED) || !std::isfinite(k_re) ||
+        !std::isfinite(k_im) || (k_re == 0 && k_im == 0) || !finite_pos(h))
+        return NVP_E_INVALID;
+    quad_weights(rule, k_re, k_im, h, &w[0], &w[1], &w[2], &w[3]);
     return NVP_OK;
 }
 
@@ -712,7 +766,8 @@ nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nv
     nvp_status st = check_grid_lengths(ctx, g, M);
     if (st) return st;
     VpCache &c = ctx->vp;
-    const bool hit = c.valid && c.kr == k_re && c.ki == k_im && c.prec == (int)prec && same_grid(c.g, *g);
+    const bool hit = c.valid && c.quad == ctx->quad && c.kr == k_re && c.ki == k_im && c.prec == (int)prec &&
+                     same_grid(c.g, *g);
     if (!hit) {
         NVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
         if (c.khat) (void)hipFree(c.khat);
@@ -729,8 +784,9 @@ nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nv
             c = VpCache{};
             return fail(ctx, NVP_E_NOMEM, "nvp_volume_potential: device allocation failed");
         }
-        if ((st = kernel_spectrum(ctx, nullptr, k_re, k_im, g, M, prec, c.khat, c.B, c.A))) return st;
+        if ((st = kernel_spectrum(ctx, nullptr, ctx->quad, k_re, k_im, g, M, prec, c.khat, c.B, c.A))) return st;
         c.valid = true;
+        c.quad = ctx->quad;
         c.kr = k_re;
         c.ki = k_im;
         c.g = *g;
@@ -759,6 +815,7 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
     nvp_plan *p = new (std::nothrow) nvp_plan;
     if (!p) return fail(ctx, NVP_E_NOMEM, "plan allocation");
     p->ctx = ctx;
+    p->quad = ctx->quad;
     p->prec = prec;
     p->order = transfer_order;
     p->med = *med;
@@ -976,7 +1033,9 @@ nvp_status run_harmonic(nvp_plan *plan, int n, const void *const *fields, void *
     Harm &h = plan->h[n - 2];
     nvp_status st;
     if (!kready && (!h.khat_ok || !plan->cache)) {
-        if ((st = kernel_spectrum(ctx, plan, h.kr, h.ki, &h.g, h.M, plan->prec, h.khat, plan->B, plan->A))) return st;
+        if ((st = kernel_spectrum(ctx, plan, plan->quad, h.kr, h.ki, &h.g, h.M, plan->prec, h.khat, plan->B,
+                                  plan->A)))
+            return st;
         h.khat_ok = true;
     }
     SourceArgs src = source_args(plan, n, fields);
@@ -1061,7 +1120,8 @@ nvp_status nvp_execute_cascade(nvp_plan *plan, const void *p1_dev, void *const *
             const hipStream_t user = ctx->stream;
             ctx->stream = plan->side;
             nvp_status st =
-                kernel_spectrum(ctx, nullptr, h.kr, h.ki, &h.g, h.M, plan->prec, h.khat, plan->kscr, plan->ktab);
+                kernel_spectrum(ctx, nullptr, plan->quad, h.kr, h.ki, &h.g, h.M, plan->prec, h.khat, plan->kscr,
+                                plan->ktab);
             ctx->stream = user;
             if (st) return st;
             NVP_HIP(ctx, hipEventRecord(plan->ev_k[n - 2], plan->side));

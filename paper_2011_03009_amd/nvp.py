@@ -14,6 +14,7 @@ from . import _native
 from ._native import Grid, Medium, Problem
 
 NVP_C64, NVP_C128 = 0, 1
+NVP_QUAD_BALL, NVP_QUAD_CORRECTED = 0, 1
 TIMING_KINDS = ("ktab", "kfft", "xfwd", "yfwd", "zconv", "yinv", "xinv", "src")
 _DT = {NVP_C64: torch.complex64, NVP_C128: torch.complex128}
 
@@ -237,6 +238,20 @@ def vie_solve(ctx, kb, g, q, rhs, p=None, tol=1e-10, max_iter=500):
                                        prec_of(q.dtype), float(tol), int(max_iter), ctypes.byref(it),
                                        ctypes.byref(rr)), ctx.handle)
     return p, it.value, rr.value
+
+
+def set_quadrature(ctx, rule):
+    """Quadrature rule of the context's later potentials, solves and plans (NVP_QUAD_BALL: the
+    paper's; NVP_QUAD_CORRECTED: the corrected lattice rule)."""
+    _check(_native.lib().nvp_ctx_set_quadrature(ctx.handle, int(rule)), ctx.handle)
+
+
+def quadrature_weights(rule, k, h):
+    """(K(0), face addition) of a quadrature rule, complex."""
+    w = (ctypes.c_double * 4)()
+    k = complex(k)
+    _check(_native.lib().nvp_quadrature_weights(int(rule), k.real, k.imag, float(h), w))
+    return complex(w[0], w[1]), complex(w[2], w[3])
 
 
 def volume_potential(ctx, k, g, f, out=None):

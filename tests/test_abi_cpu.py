@@ -123,3 +123,18 @@ def test_h101_nested_grids_match_the_paper():
         assert abs(c / printed - 1.0) < 0.005
     g, _ = P.grid_from_box((l, 0.0, 0.0), *P.rule_of_thumb_box(2, l, R, d), P.spacing(W, f0, 5))
     assert abs(int(g.n[0]) * int(g.n[1]) * int(g.n[2]) / 2.9e9 - 1.0) < 0.01
+
+
+def test_quadrature_weights_equal_oracle():
+    """The library's self and face weights of both rules against the oracle's (whose lattice
+    zeta values come from its own Ewald sums)."""
+    for k, h in ((1.05 + 0.01j, 1.0), (4651.7 + 2.9j, 2.25e-4), (0.2 + 0.0j, 3.0)):
+        s, f = P.quadrature_weights(P.NVP_QUAD_BALL, k, h)
+        assert s == pytest.approx(oracle.self_cell(k, h), rel=1e-13) and f == 0
+        s, f = P.quadrature_weights(P.NVP_QUAD_CORRECTED, k, h)
+        ws, wf = oracle.corrected_weights(k, h)
+        assert s == pytest.approx(ws, rel=1e-13)
+        assert f == pytest.approx(wf, rel=1e-13)
+    for bad in ((2, 1.0, 1.0), (-1, 1.0, 1.0), (1, 0.0, 1.0), (1, 1.0, 0.0), (0, float("nan"), 1.0)):
+        with pytest.raises(P.NvpError):
+            P.quadrature_weights(bad[0], bad[1], bad[2])
