@@ -94,3 +94,23 @@ def test_degenerate_cases_and_errors(ctx):
     with pytest.raises(P.NvpError) as e:
         P.vie_solve(ctx, KB, g, q, dev(rhs, P.NVP_C128), p=q)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("prec", [P.NVP_C128, P.NVP_C64])
+@pytest.mark.parametrize("n", [(6, 5, 7), (9, 1, 4)])
+def test_corrected_quadrature_against_dense_solve(ctx, n, prec):
+    """The solver under the context's corrected quadrature against the dense solve with the
+    corrected kernel."""
+    q = contrast(n, 11)
+    rhs = fields.random_field(n, 12)
+    ref = oracle.vie_solve(q, rhs, H, KB, rule="corrected")
+    say("case vie corrected quadrature n=%s prec=%d" % (n, prec))
+    tol = 1e-13 if prec == P.NVP_C128 else 1e-6
+    P.set_quadrature(ctx, P.NVP_QUAD_CORRECTED)
+    try:
+        p, it, rr = P.vie_solve(ctx, KB, oracle.Grid((0.0, 0.0, 0.0), H, n), dev(q, prec), dev(rhs, prec), tol=tol)
+        torch.cuda.synchronize()
+    finally:
+        P.set_quadrature(ctx, P.NVP_QUAD_BALL)
+    assert rr < (1e-12 if prec == P.NVP_C128 else 1e-5), (it, rr)
+    assert oracle.rel_l2(p.to(torch.complex128).cpu().numpy(), ref) < (1e-10 if prec == P.NVP_C128 else 1e-5), it

@@ -92,3 +92,12 @@ def test_corrected_rule_at_lambda_over_6_and_its_order():
     assert c1 < 5e-4
     assert 3.0 < b1 / b2 < 6.0
     assert c1 / c2 > 32.0
+
+
+def test_corrected_dense_operator_equals_the_corrected_sum():
+    rng = np.random.default_rng(8)
+    for n in ((4, 3, 5), (6, 1, 2)):
+        f = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        h, k = 0.9, 1.1 + 0.05j
+        A = oracle.dense_operator(k, h, n, rule="corrected")
+        assert oracle.rel_l2((A @ f.ravel()).reshape(n), oracle.conv_direct_corrected(f, h, k)) < 1e-14
