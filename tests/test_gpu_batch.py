@@ -202,3 +202,30 @@ def test_batch_errors(ctx):
     with pytest.raises(P.NvpError):
         b.set_graph(True, 17)
     b.close()
+
+
+def test_batch_under_the_corrected_quadrature_matches_the_oracle():
+    """A batch made while the context selects the corrected quadrature: graph replays against
+    the oracle's cascades under that rule."""
+    c = P.Context(0)
+    try:
+        P.set_quadrature(c, P.NVP_QUAD_CORRECTED)
+        probs = problems(3, 5)
+        p1s = inputs(probs, P.NVP_C128, 40)
+        say("case batch corrected quadrature")
+        b = P.Batch(c, probs, prec=P.NVP_C128, order=3)
+        b.set_graph(True, 2)
+        outs = b.outputs()
+        for r in range(2):
+            b.execute(p1s, outs)
+            torch.cuda.synchronize()
+            for i, pr in enumerate(probs):
+                gn = {n: g for n, g in zip(range(2, len(pr["grids"]) + 2), pr["grids"])}
+                ref = oracle.cascade(p1s[i].cpu().numpy(), pr["g1"], gn, pr["f0"], pr["med"], 3, method="fft",
+                                     rule="corrected")
+                for n, t in zip(sorted(gn), outs[i]):
+                    assert oracle.rel_l2(t.cpu().numpy(), ref[n]) < 1e-12, (r, i, n)
+        b.close()
+    finally:
+        c.sync()
+        c.close()
