@@ -14,3 +14,4 @@ from .incident import incident_at, incident_field, radiated_power  # noqa: F401
 from .vie import dense_operator, vie_solve  # noqa: F401
 from .quadrature import (conv_circulant_corrected, conv_direct_corrected, corrected_weights,  # noqa: F401
                          gaussian_potential, lattice_zeta, volume_potential_corrected)
+from . import full_cascade  # noqa: F401
