@@ -212,6 +212,22 @@ nvp_status nvp_vie_solve(nvp_ctx *ctx, double kb_re, double kb_im, const nvp_gri
                          const void *rhs_dev, void *p_dev, nvp_prec prec, double tol, int max_iter, int *iters,
                          double *relres);
 
+/* Difference-frequency term of the full harmonic cascade (Section 2, the
+ * products 2 p_m conj(p_{m-n}), m > n, of equation cascade_1 that equation
+ * cascade_2 drops): out += scale * T_a(a) * conj(T_b(b)) at the centres of
+ * grid gt.  T_x interpolates field x from its grid g_x with the cascade's
+ * transfer of order `order` (1 or 3; see nvp_transfer_axis); zero_x != 0
+ * makes it zero at targets outside the hull of g_x's voxel centres (more than
+ * 1e-9 source voxels beyond it on some axis), as for a higher harmonic that
+ * vanishes outside its own box; a field on gt itself is used as is.  Sums in
+ * FP64.  out_dev, a_dev, b_dev: device, complex in prec, C order of their own
+ * grids; out may not alias a or b.  Waits for the result (the stencil tables
+ * it allocates are freed on return).  NVP_E_INVALID for bad arguments or a
+ * source axis shorter than order + 1. */
+nvp_status nvp_difference_term(nvp_ctx *ctx, const nvp_grid *gt, void *out_dev, const nvp_grid *ga,
+                               const void *a_dev, int zero_a, const nvp_grid *gb, const void *b_dev, int zero_b,
+                               int order, double scale, nvp_prec prec);
+
 /* ---- the nested-mesh cascade (Section 6) ----------------------------------- */
 
 /* Plan harmonics 2..n_harm.  g1: grid of the incident field p_1 (Section 3.2);

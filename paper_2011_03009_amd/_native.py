@@ -38,6 +38,8 @@ SIGNATURES = {
     "nvp_ctx_sync": (_st, [_vp]),
     "nvp_ctx_set_quadrature": (_st, [_vp, _i]),
     "nvp_quadrature_weights": (_st, [_i, _d, _d, _d, _dp]),
+    "nvp_difference_term": (_st, [_vp, ctypes.POINTER(Grid), _vp, ctypes.POINTER(Grid), _vp, _i,
+                                  ctypes.POINTER(Grid), _vp, _i, _i, _d, _i]),
     "nvp_wavenumber": (_st, [ctypes.POINTER(Medium), _d, _i, _dp, _dp]),
     "nvp_cascade_constant": (_st, [ctypes.POINTER(Medium), _d, _i, _dp]),
     "nvp_spacing": (_st, [ctypes.POINTER(Medium), _d, _i, _i, _dp]),

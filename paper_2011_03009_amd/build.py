@@ -59,7 +59,7 @@ def jobs_list():
                      [os.path.join(CSRC, "inst.hip")] + hdr))
     for name, extra in (("kspec.hip", []), ("dispatch.cpp", []), ("runtime.cpp", ["-ffp-contract=off"]),
                         ("qbox.hip", []), ("boxnet.hip", []), ("learn.cpp", []),
-                        ("incident.hip", []), ("vie.hip", [])):
+                        ("incident.hip", []), ("vie.hip", []), ("difference.hip", ["-ffp-contract=off"])):
         obj = os.path.join(OBJ, os.path.splitext(name)[0] + ".o")
         jobs.append((obj, [HIPCC] + COMMON + extra + ["-c", os.path.join(CSRC, name), "-o", obj],
                      [os.path.join(CSRC, name)] + hdr))

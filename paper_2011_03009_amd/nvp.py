@@ -254,6 +254,18 @@ def quadrature_weights(rule, k, h):
     return complex(w[0], w[1]), complex(w[2], w[3])
 
 
+def difference_term(ctx, gt, out, ga, a, zero_a, gb, b, zero_b, order, scale):
+    """out += scale * T(a) * conj(T(b)) on grid gt (in place; out, a, b of one complex dtype)."""
+    gt, ga, gb = grid(gt), grid(ga), grid(gb)
+    prec = prec_of(out.dtype)
+    for t, g, what in ((out, gt, "out"), (a, ga, "a"), (b, gb, "b")):
+        _need(t, out.dtype, int(g.n[0] * g.n[1] * g.n[2]), what)
+    _check(_native.lib().nvp_difference_term(ctx.handle, ctypes.byref(gt), _ptr(out), ctypes.byref(ga), _ptr(a),
+                                             int(bool(zero_a)), ctypes.byref(gb), _ptr(b), int(bool(zero_b)),
+                                             int(order), float(scale), prec), ctx.handle)
+    return out
+
+
 def volume_potential(ctx, k, g, f, out=None):
     """u = -sum_j K(x_i - x_j) f_j on grid g (complex64 or complex128 f of shape g.n)."""
     g = grid(g)
