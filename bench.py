@@ -246,8 +246,9 @@ def incident_bench(P, torch, ctx, cfg, g1, p1_ref, stream, reps):
 
 def paper_workload_bench(P, torch, ctx, stream, reps, log):
     """The paper's own workload (its timing table): the H101 bowl (1.1 MHz, l 63.2 mm, R 32 mm)
-    in water at 100 W radiated power, 4096 points, harmonics 2..5 at lambda_n / 6 on the
-    rule-of-thumb nested boxes (post-focal d = 10.5 mm), linear transfer, complex64.
+    in water at 100 W radiated power, about 4096 points in Deserno's regular placement (as the
+    paper), harmonics 2..5 at lambda_n / 6 on the rule-of-thumb nested boxes (post-focal
+    d = 10.5 mm), linear transfer, complex64.
 
     p_1 is the GPU monopole sum on the reference window at lambda_1 / 6, scaled to 100 W by the
     disc-power integral; the cascade then recomputes its kernel spectra on every run.
@@ -261,7 +262,8 @@ def paper_workload_bench(P, torch, ctx, stream, reps, log):
     g1, _ = P.grid_from_box(focus, *P.rule_of_thumb_box(2, l, R, d), P.spacing(W, f0, 1))
     gn = [P.grid_from_box(focus, *P.rule_of_thumb_box(n, l, R, d), P.spacing(W, f0, n))[0] for n in range(2, 6)]
     k1 = P.wavenumber(W, f0, 1)
-    pts = torch.from_numpy(bowl.bowl_points(R, l, n_p, 0)).to(dev)
+    pts = torch.from_numpy(bowl.bowl_points_deserno(R, l, n_p)).to(dev)
+    n_p = int(pts.shape[0])
     s_raw = bowl.cap_area(R, l) / n_p  # the unnormalised field (A / n_p) sum_j G_k
     centre = (bowl.cap_height(R, l), 0.0, 0.0)
 
@@ -306,8 +308,8 @@ def paper_workload_bench(P, torch, ctx, stream, reps, log):
         j = [int(round((focus[ax] - g.origin[ax]) / g.h)) for ax in range(3)]
         focal.append(abs(complex(o[j[0], j[1], j[2]].item())))
     vox = [nsz(g) for g in gn]
-    res = {"workload": "H101 in water, 100 W, 4096 points, p2..p5 on rule-of-thumb boxes (d 10.5 mm) at "
-                       "lambda_n/6, linear transfer, complex64, kernel spectra recomputed",
+    res = {"workload": "H101 in water, 100 W, %d points (Deserno's regular placement), p2..p5 on rule-of-thumb "
+                       "boxes (d 10.5 mm) at lambda_n/6, linear transfer, complex64, kernel spectra recomputed" % n_p,
            "p1_grid": [int(v) for v in g1.n], "grids": [[int(v) for v in g.n] for g in gn],
            "circulants": [[P.circulant_size(int(v)) for v in g.n] for g in gn], "voxels": vox,
            "radiated_power_W_before_scaling": pw, "power_integral_s": t_power, "p1_ms": ms_p1,

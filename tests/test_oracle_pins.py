@@ -381,3 +381,24 @@ def test_tiny_nested_cascade_direct_equals_fft():
     # harmonics decay in size down the cascade at this amplitude
     mags = [np.max(np.abs(a[n])) for n in range(2, 6)]
     assert np.max(np.abs(p1)) > mags[0] > mags[1]
+
+
+@pytest.mark.parametrize("R,l", [(32e-3, 63.2e-3), (16.5e-3, 35e-3), (75e-3, 150e-3)])
+def test_deserno_placement_on_the_cap(R, l):
+    """Deserno's regular placement restricted to the bowl: about the requested count, every point
+    on the sphere of radius l about the focus inside the aperture, near-equal spacing at the
+    spacing an equal share of the area implies, and equal areas hold equal shares of points."""
+    n = 4096
+    pts = bowl.bowl_points_deserno(R, l, n)
+    assert abs(len(pts) - n) <= 0.01 * n
+    r = np.linalg.norm(pts - np.array([l, 0.0, 0.0]), axis=1)
+    assert np.max(np.abs(r - l)) < 1e-12 * l
+    assert np.all(np.hypot(pts[:, 1], pts[:, 2]) <= R * (1 + 1e-12))
+    d = np.linalg.norm(pts[:, None, :] - pts[None, :, :], axis=2)
+    np.fill_diagonal(d, np.inf)
+    nn = d.min(axis=1)
+    assert nn.min() / nn.mean() > 0.8 and nn.max() / nn.mean() < 1.1
+    assert abs(nn.mean() / math.sqrt(bowl.cap_area(R, l) / len(pts)) - 1.0) < 0.05
+    # the points above half the cap height: their share equals that sub-cap's share of the area
+    half = bowl.cap_height(R, l) / 2
+    assert abs(np.mean(pts[:, 0] <= half) - 0.5) < 0.02

@@ -51,6 +51,39 @@ def bowl_points(R, l, n_points, seed=0):
     return pts
 
 
+def bowl_points_deserno(R, l, n_target):
+    """(n, 3) float64 array of Deserno's regular placement on the cap, n close to n_target.
+
+    Deserno's regular equidistribution on a sphere (M. Deserno, "How to generate
+    equidistributed points on the surface of a sphere", 2004), restricted to the
+    bowl's polar-angle range [0, theta_max], sin(theta_max) = R / l, on the sphere of
+    radius l about the focus: with the area per point a = A / n_target and
+    d = sqrt(a) / l (an angle), the cap is cut into M_theta = round(theta_max / d)
+    bands of equal angular height d_theta = theta_max / M_theta; band m, at
+    theta_m = (m + 1/2) d_theta, carries M_phi = round(2 pi sin(theta_m) / d_phi)
+    points, d_phi = (a / l^2) / d_theta, at phi = 2 pi j / M_phi.  Apex at the
+    origin, axis +x, as bowl_points."""
+    if not (0.0 < R < l) or n_target < 1:
+        raise ValueError("bowl needs 0 < R < l and at least one point")
+    theta_max = math.asin(R / l)
+    a = cap_area(R, l) / n_target / (l * l)  # area per point on the unit sphere
+    d = math.sqrt(a)
+    m_theta = max(1, int(round(theta_max / d)))
+    d_theta = theta_max / m_theta
+    d_phi = a / d_theta
+    pts = []
+    for m in range(m_theta):
+        theta = (m + 0.5) * d_theta
+        m_phi = max(1, int(round(2.0 * math.pi * math.sin(theta) / d_phi)))
+        phi = 2.0 * math.pi * np.arange(m_phi) / m_phi
+        band = np.empty((m_phi, 3), dtype=np.float64)
+        band[:, 0] = l - l * math.cos(theta)
+        band[:, 1] = l * math.sin(theta) * np.cos(phi)
+        band[:, 2] = l * math.sin(theta) * np.sin(phi)
+        pts.append(band)
+    return np.concatenate(pts, axis=0)
+
+
 def rayleigh_scale(R, l, k1, p0, n_points):
     """Scale s of the monopole sum s * sum_j exp(i k r_j) / (4 pi r_j) that makes it the Rayleigh
     integral of a baffled cap of surface pressure p0: s = -2 i k p0 A / n_points."""
