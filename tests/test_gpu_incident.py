@@ -108,15 +108,16 @@ def test_point_on_a_voxel_centre_and_errors(ctx):
         P.incident_field(ctx, 1.0, 1.0, d[:, :2].contiguous(), g)
 
 
+@pytest.mark.parametrize("placement", ["spiral", "deserno"])
 @pytest.mark.parametrize("prec", [P.NVP_C128, P.NVP_C64])
-def test_arbitrary_targets(ctx, prec):
+def test_arbitrary_targets(ctx, prec, placement):
     R, l, f0 = 32e-3, 63.2e-3, 1.1e6
     k = oracle.wavenumber(1, f0, WATER)
-    pts = bowl.bowl_points(R, l, 777, seed=4)
-    s = bowl.rayleigh_scale(R, l, k, 1e5, 777)
+    pts = bowl.bowl_points(R, l, 777, seed=4) if placement == "spiral" else bowl.bowl_points_deserno(R, l, 777)
+    s = bowl.rayleigh_scale(R, l, k, 1e5, len(pts))
     rng = np.random.default_rng(5)
     tg = np.stack([rng.uniform(5e-3, 80e-3, 333), rng.uniform(-30e-3, 30e-3, 333), rng.uniform(-30e-3, 30e-3, 333)], 1)
-    say("case incident targets prec=%d" % prec)
+    say("case incident targets prec=%d placement=%s" % (prec, placement))
     got = P.incident_at(ctx, k, s, torch.from_numpy(pts).to("cuda"), torch.from_numpy(tg).to("cuda"), prec=prec)
     torch.cuda.synchronize()
     ref = oracle.incident_at(pts, k, s, tg)
