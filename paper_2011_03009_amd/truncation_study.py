@@ -120,11 +120,13 @@ def study(ctx, T, med, power, d, points, n_max=5, q0=Q0_LADDER, order=1, log=Non
 
 
 def table(ctx, configs, n_points=4096, log=None):
-    """Rows (name, per-harmonic (x, y/z) fractions) for a list of (name, transducer, medium, power, d)."""
+    """Rows (name, per-harmonic (x, y/z) fractions) for a list of (name, transducer, medium, power, d).
+
+    The bowl carries about n_points monopoles in Deserno's regular placement, as in the paper."""
     from workload import bowl
     rows = []
     for name, T, med, power, d in configs:
-        pts = torch.from_numpy(bowl.bowl_points(T["R"], T["l"], n_points, 0)).to("cuda")
+        pts = torch.from_numpy(bowl.bowl_points_deserno(T["R"], T["l"], n_points)).to("cuda")
         recs = study(ctx, T, med, power, d, pts, log=log)
         rows.append(dict(name=name, extent=[(r["size_x"], r["size_yz"]) for r in recs],
                          prefocal=[(r["need_x"], r["need_yz"]) for r in recs],
