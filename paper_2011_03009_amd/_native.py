@@ -97,7 +97,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError("libnvp.so is not built (%s); run __graft_entry__.build() or "
+            raise RuntimeError("libnvp.so is not built (%s); run "
                                "python -m paper_2011_03009_amd.build" % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():

@@ -1,6 +1,6 @@
 """Train the box predictor on convergence sweeps and evaluate it against the full box and the rule of thumb.
 
-  python -m paper_2011_03009_amd.train_boxnet --transducers 500 --eval 64 --out gpurun_out/boxnet
+  python -m paper_2011_03009_amd.train_boxnet --transducers 500 --eval 64 --out boxnet_out
 
 Training transducers are drawn from the batched workload's ranges with one
 seed, the held-out ones with another; p_1 is the Rayleigh integral of a
@@ -57,7 +57,7 @@ def main():
     ap.add_argument("--tau", type=float, default=0.9)
     ap.add_argument("--guard", type=float, default=BP.GUARD_DELTA)
     ap.add_argument("--eps", type=float, default=BP.EPS)
-    ap.add_argument("--out", default="gpurun_out/boxnet")
+    ap.add_argument("--out", default="boxnet_out")
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
     inc = make_incident()
