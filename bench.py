@@ -357,7 +357,7 @@ def batch_bench(P, torch, ctx, W, steps, log):
     from paper_2011_03009_amd import train_boxnet as TB
     Ts = TB.transducers(64, 0)
     net, _ = BP.load_net(ctx)
-    inc = TB.make_incident()
+    inc = TB.make_incident(ctx)
     probs, p1s = [], []
     for T in Ts:
         fr = BP.predict_fractions(net, T, ctx)

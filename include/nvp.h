@@ -43,7 +43,7 @@ typedef int32_t nvp_status;
 #define NVP_E_INVALID 1     /* bad argument: null pointer, h <= 0, n < 1, bad precision, ... */
 #define NVP_E_NOMEM 2       /* device or host allocation failed; no partial state kept */
 #define NVP_E_HIP 3         /* a HIP runtime call or kernel launch failed */
-#define NVP_E_UNSUPPORTED 4 /* valid request outside what this build handles (an axis beyond the compiled circulant lengths) */
+#define NVP_E_UNSUPPORTED 4 /* valid request outside what this build handles: an axis beyond 4096 voxels, a grid beyond a fixed scratch, a transfer order other than 1 or 3 */
 #define NVP_E_STATE 5       /* call out of order (e.g. timing read while disabled) */
 /* Fault injection for tests: with the environment variable
  * NVP_DEVICE_ALLOC_LIMIT set to a byte count, every device allocation of the
@@ -138,9 +138,15 @@ nvp_status nvp_rule_of_thumb_box(int n, double l, double R, double d, double eps
  * NVP_E_INVALID if src_n < order + 1. */
 nvp_status nvp_transfer_axis(double dst_origin, double dst_h, int64_t dst_n, double src_origin, double src_h,
                              int64_t src_n, int order, int32_t *base, double *w);
-/* Circulant length used for an axis of n voxels: the smallest supported
- * M >= 2 n - 1 (the embedding of Section 3.1 is exact for any such M). */
+/* Circulant length used for an axis of n voxels: the smallest compiled
+ * transform length M >= 2 n - 1 (the embedding of Section 3.1 is exact for any
+ * such M).  The compiled lengths are 2,3,5,7-smooth multiples of 8 from 16
+ * to 8192 (nvp_transform_lengths), spaced so that from n = 128 on M exceeds
+ * 2 n - 1 by less than 12.5%.  NVP_E_UNSUPPORTED for n > 4096. */
 nvp_status nvp_circulant_size(int64_t n, int64_t *m);
+/* The compiled transform lengths in increasing order: *count receives how
+ * many there are, and the first min(count, capacity) go to lengths (host). */
+nvp_status nvp_transform_lengths(int32_t *lengths, int capacity, int *count);
 
 /* ---- the incident field ---------------------------------------------------- */
 
@@ -194,6 +200,33 @@ nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nv
                                 const void *f_dev, void *u_dev, nvp_prec prec);
 
 
+/* The volume potential of a source restricted to a box, scaled:
+ *   u_i = scale * sum_{j in box} K(x_i - x_j) f_j   at every voxel i of g,
+ * K as in nvp_volume_potential (which is the case box = NULL, scale = -1).
+ * With scale = C_n this is p_n computed from the source f_n cut to an
+ * integration domain D (the truncated potentials of the domain study of
+ * Section 5, evaluated on the whole grid).  box: host, 6 int64 = inclusive
+ * voxel indices lo_x, lo_y, lo_z, hi_x, hi_y, hi_z inside the grid, or NULL
+ * for the whole grid.  Shares the context's kernel-spectrum cache with
+ * nvp_volume_potential.  NVP_E_INVALID: bad arguments, an empty box or one
+ * reaching outside the grid. */
+nvp_status nvp_volume_potential_box(nvp_ctx *ctx, double k_re, double k_im, const nvp_grid *g,
+                                    const void *f_dev, const int64_t *box, double scale, void *u_dev,
+                                    nvp_prec prec);
+
+/* Field arithmetic of the drivers built on the operator (the fixed-point
+ * sweeps of the full cascade, iterative solvers), on n complex values in
+ * prec, device buffers:
+ *   nvp_field_lin3:       out = a + al b + be c  (al, be complex: {re, im});
+ *                         a null a, b or c counts as zero; out may alias any
+ *                         operand.  Enqueued on the context stream.
+ *   nvp_field_diff_norms: out[0] = sum |a - b|^2, out[1] = sum |a|^2,
+ *                         accumulated in FP64; waits for the result. */
+nvp_status nvp_field_lin3(nvp_ctx *ctx, int64_t n, void *out_dev, const void *a_dev, const void *b_dev,
+                          const void *c_dev, const double al[2], const double be[2], nvp_prec prec);
+nvp_status nvp_field_diff_norms(nvp_ctx *ctx, int64_t n, const void *a_dev, const void *b_dev, nvp_prec prec,
+                                double out[2]);
+
 /* Volume integral equation of an inhomogeneous medium (Section 7, the
  * equations of the harmonics in an inhomogeneous domain): with background
  * wavenumber kb (Im kb >= 0) and contrast q_j = k(x_j)^2 - kb^2 per voxel,
@@ -236,7 +269,7 @@ nvp_status nvp_difference_term(nvp_ctx *ctx, const nvp_grid *gt, void *out_dev, 
  * paper recommends); target centres are clamped into the source grid's hull,
  * and a field on the very grid it is needed on is used as is.  Every axis
  * of a source grid needs at least transfer_order + 1 voxels, and every axis
- * a circulant length (nvp_circulant_size; up to 1024 voxels in this build).
+ * a circulant length (nvp_circulant_size; up to 4096 voxels per axis).
  * The plan discretises with the context's quadrature rule at creation. */
 nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int n_harm,
                             const nvp_grid *g1, const nvp_grid *gn, nvp_prec prec,

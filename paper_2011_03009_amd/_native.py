@@ -48,7 +48,11 @@ SIGNATURES = {
     "nvp_rule_of_thumb_box": (_st, [_i, _d, _d, _d, _d, _dp, _dp]),
     "nvp_transfer_axis": (_st, [_d, _d, _i64, _d, _d, _i64, _i, ctypes.POINTER(ctypes.c_int32), _dp]),
     "nvp_circulant_size": (_st, [_i64, _i64p]),
+    "nvp_transform_lengths": (_st, [ctypes.POINTER(ctypes.c_int32), _i, ctypes.POINTER(_i)]),
     "nvp_volume_potential": (_st, [_vp, _d, _d, ctypes.POINTER(Grid), _vp, _vp, _i]),
+    "nvp_volume_potential_box": (_st, [_vp, _d, _d, ctypes.POINTER(Grid), _vp, _i64p, _d, _vp, _i]),
+    "nvp_field_lin3": (_st, [_vp, _i64, _vp, _vp, _vp, _vp, _dp, _dp, _i]),
+    "nvp_field_diff_norms": (_st, [_vp, _i64, _vp, _vp, _i, _dp]),
     "nvp_incident_field": (_st, [_vp, _d, _d, _d, _d, _vp, ctypes.c_int64, ctypes.POINTER(Grid), _vp, _i]),
     "nvp_vie_solve": (_st, [_vp, _d, _d, ctypes.POINTER(Grid), _vp, _vp, _vp, _i, _d, _i, ctypes.POINTER(_i),
                             ctypes.POINTER(_d)]),

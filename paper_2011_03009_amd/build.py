@@ -30,9 +30,15 @@ def lengths():
     return [int(v) for v in re.findall(r"X\((\d+)\)", m.group(1))]
 
 
-def _headers():
-    return [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))] + \
-        [os.path.join(INCLUDE, "nvp.h")]
+def _deps(src, seen=None):
+    """src and the local headers it includes, transitively (quoted #include lines)."""
+    seen = set() if seen is None else seen
+    if src in seen or not os.path.exists(src):
+        return seen
+    seen.add(src)
+    for inc in re.findall(r'^\s*#\s*include\s+"([^"]+)"', open(src).read(), re.M):
+        _deps(os.path.normpath(os.path.join(os.path.dirname(src), inc)), seen)
+    return seen
 
 
 def _stale(obj, srcs):
@@ -51,18 +57,17 @@ def _run(cmd):
 
 
 def jobs_list():
-    hdr = _headers()
     jobs = []
+    inst = os.path.join(CSRC, "inst.hip")
     for L in lengths():
         obj = os.path.join(OBJ, "inst_%d.o" % L)
-        jobs.append((obj, [HIPCC] + COMMON + ["-DNVP_L=%d" % L, "-c", os.path.join(CSRC, "inst.hip"), "-o", obj],
-                     [os.path.join(CSRC, "inst.hip")] + hdr))
+        jobs.append((obj, [HIPCC] + COMMON + ["-DNVP_L=%d" % L, "-c", inst, "-o", obj], sorted(_deps(inst))))
     for name, extra in (("kspec.hip", []), ("dispatch.cpp", []), ("runtime.cpp", ["-ffp-contract=off"]),
                         ("qbox.hip", []), ("boxnet.hip", []), ("learn.cpp", []),
                         ("incident.hip", []), ("vie.hip", []), ("difference.hip", ["-ffp-contract=off"])):
         obj = os.path.join(OBJ, os.path.splitext(name)[0] + ".o")
         jobs.append((obj, [HIPCC] + COMMON + extra + ["-c", os.path.join(CSRC, name), "-o", obj],
-                     [os.path.join(CSRC, name)] + hdr))
+                     sorted(_deps(os.path.join(CSRC, name)))))
     return jobs
 
 

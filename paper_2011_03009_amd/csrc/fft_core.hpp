@@ -1,8 +1,10 @@
 // Stockham autosort mixed-radix FFT engine for gfx950 (64-wide wavefronts).
 //
-// One column of length L is transformed by P = L / E threads, each holding E
-// complex values in registers.  Stage s (radix r_s, Ns = r_0 ... r_{s-1})
-// reads butterfly b's inputs at b + q L / r_s, twiddles input q by
+// One column of length L is transformed by P threads.  Stage s (radix r_s,
+// Ns = r_0 ... r_{s-1}) has L / r_s butterflies; thread t does butterflies
+// b = t + i P, i < ceil(L / (r_s P)) (the last one only where b < L / r_s),
+// holding their r_s values each in registers.  Butterfly b
+// reads its inputs at b + q L / r_s, twiddles input q by
 // W^(j q L / (Ns r_s)) with j = b mod Ns and W = exp(-+ 2 pi i / L), does a
 // radix-r_s DFT, and writes output p to (b / Ns) Ns r_s + j + p Ns.  That
 // ordering is self-sorting: the last stage writes natural order, so its
@@ -153,21 +155,25 @@ template <typename R> struct Dft<16, R> {
     }
 };
 
-// cos and sin of 2 pi k / N for k = 1..(N-1)/2 (N = 3, 5, 7).
+// cos and sin of 2 pi k / N for k = 1..(N-1)/2 (N = 3, 5, 7, 9).
 __host__ __device__ constexpr double odd_cos(int N, int k) {
     return N == 3 ? -0.5
          : N == 5 ? (k == 1 ? 0.309016994374947424102293417183 : -0.809016994374947424102293417183)
-         : (k == 1 ? 0.623489801858733530525004884004
-            : k == 2 ? -0.222520933956314404288902564497 : -0.900968867902419126236102319507);
+         : N == 7 ? (k == 1 ? 0.623489801858733530525004884004
+                     : k == 2 ? -0.222520933956314404288902564497 : -0.900968867902419126236102319507)
+         : (k == 1 ? 0.766044443118978035202392650555 : k == 2 ? 0.173648177666930348851716626769
+            : k == 3 ? -0.5 : -0.939692620785908384054109277325);
 }
 __host__ __device__ constexpr double odd_sin(int N, int k) {
     return N == 3 ? 0.866025403784438646763723170753
          : N == 5 ? (k == 1 ? 0.951056516295153572116439333379 : 0.587785252292473129168705954639)
-         : (k == 1 ? 0.781831482468029808708444526674
-            : k == 2 ? 0.974927912181823607018131682994 : 0.433883739117558120475768332849);
+         : N == 7 ? (k == 1 ? 0.781831482468029808708444526674
+                     : k == 2 ? 0.974927912181823607018131682994 : 0.433883739117558120475768332849)
+         : (k == 1 ? 0.642787609686539326322643409907 : k == 2 ? 0.984807753012208059366743024590
+            : k == 3 ? 0.866025403784438646763723170753 : 0.342020143325668733044099614682);
 }
 
-// Odd N: pair v_q with v_{N-q}:  y_p = v_0 + sum_q a_q cos(2 pi p q / N) +- SG i sum_q b_q sin(...).
+// Odd N (any, prime or not): pair v_q with v_{N-q}:  y_p = v_0 + sum_q a_q cos(2 pi p q / N) +- SG i sum_q b_q sin(...).
 template <int N, typename R> struct DftOdd {
     template <int SG> static __device__ __forceinline__ void run(cx<R> *v) { run_lo<SG, N>(v); }
     template <int SG, int K> static __device__ __forceinline__ void run_lo(cx<R> *v) {
@@ -191,9 +197,9 @@ template <int N, typename R> struct DftOdd {
             cx<R> A = v[0], B = czero<R>();
 #pragma unroll
             for (int q = 1; q <= H; ++q) {
-                const int idx = (p * q) % N;
-                const R cv = R(idx <= H ? odd_cos(N, idx) : odd_cos(N, N - idx));
-                const R sv = R(idx <= H ? odd_sin(N, idx) : -odd_sin(N, N - idx));
+                const int idx = (p * q) % N;  // 0 where N is not prime (N = 9: p q = 3 * 3)
+                const R cv = R(idx == 0 ? 1.0 : idx <= H ? odd_cos(N, idx) : odd_cos(N, N - idx));
+                const R sv = R(idx == 0 ? 0.0 : idx <= H ? odd_sin(N, idx) : -odd_sin(N, N - idx));
                 A = cadd<R>(A, cscale<R>(a[q - 1], cv));
                 B = cadd<R>(B, cscale<R>(b[q - 1], sv));
             }
@@ -209,6 +215,7 @@ template <int N, typename R> struct DftOdd {
 template <typename R> struct Dft<3, R> : DftOdd<3, R> {};
 template <typename R> struct Dft<5, R> : DftOdd<5, R> {};
 template <typename R> struct Dft<7, R> : DftOdd<7, R> {};
+template <typename R> struct Dft<9, R> : DftOdd<9, R> {};
 
 // ---------------------------------------------------------------- octant layout
 
@@ -222,38 +229,81 @@ __host__ __device__ constexpr int64_t octant_row(int64_t Mz) { return (Mz / 2 + 
 struct PlanDesc {
     int S;      // number of stages
     int r[6];   // radix of each stage
-    int E;      // complex values per thread (a multiple of every radix)
+    int P;      // threads per column
 };
 
 // Radix plans of the supported lengths.  The first stage reads global memory
 // directly and the last writes it, so fewer stages mean fewer LDS round trips.
+// A column's threads split each stage's butterflies as evenly as they can;
+// where L / r is not a multiple of P, some threads of that stage have one
+// butterfly fewer.  P is a power of two up to 64 where that keeps the
+// registers per thread (the largest butterfly share times its radix) at 48
+// complex values or fewer, so that the contiguous axis can run a column in
+// one wavefront.
 __host__ __device__ constexpr PlanDesc plan_for(int L) {
     switch (L) {
-    case 16: return PlanDesc{1, {16, 0, 0, 0, 0, 0}, 16};
-    case 32: return PlanDesc{2, {2, 16, 0, 0, 0, 0}, 16};
-    case 48: return PlanDesc{3, {3, 4, 4, 0, 0, 0}, 12};
-    case 64: return PlanDesc{2, {4, 16, 0, 0, 0, 0}, 16};
-    case 96: return PlanDesc{3, {3, 4, 8, 0, 0, 0}, 24};
-    case 128: return PlanDesc{2, {8, 16, 0, 0, 0, 0}, 16};
-    case 160: return PlanDesc{3, {5, 4, 8, 0, 0, 0}, 40};
-    case 192: return PlanDesc{3, {3, 8, 8, 0, 0, 0}, 24};
+    case 16: return PlanDesc{1, {16, 0, 0, 0, 0, 0}, 1};
+    case 32: return PlanDesc{2, {2, 16, 0, 0, 0, 0}, 2};
+    case 48: return PlanDesc{3, {3, 4, 4, 0, 0, 0}, 4};
+    case 64: return PlanDesc{2, {4, 16, 0, 0, 0, 0}, 4};
+    case 80: return PlanDesc{3, {4, 4, 5, 0, 0, 0}, 4};
+    case 96: return PlanDesc{3, {3, 4, 8, 0, 0, 0}, 4};
+    case 112: return PlanDesc{3, {7, 4, 4, 0, 0, 0}, 4};
+    case 128: return PlanDesc{2, {8, 16, 0, 0, 0, 0}, 8};
+    case 144: return PlanDesc{3, {4, 9, 4, 0, 0, 0}, 4};
+    case 160: return PlanDesc{3, {5, 4, 8, 0, 0, 0}, 4};
+    case 192: return PlanDesc{3, {3, 8, 8, 0, 0, 0}, 8};
+    case 224: return PlanDesc{3, {16, 7, 2, 0, 0, 0}, 8};
     case 256: return PlanDesc{2, {16, 16, 0, 0, 0, 0}, 16};
-    case 320: return PlanDesc{3, {5, 8, 8, 0, 0, 0}, 40};
-    case 384: return PlanDesc{4, {3, 8, 4, 4, 0, 0}, 24};
-    case 448: return PlanDesc{4, {7, 4, 4, 4, 0, 0}, 28};
-    case 512: return PlanDesc{3, {8, 8, 8, 0, 0, 0}, 16};
-    case 640: return PlanDesc{4, {8, 4, 4, 5, 0, 0}, 40};  // the order 5,8,4,4 computed wrong FP64 results
-    case 768: return PlanDesc{4, {3, 4, 8, 8, 0, 0}, 24};
-    case 896: return PlanDesc{5, {7, 4, 4, 4, 2, 0}, 28};
+    case 288: return PlanDesc{3, {8, 9, 4, 0, 0, 0}, 16};
+    case 320: return PlanDesc{3, {5, 8, 8, 0, 0, 0}, 8};
+    case 336: return PlanDesc{3, {16, 7, 3, 0, 0, 0}, 16};
+    case 360: return PlanDesc{3, {8, 9, 5, 0, 0, 0}, 16};
+    case 384: return PlanDesc{4, {3, 8, 4, 4, 0, 0}, 16};
+    case 432: return PlanDesc{3, {16, 9, 3, 0, 0, 0}, 16};
+    case 448: return PlanDesc{4, {7, 4, 4, 4, 0, 0}, 16};
+    case 480: return PlanDesc{4, {16, 5, 3, 2, 0, 0}, 16};
+    case 512: return PlanDesc{3, {8, 8, 8, 0, 0, 0}, 32};
+    case 576: return PlanDesc{3, {8, 9, 8, 0, 0, 0}, 16};
+    case 640: return PlanDesc{4, {8, 4, 4, 5, 0, 0}, 16};
+    case 720: return PlanDesc{3, {16, 9, 5, 0, 0, 0}, 32};
+    case 768: return PlanDesc{4, {3, 4, 8, 8, 0, 0}, 32};
+    case 864: return PlanDesc{4, {16, 9, 3, 2, 0, 0}, 32};
+    case 896: return PlanDesc{5, {7, 4, 4, 4, 2, 0}, 32};
+    case 960: return PlanDesc{4, {16, 5, 3, 4, 0, 0}, 32};
     case 1024: return PlanDesc{3, {16, 8, 8, 0, 0, 0}, 32};
-    case 1280: return PlanDesc{4, {5, 8, 8, 4, 0, 0}, 40};
-    case 1536: return PlanDesc{4, {3, 8, 8, 8, 0, 0}, 24};
-    case 2048: return PlanDesc{3, {16, 16, 8, 0, 0, 0}, 32};
+    case 1152: return PlanDesc{4, {8, 9, 4, 4, 0, 0}, 32};
+    case 1280: return PlanDesc{4, {5, 8, 8, 4, 0, 0}, 32};
+    case 1344: return PlanDesc{4, {8, 7, 3, 8, 0, 0}, 64};
+    case 1440: return PlanDesc{4, {8, 9, 5, 4, 0, 0}, 64};
+    case 1536: return PlanDesc{4, {3, 8, 8, 8, 0, 0}, 64};
+    case 1728: return PlanDesc{4, {16, 9, 3, 4, 0, 0}, 64};
+    case 1792: return PlanDesc{3, {16, 7, 16, 0, 0, 0}, 64};
+    case 1920: return PlanDesc{4, {16, 5, 3, 8, 0, 0}, 64};
+    case 2048: return PlanDesc{3, {16, 16, 8, 0, 0, 0}, 64};
+    case 2304: return PlanDesc{4, {8, 9, 8, 4, 0, 0}, 64};
+    case 2560: return PlanDesc{4, {8, 5, 8, 8, 0, 0}, 64};
+    case 2880: return PlanDesc{4, {16, 9, 5, 4, 0, 0}, 64};
+    case 3072: return PlanDesc{4, {16, 3, 16, 4, 0, 0}, 64};
+    case 3456: return PlanDesc{4, {16, 9, 3, 8, 0, 0}, 128};
+    case 3840: return PlanDesc{4, {16, 5, 3, 16, 0, 0}, 128};
+    case 4096: return PlanDesc{3, {16, 16, 16, 0, 0, 0}, 128};
+    case 4608: return PlanDesc{4, {8, 9, 8, 8, 0, 0}, 128};
+    case 5120: return PlanDesc{4, {16, 5, 8, 8, 0, 0}, 256};
+    case 5760: return PlanDesc{4, {16, 9, 5, 8, 0, 0}, 256};
+    case 6144: return PlanDesc{4, {16, 3, 16, 8, 0, 0}, 256};
+    case 6912: return PlanDesc{4, {16, 9, 3, 16, 0, 0}, 256};
+    case 7680: return PlanDesc{5, {16, 5, 3, 16, 2, 0}, 256};
+    case 8192: return PlanDesc{4, {16, 16, 16, 2, 0, 0}, 256};
     default: return PlanDesc{0, {0, 0, 0, 0, 0, 0}, 0};
     }
 }
 
-__host__ __device__ constexpr int plan_threads(int L) { return plan_for(L).E ? L / plan_for(L).E : 0; }
+__host__ __device__ constexpr int plan_threads(int L) { return plan_for(L).P; }
+// Whether a column's threads fit one wavefront with no column straddling two.
+__host__ __device__ constexpr bool plan_wave_local(int L) {
+    return plan_threads(L) > 0 && plan_threads(L) <= 64 && 64 % plan_threads(L) == 0;
+}
 
 // Radix of stage s and product of the radices before it, for the plan run
 // forward (rev = false) or in reverse radix order (rev = true).
@@ -316,13 +366,17 @@ template <typename R, int T> struct is_split_cols<SplitCols<R, T>> { static cons
 // accesses on either side may provably not alias (so the compiler would be
 // free to swap them), but other lanes' do: the memory clobber keeps every LDS
 // access on its side, and the wait makes the writes complete before any lane
-// reads.
+// reads.  (NVP_HOST_EMULATION: the engine compiled for the host by the
+// CPU tests, which run a column's threads as host threads and supply their
+// own wave_sync and __syncthreads.)
+#ifndef NVP_HOST_EMULATION
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+#endif
 
 // REV = true runs the stages in reverse radix order.  Its first stage then has
 // the radix of the forward plan's last stage, so a forward transform's
@@ -334,29 +388,64 @@ __device__ __forceinline__ void wave_sync() {
 template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
     static constexpr PlanDesc D = plan_for(L);
     static constexpr int S = D.S;
-    static constexpr int E = D.E;
-    static constexpr int P = L / E;  // threads per column
+    static constexpr int P = D.P;  // threads per column
     static_assert(S > 0, "unsupported FFT length");
-    static_assert(!WAVE || P <= 64, "a wave-local column needs at most 64 threads");
+    static_assert(!WAVE || (P <= 64 && 64 % P == 0), "a wave-local column needs at most 64 threads, 64 % P == 0");
     static constexpr int TW_BASE = REV ? plan_tw_len(L, false) : 0;  // offset in the two-direction table
 
-    static constexpr int rad(int s) { return plan_rad(L, REV, s); }
-    static constexpr int ns(int s) { return plan_ns(L, REV, s); }
+    // (from the plan held in D, so that the compile-time checks below do not
+    // look the plan up again for every index they check)
+    static constexpr int rad(int s) { return REV ? D.r[S - 1 - s] : D.r[s]; }
+    static constexpr int ns(int s) {
+        int n = 1;
+        for (int i = 0; i < s; ++i) n *= rad(i);
+        return n;
+    }
+    // butterflies of stage s, and how many each thread takes (the last one
+    // only where t + i P < nb(s): full(s) says every thread has all of them)
+    static constexpr int nb(int s) { return L / rad(s); }
+    static constexpr int per(int s) { return (nb(s) + P - 1) / P; }
+    static constexpr bool full(int s) { return nb(s) % P == 0; }
+    static constexpr int regs() {
+        int e = 0;
+        for (int s = 0; s < S; ++s) e = per(s) * rad(s) > e ? per(s) * rad(s) : e;
+        return e;
+    }
+    static constexpr bool every_thread_busy() {
+        for (int s = 0; s < S; ++s)
+            if (nb(s) < P) return false;
+        return true;
+    }
+    static_assert(every_thread_busy(), "each stage needs at least one butterfly per thread");
+    static constexpr int E = regs();                      // complex values per thread
+    static constexpr int EOUT = per(S - 1) * rad(S - 1);  // registers the last stage leaves (compute_keep)
 
     static __device__ __forceinline__ void sync() {
         if constexpr (WAVE) wave_sync();
         else __syncthreads();
     }
 
-    // Output index held in register `slot` after the last stage.
+    template <int s> static __device__ __forceinline__ bool valid(int t, int i) {
+        if constexpr (full(s)) return true;
+        else return t + i * P < nb(s);
+    }
+
+    // Output index held in register `slot` (< EOUT) after the last stage, and
+    // whether that register holds an output at all.
     static __device__ __forceinline__ int out_index(int t, int slot) {
         constexpr int r = rad(S - 1);
         return t + (slot / r) * P + (slot % r) * (L / r);
     }
+    static __device__ __forceinline__ bool out_valid(int t, int slot) {
+        return valid<S - 1>(t, slot / rad(S - 1));
+    }
 
-    template <int r, int SG> static __device__ __forceinline__ void bflies(cx<R> *v) {
+    // Butterflies of stage s on v (a thread's share; values of a missing last
+    // butterfly are transformed too, and never stored).
+    template <int s, int SG> static __device__ __forceinline__ void bflies(cx<R> *v) {
+        constexpr int r = rad(s);
 #pragma unroll
-        for (int i = 0; i < E / r; ++i) Dft<r, R>::template run<SG>(v + i * r);
+        for (int i = 0; i < per(s); ++i) Dft<r, R>::template run<SG>(v + i * r);
     }
 
     // Inputs at or beyond L/2 of a column whose upper half is zero: first-stage
@@ -366,9 +455,9 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
         constexpr int r0 = rad(0);
         if constexpr (ZH) {
 #pragma unroll
-            for (int i = 0; i < E / r0; ++i) Dft<r0, R>::template run_lo<SG, K0>(v + i * r0);
+            for (int i = 0; i < per(0); ++i) Dft<r0, R>::template run_lo<SG, K0>(v + i * r0);
         } else {
-            bflies<r0, SG>(v);
+            bflies<0, SG>(v);
         }
     }
 
@@ -377,56 +466,64 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
     static __host__ __device__ constexpr int wr_idx(int s, int t, int i) {
         const int Ns = ns(s), r = rad(s);
         if (P % Ns == 0) return (t / Ns) * Ns * r + (t % Ns) + i * P * r;
-        if (P * (E / r) <= Ns) return t + i * P;
+        if (P * per(s) <= Ns) return t + i * P;
         const int b = t + i * P;
         return (b / Ns) * Ns * r + b % Ns;
     }
     template <int s> static __device__ __forceinline__ int wr_index(int t, int i) { return wr_idx(s, t, i); }
     // j = b mod Ns for b = t + i P, likewise.
     template <int s> static __device__ __forceinline__ int tw_j(int t, int i) {
-        constexpr int Ns = ns(s), r = rad(s);
+        constexpr int Ns = ns(s);
         if constexpr (P % Ns == 0) return t % Ns;
-        else if constexpr (P * (E / r) <= Ns) return t + i * P;
+        else if constexpr (P * per(s) <= Ns) return t + i * P;
         else return (t + i * P) % Ns;
     }
 
     // Whether the writes of stage s (element wr_idx(s, t, i) + p Ns) and the
     // reads of stage s (element t + i P + q L / r) may address a padded slot
-    // as pad(base) + pad(offset), checked for every thread and slot.
+    // as pad(base) + pad(offset) with the offset taken from thread 0, checked
+    // for every thread and butterfly.
     static constexpr bool split_writes(int s) {
         const int Ns = ns(s), r = rad(s);
-        if (!(P % Ns == 0 || P * (E / r) <= Ns)) return false;
+        if (!(P % Ns == 0 || P * per(s) <= Ns)) return false;
         for (int t = 0; t < P; ++t) {
             const int B = wr_idx(s, t, 0);
-            for (int i = 0; i < E / r; ++i)
+            for (int i = 0; i < per(s); ++i) {
+                if (t + i * P >= nb(s)) continue;
                 for (int p = 0; p < r; ++p) {
                     const int c = wr_idx(s, t, i) - B + p * Ns;
-                    if (c < 0 || pencil_pad<R>(B + c) != pencil_pad<R>(B) + pencil_pad<R>(c)) return false;
+                    const int c0 = wr_idx(s, 0, i) - wr_idx(s, 0, 0) + p * Ns;
+                    if (c != c0 || c < 0 || pencil_pad<R>(B + c) != pencil_pad<R>(B) + pencil_pad<R>(c)) return false;
                 }
+            }
         }
         return true;
     }
     static constexpr bool split_reads(int s) {
         const int r = rad(s);
         for (int t = 0; t < P; ++t)
-            for (int i = 0; i < E / r; ++i)
+            for (int i = 0; i < per(s); ++i) {
+                if (t + i * P >= nb(s)) continue;
                 for (int q = 0; q < r; ++q) {
                     const int c = i * P + q * (L / r);
                     if (pencil_pad<R>(t + c) != pencil_pad<R>(t) + pencil_pad<R>(c)) return false;
                 }
+            }
         return true;
     }
 
-    // First-stage inputs: v[i r0 + q] = x[t + i P + q L / r0].  ZH: the
-    // column's elements from L/2 on are zero and are not read.
+    // First-stage inputs: v[i r0 + q] = x[t + i P + q L / r0] for the
+    // thread's butterflies (zero for a missing last one, which reads nothing).
+    // ZH: the column's elements from L/2 on are zero and are not read.
     template <bool ZH = false, class Ld> static __device__ __forceinline__ void load0(cx<R> *v, int t, Ld ld) {
         constexpr int r0 = rad(0);
 #pragma unroll
-        for (int i = 0; i < E / r0; ++i) {
+        for (int i = 0; i < per(0); ++i) {
             const int b = t + i * P;
+            const bool ok = valid<0>(t, i);
 #pragma unroll
             for (int q = 0; q < r0; ++q) {
-                if (!ZH || q < K0) v[i * r0 + q] = ld(b + q * (L / r0));
+                if ((!ZH || q < K0) && ok) v[i * r0 + q] = ld(b + q * (L / r0));
                 else v[i * r0 + q] = czero<R>();
             }
         }
@@ -440,7 +537,7 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
         next<0, SG, true, OH>(v, t, tw, st, lds);
     }
 
-    // All stages on v; the outputs stay in v (see out_index).
+    // All stages on v; the outputs stay in v (see out_index, out_valid).
     template <int SG, bool ZH = false, class Tw, class Lds>
     static __device__ __forceinline__ void compute_keep(cx<R> *v, int t, Tw tw, Lds lds) {
         bflies0<SG, ZH>(v);
@@ -469,14 +566,16 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
 #pragma unroll
         for (int part = 0; part < 2; ++part) {
 #pragma unroll
-            for (int i = 0; i < E / r; ++i) {
+            for (int i = 0; i < per(s); ++i) {
+                if (!valid<s>(t, i)) continue;
                 const int w = wr_index<s>(t, i);
 #pragma unroll
                 for (int p = 0; p < r; ++p) lds.re(w + p * Ns) = part ? v[i * r + p].y : v[i * r + p].x;
             }
             sync();
 #pragma unroll
-            for (int i = 0; i < E / r1; ++i) {
+            for (int i = 0; i < per(s + 1); ++i) {
+                if (!valid<s + 1>(t, i)) continue;
                 const int b = t + i * P;
 #pragma unroll
                 for (int q = 0; q < r1; ++q) {
@@ -501,7 +600,8 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
         if constexpr (s == S - 1) {
             if constexpr (STORE) {
 #pragma unroll
-                for (int i = 0; i < E / r; ++i) {
+                for (int i = 0; i < per(s); ++i) {
+                    if (!valid<s>(t, i)) continue;
                     const int b = t + i * P;
 #pragma unroll
                     for (int p = 0; p < r; ++p)
@@ -510,14 +610,16 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
             }
         } else {
             constexpr int r1 = rad(s + 1);
+            constexpr int I1 = per(s + 1);
             constexpr int off = TW_BASE + plan_tw_off(L, REV, s + 1);
             // next stage's twiddles first, so that their loads are in flight during the
             // LDS exchange (complex64; complex128 values would cost too many registers)
             constexpr bool PRE = sizeof(R) == 4;
-            cx<R> wv[E / r1][r1 - 1];
+            cx<R> wv[I1][r1 - 1];
             if constexpr (PRE) {
 #pragma unroll
-                for (int i = 0; i < E / r1; ++i) {
+                for (int i = 0; i < I1; ++i) {
+                    if (!valid<s + 1>(t, i)) continue;
                     const int jb = off + tw_j<s + 1>(t, i) * (r1 - 1) - 1;
 #pragma unroll
                     for (int q = 1; q < r1; ++q) wv[i][q - 1] = tw(jb + q);
@@ -533,7 +635,8 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
             constexpr bool WS = is_pencil_slot<Lds>::value && split_writes(s);
             const int pw = WS ? pencil_pad<R>(wr_index<s>(t, 0)) : 0;
 #pragma unroll
-            for (int i = 0; i < E / r; ++i) {
+            for (int i = 0; i < per(s); ++i) {
+                if (!valid<s>(t, i)) continue;
                 const int w = wr_index<s>(t, i);
 #pragma unroll
                 for (int p = 0; p < r; ++p) {
@@ -545,7 +648,8 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
             constexpr bool RS = is_pencil_slot<Lds>::value && split_reads(s + 1);
             const int pr = RS ? pencil_pad<R>(t) : 0;
 #pragma unroll
-            for (int i = 0; i < E / r1; ++i) {
+            for (int i = 0; i < I1; ++i) {
+                if (!valid<s + 1>(t, i)) continue;
                 const int b = t + i * P;
                 if constexpr (RS) v[i * r1] = lds.at(pr, i * P);
                 else v[i * r1] = lds(b);
@@ -560,7 +664,7 @@ template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
             }
             sync();
             }
-            bflies<r1, SG>(v);
+            bflies<s + 1, SG>(v);
             next<s + 1, SG, STORE, OH>(v, t, tw, st, lds);
         }
     }

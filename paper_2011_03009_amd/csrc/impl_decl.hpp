@@ -16,7 +16,6 @@ template <typename R, int L>
 hipError_t strided_multi_impl(const StridedTaskArgs *, int, int64_t, int, int, const void *, hipStream_t);
 template <typename R, int L>
 hipError_t zconv_multi_impl(const ZconvTaskArgs *, int, int64_t, const void *, hipStream_t);
-template <typename R, int L> constexpr int zconv_default_qw();
 
 template <int L>
 hipError_t kz_impl(double2 *, const int64_t[3], const int64_t[3], const double2 *, const void *, hipStream_t);

@@ -545,30 +545,36 @@ k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems)
 // The z pass of the convolution.  A quad = the up-to-four pencils
 // (kx, ky), (Mx-kx, ky), (kx, My-ky), (Mx-kx, My-ky) that share one row of the
 // kernel spectrum's octant (the embedded kernel is even on every axis, so
-// K^(k) = K^(M - k)); QW quads per workgroup.  Each pencil: Nz inputs ->
-// forward FFT of length Mz -> times K^ -> inverse FFT -> first Nz outputs
-// written back in place.  A pencil's threads lie in one wavefront, so the
-// waves run without workgroup barriers; twiddles come through the caches from
-// the global table (staging them in LDS cost occupancy and was slower).  The
-// inverse runs the radix plan in reverse order, so the forward outputs feed
-// it straight from registers, where the product with K^ is taken.
-template <typename R, int L, int QW>
+// K^(k) = K^(M - k)).  A workgroup takes SLOTS consecutive pencils of the
+// quad sequence (pencil 4 q + j is member j of quad q): SLOTS = 4 or 8 keeps
+// whole quads together; long transforms, whose pencils do not all fit the
+// LDS at once, take 2 or 1.  Each pencil: Nz inputs -> forward FFT of length
+// Mz -> times K^ -> inverse FFT -> first Nz outputs written back in place.
+// Where a pencil's threads lie in one wavefront the waves run without
+// workgroup barriers; twiddles come through the caches from the global table
+// (staging them in LDS cost occupancy and was slower).  The inverse runs the
+// radix plan in reverse order, so the forward outputs feed it straight from
+// registers, where the product with K^ is taken.
+template <typename R, int L, int SLOTS>
 __device__ __forceinline__ void zconv_block(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx,
                                             int64_t My, int Nz, int64_t Hy, int64_t n_quads,
                                             const cx<R> *__restrict__ tw, int64_t block) {
-    using F = Fft<R, L, false, true>;
-    using G = Fft<R, L, true, true>;
-    constexpr int E = F::E;
-    constexpr int HZ = L / 2 + 1;
+    constexpr bool WL = plan_wave_local(L);
+    using F = Fft<R, L, false, WL>;
+    using G = Fft<R, L, true, WL>;
+    constexpr int EO = F::EOUT;
     constexpr int SL = slot_len<R>(L);
     cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
-    const int tid = threadIdx.x, t = tid % F::P, slot = tid / F::P, j = slot & 3;
-    // The workgroup's first quad is split into (kx, ky) once, with a 32-bit
-    // division on workgroup-uniform values (the host keeps the quad count
-    // below 2^31); a slot's own quad follows with at most one carry, since
-    // QW <= 2 <= Hy.  The mirrored index M - k needs no division either:
-    // k = 0 mirrors onto itself.
-    const uint32_t hy = (uint32_t)Hy, q0 = (uint32_t)block * (uint32_t)QW, sq = (uint32_t)(slot >> 2);
+    const int tid = threadIdx.x, t = tid % F::P, slot = tid / F::P;
+    // The workgroup's first pencil v0 = block SLOTS lies in quad q0 = v0 / 4,
+    // split into (kx, ky) once, with a 32-bit division on workgroup-uniform
+    // values (the host keeps the pencil count below 2^31); a slot's own quad
+    // is at most two further on and follows with one carry, since Hy >= 9.
+    // The mirrored index M - k needs no division either: k = 0 mirrors onto
+    // itself.
+    const uint32_t hy = (uint32_t)Hy, v0 = (uint32_t)block * (uint32_t)SLOTS, q0 = v0 >> 2;
+    const uint32_t vs = v0 + (uint32_t)slot, sq = (vs >> 2) - q0;
+    const int j = (int)(vs & 3u);
     const uint32_t kx0 = q0 / hy;
     const bool valid = (int64_t)(q0 + sq) < n_quads;
     uint32_t ukx = kx0, uky = q0 - kx0 * hy + sq;
@@ -581,9 +587,9 @@ __device__ __forceinline__ void zconv_block(cx<R> *__restrict__ buf, const cx<R>
     const cx<R> *krow = khat + (kx * Hy + ky) * octant_row(L);
     cx<R> *my = lds + slot * SL;
     const PencilSlot<R> ref{my};
-    cx<R> v[E];
+    cx<R> v[F::E];
     // the pencil's upper half is zero (Mz >= 2 Nz - 1) and only its lower half
-    // is kept.  Loads need no guard but m < Nz: a quad past the last maps to
+    // is kept.  Loads need no guard but m < Nz: a pencil past the last maps to
     // pencil (0, 0) and kernel row (0, 0), which exist, and an inactive
     // pencil's results are never stored.  With an even first radix the first
     // stage reads only elements below L/2, so for Nz = L/2 none is guarded.
@@ -593,17 +599,21 @@ __device__ __forceinline__ void zconv_block(cx<R> *__restrict__ buf, const cx<R>
     else
         F::template load0<true>(v, t, [&](int m) { return m < Nz ? pen[m] : czero<R>(); });
     // the spectrum values this thread multiplies by, loaded before the forward
-    // transform so that their latency overlaps it
-    cx<R> kv[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
+    // transform so that their latency overlaps it (where registers allow)
+    constexpr bool KPRE = sizeof(R) == 4 || EO <= 32;
+    auto kval = [&](int i) {
         const int k = F::out_index(t, i);
-        kv[i] = krow[k <= L / 2 ? k : L - k];
+        return F::out_valid(t, i) ? krow[k <= L / 2 ? k : L - k] : czero<R>();
+    };
+    cx<R> kv[KPRE ? EO : 1];
+    if constexpr (KPRE) {
+#pragma unroll
+        for (int i = 0; i < EO; ++i) kv[i] = kval(i);
     }
     auto twf = [&](int e) { return tw[e]; };
     F::template compute_keep<-1, true>(v, t, twf, ref);
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = cmul<R>(v[i], kv[i]);
+    for (int i = 0; i < EO; ++i) v[i] = cmul<R>(v[i], KPRE ? kv[i] : kval(i));
     G::template compute<1, false, true>(v, t, twf,
                            [&](int m, cx<R> x) {
                                if (act && m < Nz) pen[m] = x;
@@ -611,23 +621,23 @@ __device__ __forceinline__ void zconv_block(cx<R> *__restrict__ buf, const cx<R>
                            ref);
 }
 
-template <typename R, int L, int QW>
-__global__ void __launch_bounds__(4 * QW * plan_threads(L))
+template <typename R, int L, int SLOTS>
+__global__ void __launch_bounds__(SLOTS *plan_threads(L))
 k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int64_t My, int Nz, int64_t Hy,
         int64_t n_quads, const cx<R> *__restrict__ tw) {
-    zconv_block<R, L, QW>(buf, khat, Mx, My, Nz, Hy, n_quads, tw, blockIdx.x);
+    zconv_block<R, L, SLOTS>(buf, khat, Mx, My, Nz, Hy, n_quads, tw, blockIdx.x);
 }
 
 // Multi-task z pass (batches), laid out like k_strided_multi.
-template <typename R, int L, int QW>
-__global__ void __launch_bounds__(4 * QW * plan_threads(L))
+template <typename R, int L, int SLOTS>
+__global__ void __launch_bounds__(SLOTS *plan_threads(L))
 k_zconv_multi(const ZconvTaskArgs *__restrict__ tasks, int ntasks, const cx<R> *__restrict__ tw) {
     const int64_t b = blockIdx.x;
     int k = 0;
     while (k + 1 < ntasks && tasks[k + 1].first <= b) ++k;
     const ZconvTaskArgs a = tasks[k];
-    zconv_block<R, L, QW>(static_cast<cx<R> *>(a.buf), static_cast<const cx<R> *>(a.khat), a.Mx, a.My, a.Nz, a.Hy,
-                          a.n_quads, tw, b - a.first);
+    zconv_block<R, L, SLOTS>(static_cast<cx<R> *>(a.buf), static_cast<const cx<R> *>(a.khat), a.Mx, a.My, a.Nz,
+                             a.Hy, a.n_quads, tw, b - a.first);
 }
 
 // First pass of the kernel spectrum, fused with the kernel's tabulation: one
@@ -637,11 +647,12 @@ k_zconv_multi(const ZconvTaskArgs *__restrict__ tasks, int ntasks, const cx<R> *
 // embedding is exact for M >= 2N - 1) -- are gathered into LDS in FP64, then
 // the FFT of the even extension to length L is written back as the row's first
 // Hz outputs.
-template <int L, int PW>
+template <int L, int PW, bool TWL>
 __global__ void __launch_bounds__(PW *plan_threads(L))
 k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, int64_t Nz,
      const double2 *__restrict__ ktab, const double2 *__restrict__ tw) {
-    using F = Fft<double, L, false, true>;
+    constexpr bool WL = plan_wave_local(L);
+    using F = Fft<double, L, false, WL>;
     constexpr int HZ = L / 2 + 1;
     constexpr int SL = slot_len<double>(L);
     constexpr int NT = plan_tw_len(L, false);
@@ -657,10 +668,12 @@ k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, 
     while (uj >= hy) uj -= hy, ++ui;
     const int64_t i = act ? ui : 0, jj = act ? uj : 0;
     cx<double> *my = lds + c * SL;
-    cx<double> *twl = lds + PW * SL;
-    stage_table<double>(twl, tw, NT);
-    __syncthreads();
-    auto twf = [&](int e) { return twl[e]; };
+    cx<double> *twl = lds + PW * SL;  // the twiddle table, staged when it fits (TWL)
+    if constexpr (TWL) {
+        stage_table<double>(twl, tw, NT);
+        __syncthreads();
+    }
+    auto twf = [&](int e) { return TWL ? twl[e] : tw[e]; };
     // all of this thread's gathers in flight before the first store
     constexpr int NK = (HZ + F::P - 1) / F::P;
     double2 g[NK];
@@ -675,7 +688,8 @@ k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, 
         const int k = t + q * F::P;
         if (k < HZ) my[padded<double>(k)] = g[q];
     }
-    wave_sync();
+    if constexpr (WL) wave_sync();
+    else __syncthreads();
     F::template run<-1, true>(
         t, twf, [&](int m) { return my[padded<double>(m <= L / 2 ? m : L - m)]; },
         [&](int m, cx<double> v) {

@@ -86,9 +86,6 @@ int threads_per_column(int L) { return plan_threads(L); }
 
 int strided_tile_cols(int L, int dbl) { return dbl ? strided_cols<double>(L) : strided_cols<float>(L); }
 
-int zconv_quads_per_block(int L, int dbl) {
-    const int slot = dbl ? slot_len<double>(L) * 16 : slot_len<float>(L) * 8;
-    return (4 * plan_threads(L) <= 128 && 8 * slot <= 81920) ? 2 : 1;
-}
+int zconv_slots_per_block(int L, int dbl) { return zconv_slots_for(L, dbl ? sizeof(double2) : sizeof(float2)); }
 
 }  // namespace nvp

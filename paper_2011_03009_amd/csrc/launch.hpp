@@ -8,8 +8,10 @@
 
 // Transform lengths with a compiled radix plan.
 #define NVP_FOR_EACH_LENGTH(X) \
-    X(16) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(448) X(512) X(640) X(768) X(896) \
-    X(1024) X(1280) X(1536) X(2048)
+    X(16) X(32) X(48) X(64) X(80) X(96) X(112) X(128) X(144) X(160) X(192) X(224) X(256) X(288) X(320) X(336) \
+    X(360) X(384) X(432) X(448) X(480) X(512) X(576) X(640) X(720) X(768) X(864) X(896) X(960) X(1024) X(1152) X(1280) \
+    X(1344) X(1440) X(1536) X(1728) X(1792) X(1920) X(2048) X(2304) X(2560) X(2880) X(3072) X(3456) X(3840) \
+    X(4096) X(4608) X(5120) X(5760) X(6144) X(6912) X(7680) X(8192)
 
 namespace nvp {
 
@@ -115,9 +117,9 @@ hipError_t launch_zconv_multi_c64(int L, const ZconvTaskArgs *tasks_dev, int nta
 hipError_t launch_zconv_multi_c128(int L, const ZconvTaskArgs *tasks_dev, int ntasks, int64_t blocks, const void *tw,
                                    hipStream_t s);
 // Launch geometry of the default variants: columns per strided workgroup and
-// pencil quads per z-pass workgroup.
+// pencils per z-pass workgroup.
 int strided_tile_cols(int L, int dbl);
-int zconv_quads_per_block(int L, int dbl);
+int zconv_slots_per_block(int L, int dbl);
 
 // The kernel by squared integer distance: ktab[q], q < n (see k_kradial);
 // (face_re, face_im) is added to the entry q = 1 (zero for the paper's rule).

@@ -11,20 +11,27 @@ template <typename R> constexpr int strided_cols(int L) {
     const int lo = sizeof(R) == 4 ? 16 : 8, hi = sizeof(R) == 4 ? 64 : 32;
     const int t = 256 / plan_threads(L);
     int c = t < lo ? lo : (t > hi ? hi : t);
-    // the workgroup's columns must fit the 160 KiB of LDS
-    while (c > 1 && (size_t)c * L * sizeof(cx<R>) > 163840) c /= 2;
+    // the workgroup's columns must fit the 160 KiB of LDS and 1024 threads
+    while (c > 1 && ((size_t)c * L * sizeof(cx<R>) > 163840 || c * plan_threads(L) > 1024)) c /= 2;
     return c;
 }
 
+// Whether the contiguous FP64 kernel stages its twiddle table in LDS: when
+// the table and one pencil fit 128 KiB.
+template <typename R> constexpr bool contig_tw_lds(int L) {
+    return (size_t)(twiddle_table_len(L) + slot_len<R>(L)) * sizeof(cx<R>) <= 131072;
+}
+
 // Pencils per workgroup of the contiguous FP64 kernel: about 256 threads,
-// LDS <= 128 KiB, and whole wavefronts (a multiple of 64 / P pencils).
+// LDS <= 128 KiB (with the staged twiddles), and whole wavefronts (a multiple
+// of 64 / P pencils where a pencil is wave-local).
 template <typename R> constexpr int contig_pencils(int L) {
     const int P = plan_threads(L);
     const int by_threads = 256 / P > 0 ? 256 / P : 1;
-    const int by_lds = (int)((131072 - twiddle_table_len(L) * (int)sizeof(cx<R>)) /
-                             (slot_len<R>(L) * (int)sizeof(cx<R>)));
+    const int tw = contig_tw_lds<R>(L) ? twiddle_table_len(L) * (int)sizeof(cx<R>) : 0;
+    const int by_lds = (int)((131072 - tw) / (slot_len<R>(L) * (int)sizeof(cx<R>)));
     int p = by_threads < by_lds ? by_threads : by_lds;
-    const int unit = P < 64 ? 64 / P : 1;
+    const int unit = plan_wave_local(L) ? 64 / P : 1;
     p = (p / unit) * unit;
     return p > 0 ? p : unit;
 }
@@ -138,42 +145,58 @@ template <typename R, int L> hipError_t xsrc_impl(const SourceArgs &a, const voi
     return hipErrorInvalidValue;
 }
 
-template <typename R, int L, int QW>
-hipError_t zconv_qw(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, hipStream_t s) {
-    auto kern = k_zconv<R, L, QW>;
-    constexpr size_t lds = (size_t)4 * QW * slot_len<R>(L) * sizeof(cx<R>);
+template <typename R, int L, int SLOTS>
+hipError_t zconv_slots(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, hipStream_t s) {
+    auto kern = k_zconv<R, L, SLOTS>;
+    constexpr size_t lds = (size_t)SLOTS * slot_len<R>(L) * sizeof(cx<R>);
+    static_assert(lds <= 163840 && SLOTS * plan_threads(L) <= 1024, "z-pass workgroup too large");
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
     const int64_t Hx = Mx / 2 + 1, Hy = My / 2 + 1, nq = Hx * Hy;
-    if (nq > 0x7fffffff - QW) return hipErrorInvalidValue;  // quad indices are 32-bit in the kernel
-    hipLaunchKernelGGL(kern, dim3((unsigned)((nq + QW - 1) / QW)), dim3(4 * QW * plan_threads(L)), lds, s,
+    if (4 * nq > 0x7fffffff - SLOTS) return hipErrorInvalidValue;  // pencil indices are 32-bit in the kernel
+    hipLaunchKernelGGL(kern, dim3((unsigned)((4 * nq + SLOTS - 1) / SLOTS)), dim3(SLOTS * plan_threads(L)), lds, s,
                        static_cast<cx<R> *>(buf), static_cast<const cx<R> *>(khat), Mx, My, Nz, Hy, nq,
                        static_cast<const cx<R> *>(tw));
     return hipGetLastError();
 }
 
-// Pencil quads per z-pass workgroup by default: up to 256 threads and 80 KiB of LDS.
-template <typename R, int L> constexpr int zconv_default_qw() {
-    return (4 * plan_threads(L) <= 128 && 8 * slot_len<R>(L) * (int)sizeof(cx<R>) <= 81920) ? 2 : 1;
+// Pencils per z-pass workgroup that fit: `slots` pencils of slot_len entries
+// of esz bytes within `lds_cap` bytes and `thr_cap` threads.
+constexpr bool zconv_fits(int L, size_t esz, int slots, size_t lds_cap, int thr_cap) {
+    const size_t slot = (size_t)(esz == sizeof(float2) ? slot_len<float>(L) : slot_len<double>(L)) * esz;
+    return (size_t)slots * slot <= lds_cap && slots * plan_threads(L) <= thr_cap;
 }
 
-// quads: pencil quads per workgroup, 0 for the default (2 when that keeps the
-// workgroup within 256 threads and 80 KiB of LDS, else 1), or 1 / 2 forced
-// (2 falls back to 1 where it does not fit).
+// Pencils per z-pass workgroup by default: two quads (8) when that keeps the
+// workgroup within 128 threads and 80 KiB of LDS, else one quad (4);
+// transforms too long for a quad in 160 KiB take 2 or 1.
+constexpr int zconv_slots_for(int L, size_t esz) {
+    return 4 * plan_threads(L) <= 128 && zconv_fits(L, esz, 8, 81920, 1024) ? 8
+         : zconv_fits(L, esz, 4, 163840, 1024) ? 4
+         : zconv_fits(L, esz, 2, 163840, 1024) ? 2 : 1;
+}
+template <typename R, int L> constexpr int zconv_default_slots() { return zconv_slots_for(L, sizeof(cx<R>)); }
+
+// quads: pencil quads per workgroup, 0 for the default, or 1 / 2 forced
+// (where a whole quad fits; otherwise the default).
 template <typename R, int L>
 hipError_t zconv_impl(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, int quads,
                       hipStream_t s) {
-    constexpr int QW = zconv_default_qw<R, L>();
-    if (quads == 1 || zconv_quads_override() == 1) return zconv_qw<R, L, 1>(buf, khat, Mx, My, Nz, tw, s);
-    return zconv_qw<R, L, QW>(buf, khat, Mx, My, Nz, tw, s);
+    constexpr int SD = zconv_default_slots<R, L>();
+    if constexpr (SD >= 4) {
+        if (quads == 1 || zconv_quads_override() == 1) return zconv_slots<R, L, 4>(buf, khat, Mx, My, Nz, tw, s);
+    }
+    return zconv_slots<R, L, SD>(buf, khat, Mx, My, Nz, tw, s);
 }
 
 template <int L>
 hipError_t kz_impl(double2 *out, const int64_t H[3], const int64_t N[3], const double2 *ktab, const void *tw,
                    hipStream_t s) {
     constexpr int PW = contig_pencils<double>(L);
-    auto kern = k_kz<L, PW>;
-    constexpr size_t lds = ((size_t)PW * slot_len<double>(L) + plan_tw_len(L, false)) * sizeof(double2);
+    constexpr bool TWL = contig_tw_lds<double>(L);
+    auto kern = k_kz<L, PW, TWL>;
+    constexpr size_t lds = ((size_t)PW * slot_len<double>(L) + (TWL ? plan_tw_len(L, false) : 0)) * sizeof(double2);
+    static_assert(lds <= 163840 && PW * plan_threads(L) <= 1024, "kernel-spectrum workgroup too large");
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
     const int64_t rows = H[0] * H[1];
@@ -207,12 +230,12 @@ hipError_t strided_multi_impl(const StridedTaskArgs *tasks, int ntasks, int64_t 
 template <typename R, int L>
 hipError_t zconv_multi_impl(const ZconvTaskArgs *tasks, int ntasks, int64_t blocks, const void *tw, hipStream_t s) {
     if (ntasks < 1 || blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
-    constexpr int QW = zconv_default_qw<R, L>();
-    auto kern = k_zconv_multi<R, L, QW>;
-    constexpr size_t lds = (size_t)4 * QW * slot_len<R>(L) * sizeof(cx<R>);
+    constexpr int SLOTS = zconv_default_slots<R, L>();
+    auto kern = k_zconv_multi<R, L, SLOTS>;
+    constexpr size_t lds = (size_t)SLOTS * slot_len<R>(L) * sizeof(cx<R>);
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(4 * QW * plan_threads(L)), lds, s, tasks, ntasks,
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(SLOTS * plan_threads(L)), lds, s, tasks, ntasks,
                        static_cast<const cx<R> *>(tw));
     return hipGetLastError();
 }

@@ -22,6 +22,11 @@
 #include "fft_core.hpp"
 #include "launch.hpp"
 
+namespace nvp {
+hipError_t launch_box_mask(const void *f, void *out, bool dbl, const int64_t n[3], const int64_t box[6],
+                           hipStream_t s);
+}  // namespace nvp
+
 using nvp::FieldArgs;
 using nvp::SourceArgs;
 using nvp::StridedArgs;
@@ -52,7 +57,8 @@ struct nvp_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
-    std::vector<Twiddle> tw;
+    std::vector<Twiddle> tw;  // tables of every compiled length, inside tw_blob
+    void *tw_blob = nullptr;
     VpCache vp;
     size_t max_lds = 0;
     int quad = NVP_QUAD_BALL;  // quadrature rule of plans and potentials created from now on
@@ -195,15 +201,12 @@ int64_t circulant_len(int64_t n) {
 // Per-stage twiddle tables of length L: for the radix plan run forward and
 // then in reverse order, stage s >= 1 (radix r, Ns = product of the earlier
 // radices) holds exp(-2 pi i j q / (Ns r)) at [j][q-1], j < Ns, 1 <= q < r;
-// computed in extended precision and rounded once.
-nvp_status twiddles(nvp_ctx *ctx, int L, bool dbl, const void **out) {
-    for (auto &t : ctx->tw)
-        if (t.L == L && t.dbl == (int)dbl) {
-            *out = t.dev;
-            return NVP_OK;
-        }
+// computed in extended precision and rounded once.  The tables of every
+// compiled length, in both precisions, are made once per context, in one
+// device allocation at nvp_ctx_create, so that no later call allocates them.
+void twiddle_values(int L, std::vector<double> &hd) {
     const int n = nvp::twiddle_table_len(L);
-    std::vector<double> hd(2 * (size_t)(n > 0 ? n : 1));
+    hd.assign(2 * (size_t)(n > 0 ? n : 1), 0.0);
     size_t e = 0;
     for (int rev = 0; rev < 2; ++rev) {
         const int S = nvp::plan_for(L).S;
@@ -218,25 +221,47 @@ nvp_status twiddles(nvp_ctx *ctx, int L, bool dbl, const void **out) {
                 }
         }
     }
-    const size_t cnt = hd.size() / 2;
+}
+
+nvp_status make_twiddles(nvp_ctx *ctx) {
+    std::vector<unsigned char> blob;
+    std::vector<std::pair<size_t, std::pair<int, int>>> at;  // offset, (L, dbl)
+    std::vector<double> hd;
+    for (int L : kLengths) {
+        twiddle_values(L, hd);
+        for (int dbl = 0; dbl < 2; ++dbl) {
+            const size_t off = (blob.size() + 255) / 256 * 256;
+            const size_t bytes = hd.size() / 2 * (dbl ? 16 : 8);
+            blob.resize(off + bytes);
+            if (dbl) {
+                std::memcpy(blob.data() + off, hd.data(), bytes);
+            } else {
+                float *f = reinterpret_cast<float *>(blob.data() + off);
+                for (size_t i = 0; i < hd.size(); ++i) f[i] = (float)hd[i];
+            }
+            at.push_back({off, {L, dbl}});
+        }
+    }
     void *dev = nullptr;
-    const size_t bytes = cnt * (dbl ? 16 : 8);
-    NVP_HIP(ctx, dev_malloc((void **)&dev, bytes));
-    hipError_t err;
-    if (dbl) {
-        err = hipMemcpy(dev, hd.data(), bytes, hipMemcpyHostToDevice);
-    } else {
-        std::vector<float> hf(hd.size());
-        for (size_t i = 0; i < hf.size(); ++i) hf[i] = (float)hd[i];
-        err = hipMemcpy(dev, hf.data(), bytes, hipMemcpyHostToDevice);
-    }
-    if (err != hipSuccess) {
+    hipError_t e = dev_malloc(&dev, blob.size());
+    if (e != hipSuccess) return hip_fail(ctx, "twiddle tables", e);
+    e = hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
         (void)hipFree(dev);
-        return hip_fail(ctx, "twiddle upload", err);
+        return hip_fail(ctx, "twiddle upload", e);
     }
-    ctx->tw.push_back({L, (int)dbl, dev});
-    *out = dev;
+    ctx->tw_blob = dev;
+    for (auto &a : at) ctx->tw.push_back({a.second.first, a.second.second, static_cast<unsigned char *>(dev) + a.first});
     return NVP_OK;
+}
+
+nvp_status twiddles(nvp_ctx *ctx, int L, bool dbl, const void **out) {
+    for (auto &t : ctx->tw)
+        if (t.L == L && t.dbl == (int)dbl) {
+            *out = t.dev;
+            return NVP_OK;
+        }
+    return fail(ctx, NVP_E_UNSUPPORTED, "no compiled transform of length " + std::to_string(L));
 }
 
 void self_cell(double kr, double ki, double h, double *re, double *im) {
@@ -289,7 +314,10 @@ nvp_status check_grid_lengths(nvp_ctx *ctx, const nvp_grid *g, int64_t M[3]) {
         M[a] = circulant_len(g->n[a]);
         if (M[a] < 0)
             return fail(ctx, NVP_E_UNSUPPORTED,
-                        "axis of " + std::to_string(g->n[a]) + " voxels exceeds the largest compiled circulant length");
+                        "axis of " + std::to_string(g->n[a]) + " voxels: the longest transform is " +
+                            std::to_string(kLengths[sizeof kLengths / sizeof kLengths[0] - 1]) +
+                            ", so axes are limited to " +
+                            std::to_string((kLengths[sizeof kLengths / sizeof kLengths[0] - 1] + 1) / 2) + " voxels");
     }
     return NVP_OK;
 }
@@ -470,6 +498,43 @@ bool same_grid(const nvp_grid &a, const nvp_grid &b) {
            std::memcmp(a.n, b.n, sizeof a.n) == 0;
 }
 
+// The context's volume-potential buffers and kernel spectrum for (rule, k, g,
+// prec): kept from the last call when they match, else made again.
+nvp_status vp_prepare(nvp_ctx *ctx, double k_re, double k_im, const nvp_grid *g, const int64_t M[3], nvp_prec prec) {
+    VpCache &c = ctx->vp;
+    const bool hit = c.valid && c.quad == ctx->quad && c.kr == k_re && c.ki == k_im && c.prec == (int)prec &&
+                     same_grid(c.g, *g);
+    if (hit) return NVP_OK;
+    NVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (c.khat) (void)hipFree(c.khat);
+    if (c.A) (void)hipFree(c.A);
+    if (c.B) (void)hipFree(c.B);
+    c = VpCache{};
+    hipError_t e1 = dev_malloc((void **)&c.khat, khat_bytes(M, prec));
+    hipError_t e2 = dev_malloc((void **)&c.A, bytesA(g, M, prec));
+    hipError_t e3 = dev_malloc((void **)&c.B, bytesB(g, M, prec));
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        if (c.khat) (void)hipFree(c.khat);
+        if (c.A) (void)hipFree(c.A);
+        if (c.B) (void)hipFree(c.B);
+        c = VpCache{};
+        return fail(ctx, NVP_E_NOMEM, "volume potential: device allocation failed");
+    }
+    nvp_status st = kernel_spectrum(ctx, nullptr, ctx->quad, k_re, k_im, g, M, prec, c.khat, c.B, c.A);
+    if (st) {
+        c.valid = false;
+        return st;
+    }
+    c.valid = true;
+    c.quad = ctx->quad;
+    c.kr = k_re;
+    c.ki = k_im;
+    c.g = *g;
+    c.prec = (int)prec;
+    std::memcpy(c.M, M, sizeof M);
+    return NVP_OK;
+}
+
 // 1-D interpolation of a source axis at the target centres (clamped into the
 // source hull): order 1 linear, order 3 four-point Lagrange with the stencil
 // shifted inward at the edges.
@@ -635,6 +700,13 @@ nvp_status nvp_ctx_create(int device, void *hip_stream, nvp_ctx **out) {
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->max_lds = prop.sharedMemPerBlock;
+    nvp_status st = make_twiddles(c);
+    if (st) {
+        g_create_err_buf = c->err;
+        g_create_err = g_create_err_buf.c_str();
+        delete c;
+        return st;
+    }
     *out = c;
     return NVP_OK;
 }
@@ -659,7 +731,7 @@ nvp_status nvp_ctx_destroy(nvp_ctx *ctx) {
     if (!ctx) return NVP_E_INVALID;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    for (auto &t : ctx->tw) (void)hipFree(t.dev);
+    if (ctx->tw_blob) (void)hipFree(ctx->tw_blob);
     if (ctx->vp.khat) (void)hipFree(ctx->vp.khat);
     if (ctx->vp.A) (void)hipFree(ctx->vp.A);
     if (ctx->vp.B) (void)hipFree(ctx->vp.B);
@@ -755,6 +827,14 @@ nvp_status nvp_circulant_size(int64_t n, int64_t *m) {
     return *m < 0 ? NVP_E_UNSUPPORTED : NVP_OK;
 }
 
+nvp_status nvp_transform_lengths(int32_t *lengths, int capacity, int *count) {
+    if (!count || capacity < 0 || (capacity > 0 && !lengths)) return NVP_E_INVALID;
+    const int n = (int)(sizeof kLengths / sizeof kLengths[0]);
+    *count = n;
+    for (int i = 0; i < n && i < capacity; ++i) lengths[i] = kLengths[i];
+    return NVP_OK;
+}
+
 nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nvp_grid *g, const void *f_dev,
                                 void *u_dev, nvp_prec prec) {
     if (!ctx) return NVP_E_INVALID;
@@ -765,36 +845,37 @@ nvp_status nvp_volume_potential(nvp_ctx *ctx, double k_re, double k_im, const nv
     int64_t M[3];
     nvp_status st = check_grid_lengths(ctx, g, M);
     if (st) return st;
-    VpCache &c = ctx->vp;
-    const bool hit = c.valid && c.quad == ctx->quad && c.kr == k_re && c.ki == k_im && c.prec == (int)prec &&
-                     same_grid(c.g, *g);
-    if (!hit) {
-        NVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        if (c.khat) (void)hipFree(c.khat);
-        if (c.A) (void)hipFree(c.A);
-        if (c.B) (void)hipFree(c.B);
-        c = VpCache{};
-        hipError_t e1 = dev_malloc((void **)&c.khat, khat_bytes(M, prec));
-        hipError_t e2 = dev_malloc((void **)&c.A, bytesA(g, M, prec));
-        hipError_t e3 = dev_malloc((void **)&c.B, bytesB(g, M, prec));
-        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-            if (c.khat) (void)hipFree(c.khat);
-            if (c.A) (void)hipFree(c.A);
-            if (c.B) (void)hipFree(c.B);
-            c = VpCache{};
-            return fail(ctx, NVP_E_NOMEM, "nvp_volume_potential: device allocation failed");
-        }
-        if ((st = kernel_spectrum(ctx, nullptr, ctx->quad, k_re, k_im, g, M, prec, c.khat, c.B, c.A))) return st;
-        c.valid = true;
-        c.quad = ctx->quad;
-        c.kr = k_re;
-        c.ki = k_im;
-        c.g = *g;
-        c.prec = (int)prec;
-        std::memcpy(c.M, M, sizeof M);
-    }
+    if ((st = vp_prepare(ctx, k_re, k_im, g, M, prec))) return st;
     const double scale = -1.0 / ((double)M[0] * (double)M[1] * (double)M[2]);
-    return convolve(ctx, nullptr, prec, g, M, c.khat, c.A, c.B, f_dev, nullptr, u_dev, scale);
+    return convolve(ctx, nullptr, prec, g, M, ctx->vp.khat, ctx->vp.A, ctx->vp.B, f_dev, nullptr, u_dev, scale);
+}
+
+nvp_status nvp_volume_potential_box(nvp_ctx *ctx, double k_re, double k_im, const nvp_grid *g, const void *f_dev,
+                                    const int64_t *box, double scale, void *u_dev, nvp_prec prec) {
+    if (!ctx) return NVP_E_INVALID;
+    if (!grid_ok(g) || !f_dev || !u_dev || f_dev == u_dev || (prec != NVP_C64 && prec != NVP_C128) ||
+        !std::isfinite(k_re) || !std::isfinite(k_im) || k_im < 0 || (k_re == 0 && k_im == 0) ||
+        !std::isfinite(scale))
+        return fail(ctx, NVP_E_INVALID, "nvp_volume_potential_box: bad argument");
+    if (box)
+        for (int a = 0; a < 3; ++a)
+            if (box[a] < 0 || box[a] > box[a + 3] || box[a + 3] >= g->n[a])
+                return fail(ctx, NVP_E_INVALID, "nvp_volume_potential_box: box outside the grid or empty");
+    NVP_HIP(ctx, hipSetDevice(ctx->device));
+    int64_t M[3];
+    nvp_status st = check_grid_lengths(ctx, g, M);
+    if (st) return st;
+    if ((st = vp_prepare(ctx, k_re, k_im, g, M, prec))) return st;
+    VpCache &c = ctx->vp;
+    const void *f = f_dev;
+    if (box) {
+        // the source restricted to the box, in the first Nx rows of the x-pass buffer (the x pass
+        // then runs in place there; the kernel spectrum no longer needs that buffer)
+        NVP_HIP(ctx, nvp::launch_box_mask(f_dev, c.A, prec == NVP_C128, g->n, box, ctx->stream));
+        f = c.A;
+    }
+    const double sc = scale / ((double)M[0] * (double)M[1] * (double)M[2]);
+    return convolve(ctx, nullptr, prec, g, M, c.khat, c.A, c.B, f, nullptr, u_dev, sc);
 }
 
 nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int n_harm, const nvp_grid *g1,
@@ -1451,7 +1532,7 @@ nvp_status build_grouped(nvp_batch *b, const void *const *p1, void *const *pn, s
                 g.ntasks = (int)kv.second.size();
                 if (pass == P_ZCONV) {
                     g.kind = 2;
-                    const int qw = nvp::zconv_quads_per_block(L, dbl);
+                    const int slots = nvp::zconv_slots_per_block(L, dbl);
                     std::vector<nvp::ZconvTaskArgs> t;
                     for (int i : kv.second) {
                         nvp_plan *p = b->plans[i];
@@ -1465,7 +1546,7 @@ nvp_status build_grouped(nvp_batch *b, const void *const *p1, void *const *pn, s
                         a.n_quads = (h.M[0] / 2 + 1) * a.Hy;
                         a.Nz = (int)h.g.n[2];
                         a.first = g.blocks;
-                        g.blocks += (a.n_quads + qw - 1) / qw;
+                        g.blocks += (4 * a.n_quads + slots - 1) / slots;
                         t.push_back(a);
                     }
                     g.offset = push(t.data(), t.size() * sizeof(t[0]));

@@ -84,6 +84,43 @@ __global__ void __launch_bounds__(kBlock) k_dot(const V *__restrict__ a, const V
     if (threadIdx.x == 0) part[blockIdx.x] = make_double2(sr[0], si[0]);
 }
 
+// out = f inside the voxel box [lo, hi] (inclusive, per axis), 0 outside;
+// grid (ceil(Nz / kBlock), Ny, Nx).
+template <typename V>
+__global__ void __launch_bounds__(kBlock) k_box_mask(const V *__restrict__ f, V *__restrict__ out, int64_t Ny,
+                                                     int64_t Nz, int64_t lx, int64_t ly, int64_t lz, int64_t hx,
+                                                     int64_t hy, int64_t hz) {
+    const int64_t iz = (int64_t)blockIdx.x * kBlock + threadIdx.x, iy = blockIdx.y, ix = blockIdx.z;
+    if (iz >= Nz) return;
+    const int64_t i = (ix * Ny + iy) * Nz + iz;
+    const bool in = ix >= lx && ix <= hx && iy >= ly && iy <= hy && iz >= lz && iz <= hz;
+    out[i] = in ? f[i] : mk<V>(0.0, 0.0);
+}
+
+// Partial sums of |a - b|^2 and |a|^2 in FP64, one pair per workgroup.
+template <typename V>
+__global__ void __launch_bounds__(kBlock) k_diff_norms(const V *__restrict__ a, const V *__restrict__ b, int64_t n,
+                                                       double2 *__restrict__ part) {
+    __shared__ double sd[kBlock], sa[kBlock];
+    double d = 0.0, q = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const double ax = a[i].x, ay = a[i].y, dx = ax - (double)b[i].x, dy = ay - (double)b[i].y;
+        d += dx * dx + dy * dy;
+        q += ax * ax + ay * ay;
+    }
+    sd[threadIdx.x] = d;
+    sa[threadIdx.x] = q;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sd[threadIdx.x] += sd[threadIdx.x + w];
+            sa[threadIdx.x] += sa[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(sd[0], sa[0]);
+}
+
 using cd = std::complex<double>;
 
 struct DevMem {
@@ -222,4 +259,76 @@ extern "C" nvp_status nvp_vie_solve(nvp_ctx *ctx, double kb_re, double kb_im, co
     return prec == NVP_C128
                ? bicgstab<double2>(ctx, kb_re, kb_im, g, prec, q_dev, rhs_dev, p_dev, tol, max_iter, iters, relres)
                : bicgstab<float2>(ctx, kb_re, kb_im, g, prec, q_dev, rhs_dev, p_dev, tol, max_iter, iters, relres);
+}
+
+namespace nvp {
+
+// Copies f ([Nx][Ny][Nz]) to out with every voxel outside the inclusive box
+// lo..hi set to zero (the volume potential of a source restricted to a box).
+hipError_t launch_box_mask(const void *f, void *out, bool dbl, const int64_t n[3], const int64_t box[6],
+                           hipStream_t s) {
+    const dim3 grid((unsigned)((n[2] + kBlock - 1) / kBlock), (unsigned)n[1], (unsigned)n[0]);
+    if (dbl)
+        hipLaunchKernelGGL(k_box_mask<double2>, grid, dim3(kBlock), 0, s, static_cast<const double2 *>(f),
+                           static_cast<double2 *>(out), n[1], n[2], box[0], box[1], box[2], box[3], box[4], box[5]);
+    else
+        hipLaunchKernelGGL(k_box_mask<float2>, grid, dim3(kBlock), 0, s, static_cast<const float2 *>(f),
+                           static_cast<float2 *>(out), n[1], n[2], box[0], box[1], box[2], box[3], box[4], box[5]);
+    return hipGetLastError();
+}
+
+}  // namespace nvp
+
+extern "C" nvp_status nvp_field_lin3(nvp_ctx *ctx, int64_t n, void *out_dev, const void *a_dev, const void *b_dev,
+                                     const void *c_dev, const double al[2], const double be[2], nvp_prec prec) {
+    if (!ctx) return NVP_E_INVALID;
+    if (n < 0 || !out_dev || !al || !be || (prec != NVP_C64 && prec != NVP_C128) || !std::isfinite(al[0]) ||
+        !std::isfinite(al[1]) || !std::isfinite(be[0]) || !std::isfinite(be[1]))
+        return nvp::ctx_fail(ctx, NVP_E_INVALID, "nvp_field_lin3: bad argument");
+    if (n == 0) return NVP_OK;
+    hipError_t e = hipSetDevice(nvp::ctx_device(ctx));
+    if (e != hipSuccess) return nvp::ctx_hip_fail(ctx, "hipSetDevice", e);
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
+    const double2 A = make_double2(al[0], al[1]), B = make_double2(be[0], be[1]);
+    hipStream_t s = nvp::ctx_stream(ctx);
+    if (prec == NVP_C128)
+        hipLaunchKernelGGL(k_lin3<double2>, grid, dim3(kBlock), 0, s, static_cast<double2 *>(out_dev),
+                           static_cast<const double2 *>(a_dev), static_cast<const double2 *>(b_dev),
+                           static_cast<const double2 *>(c_dev), A, B, n);
+    else
+        hipLaunchKernelGGL(k_lin3<float2>, grid, dim3(kBlock), 0, s, static_cast<float2 *>(out_dev),
+                           static_cast<const float2 *>(a_dev), static_cast<const float2 *>(b_dev),
+                           static_cast<const float2 *>(c_dev), A, B, n);
+    e = hipGetLastError();
+    return e == hipSuccess ? NVP_OK : nvp::ctx_hip_fail(ctx, "k_lin3", e);
+}
+
+extern "C" nvp_status nvp_field_diff_norms(nvp_ctx *ctx, int64_t n, const void *a_dev, const void *b_dev,
+                                           nvp_prec prec, double out[2]) {
+    if (!ctx) return NVP_E_INVALID;
+    if (n < 0 || !a_dev || !b_dev || !out || (prec != NVP_C64 && prec != NVP_C128))
+        return nvp::ctx_fail(ctx, NVP_E_INVALID, "nvp_field_diff_norms: bad argument");
+    out[0] = out[1] = 0.0;
+    if (n == 0) return NVP_OK;
+    hipError_t e = hipSetDevice(nvp::ctx_device(ctx));
+    if (e != hipSuccess) return nvp::ctx_hip_fail(ctx, "hipSetDevice", e);
+    hipStream_t s = nvp::ctx_stream(ctx);
+    const unsigned nb = (unsigned)std::min<int64_t>(kDotBlocks, (n + kBlock - 1) / kBlock);
+    DevMem part;
+    e = hipMalloc(&part.p, nb * sizeof(double2));
+    if (e != hipSuccess) return nvp::ctx_hip_fail(ctx, "nvp_field_diff_norms: partial sums", e);
+    if (prec == NVP_C128)
+        hipLaunchKernelGGL(k_diff_norms<double2>, dim3(nb), dim3(kBlock), 0, s, static_cast<const double2 *>(a_dev),
+                           static_cast<const double2 *>(b_dev), n, static_cast<double2 *>(part.p));
+    else
+        hipLaunchKernelGGL(k_diff_norms<float2>, dim3(nb), dim3(kBlock), 0, s, static_cast<const float2 *>(a_dev),
+                           static_cast<const float2 *>(b_dev), n, static_cast<double2 *>(part.p));
+    e = hipGetLastError();
+    if (e != hipSuccess) return nvp::ctx_hip_fail(ctx, "k_diff_norms", e);
+    std::vector<double2> h(nb);
+    e = hipMemcpyAsync(h.data(), part.p, nb * sizeof(double2), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return nvp::ctx_hip_fail(ctx, "nvp_field_diff_norms: result", e);
+    for (const double2 &v : h) out[0] += v.x, out[1] += v.y;
+    return NVP_OK;
 }

@@ -15,8 +15,9 @@ are transferred onto p_n's grid as in Section 6; a higher harmonic is zero
 outside its own box (zero outside the hull of its voxel centres).
 
 The library does the numerics: S_n by the plan's source build, D_n by
-nvp_difference_term, the convolution by nvp_volume_potential.  This module
-orders the sweeps and scales the results (-C_n u, plus p_inc for n = 1).
+nvp_difference_term, C_n times the convolution by nvp_volume_potential_box,
+p_inc added by nvp_field_lin3 and the change of each harmonic by
+nvp_field_diff_norms.  This module only orders the calls.
 """
 
 import torch
@@ -49,12 +50,13 @@ def full_cascade(ctx, med, f0, g1, grids, p_inc, order=1, tol=1e-6, max_sweeps=3
                 for m in range(n + 1, N + 1):
                     nvp.difference_term(ctx, gn, f, g[m - 1], p[m - 1], True, g[m - n - 1], p[m - n - 1],
                                         m - n > n, order, 2.0)
-                u = nvp.volume_potential(ctx, nvp.wavenumber(med, f0, n), gn, f)
-                new = u * (-nvp.cascade_constant(med, f0, n))
+                new = nvp.volume_potential_box(ctx, nvp.wavenumber(med, f0, n), gn, f, None,
+                                               nvp.cascade_constant(med, f0, n))
+                del f
                 if n == 1:
-                    new += p_inc
-                d = float(torch.linalg.vector_norm(new - p[n - 1]) / torch.linalg.vector_norm(new))
-                change = max(change, d)
+                    nvp.field_lin3(ctx, new, new, p_inc, None, 1.0, 0.0)
+                dd, nn = nvp.field_diff_norms(ctx, new, p[n - 1])
+                change = max(change, (dd / nn) ** 0.5 if nn > 0 else 0.0)
                 p[n - 1] = new
             if log:
                 log("sweep %d: largest relative change %.2e" % (sweeps, change))

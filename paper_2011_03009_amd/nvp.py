@@ -125,6 +125,16 @@ def circulant_size(n):
     return m.value
 
 
+def transform_lengths():
+    """The compiled transform lengths (circulant sizes per axis), increasing."""
+    L = _native.lib()
+    n = ctypes.c_int()
+    _check(L.nvp_transform_lengths(None, 0, ctypes.byref(n)))
+    buf = (ctypes.c_int32 * n.value)()
+    _check(L.nvp_transform_lengths(buf, n.value, ctypes.byref(n)))
+    return [int(v) for v in buf]
+
+
 # ------------------------------------------------------------- context
 
 def _ptr(t):
@@ -279,6 +289,47 @@ def volume_potential(ctx, k, g, f, out=None):
     _check(_native.lib().nvp_volume_potential(ctx.handle, k.real, k.imag, ctypes.byref(g), _ptr(f), _ptr(out), prec),
            ctx.handle)
     return out
+
+
+def volume_potential_box(ctx, k, g, f, box, scale, out=None):
+    """u = scale * sum_{j in box} K(x_i - x_j) f_j on all of grid g; box: 6 inclusive voxel indices
+    (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z) or None for the whole grid.  scale = C_n gives p_n."""
+    g = grid(g)
+    n = tuple(g.n)
+    prec = prec_of(f.dtype)
+    _need(f, f.dtype, n[0] * n[1] * n[2], "f")
+    if out is None:
+        out = torch.empty(n, dtype=f.dtype, device=f.device)
+    _need(out, f.dtype, n[0] * n[1] * n[2], "out")
+    k = complex(k)
+    b = None if box is None else (ctypes.c_int64 * 6)(*[int(v) for v in box])
+    _check(_native.lib().nvp_volume_potential_box(ctx.handle, k.real, k.imag, ctypes.byref(g), _ptr(f), b,
+                                                  float(scale), _ptr(out), prec), ctx.handle)
+    return out
+
+
+def field_lin3(ctx, out, a=None, b=None, c=None, al=0.0, be=0.0):
+    """out = a + al b + be c on device tensors of one complex dtype (None operands count as zero)."""
+    prec = prec_of(out.dtype)
+    n = out.numel()
+    for t, w in ((a, "a"), (b, "b"), (c, "c")):
+        if t is not None:
+            _need(t, out.dtype, n, w)
+    al, be = complex(al), complex(be)
+    A = (ctypes.c_double * 2)(al.real, al.imag)
+    B = (ctypes.c_double * 2)(be.real, be.imag)
+    p = lambda t: None if t is None else _ptr(t)  # noqa: E731
+    _check(_native.lib().nvp_field_lin3(ctx.handle, n, _ptr(out), p(a), p(b), p(c), A, B, prec), ctx.handle)
+    return out
+
+
+def field_diff_norms(ctx, a, b):
+    """(sum |a - b|^2, sum |a|^2) in FP64 for device tensors of one complex dtype."""
+    prec = prec_of(a.dtype)
+    _need(b, a.dtype, a.numel(), "b")
+    out = (ctypes.c_double * 2)()
+    _check(_native.lib().nvp_field_diff_norms(ctx.handle, a.numel(), _ptr(a), _ptr(b), prec, out), ctx.handle)
+    return float(out[0]), float(out[1])
 
 
 class CascadePlan:

@@ -5,7 +5,7 @@
 Training transducers are drawn from the batched workload's ranges with one
 seed, the held-out ones with another; p_1 is the Rayleigh integral of a
 seeded equal-area point set on each bowl (synthetic stand-ins for measured
-transducers).  Writes dataset.npz, boxnet_window.npy/.json (the trained network) and summary.json to --out.
+transducers), summed on the GPU by the library's incident-field kernel.  Writes dataset.npz, boxnet_window.npy/.json (the trained network) and summary.json to --out.
 """
 
 import argparse
@@ -28,13 +28,13 @@ from workload import bowl, configs, learn as WL  # noqa: E402
 MED = configs.WATER
 
 
-def make_incident(n_points=4096, seed=0):
+def make_incident(ctx, n_points=4096, seed=0):
+    """p_1 of a transducer on a grid: the library's monopole sum (nvp_incident_field) over a seeded
+    equal-area point set on the bowl, scaled to the Rayleigh integral of surface pressure p0."""
     def incident(T, g):
         k1 = nvp.wavenumber(MED, T.f0, 1)
-        pts = bowl.bowl_points(T.R, T.l, n_points, seed)
-        ax = [g.origin[a] + g.h * np.arange(int(g.n[a]), dtype=np.float64) for a in range(3)]
-        p = bowl.incident_field(pts, T.R, T.l, k1, T.p0, ax[0], ax[1], ax[2], device="cuda", chunk=8192)
-        return p.to(torch.complex64).contiguous()
+        pts = torch.from_numpy(bowl.bowl_points(T.R, T.l, n_points, seed)).to("cuda")
+        return nvp.incident_field(ctx, k1, bowl.rayleigh_scale(T.R, T.l, k1, T.p0, n_points), pts, g)
     return incident
 
 
@@ -60,8 +60,8 @@ def main():
     ap.add_argument("--out", default="boxnet_out")
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
-    inc = make_incident()
     with nvp.Context(0) as ctx:
+        inc = make_incident(ctx)
         t0 = time.time()
         recs = []
         for i, T in enumerate(transducers(a.transducers, a.seed)):

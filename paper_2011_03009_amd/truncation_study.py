@@ -1,24 +1,35 @@
 """The truncation-convergence study of Section 5 at the paper's scale.
 
-For one transducer and medium, every harmonic p_2..p_n is first computed on
-the reference domain (equation "domain": [l - L, l + d] x [-R, R]^2, each
-harmonic at its own lambda_n / 6); these are the reference solutions p_n^r.
-Then, for each harmonic, the source f_n (built from the reference lower
-harmonics) is cut to the localisation boxes {Q >= Q0} of Section 5
-(Q = log10(|f| / max |f|)) for a ladder of thresholds, the volume potential
-of each cut source is taken, and its error is measured as the paper does,
-along the x axis and relative to the first harmonic:
+The protocol of Section 5 (the domain study behind the table of domain
+fractions):
+- The reference domain is D_2 of equation "domain", [l - L, l + d] x
+  [-R, R]^2 with L = sqrt(l^2 - R^2) - eps and eps = 0.1 mm, meshed once at
+  lambda_5 / 6 with the focus on a voxel centre (for H131 with d = 9.8 mm:
+  900 x 732 x 732 voxels); every harmonic's reference solution p_n^r is
+  computed on that one mesh, by the cascade of eqs. harm2-harm5.
+- For harmonic n and a threshold Q0, the integration domain is the smallest
+  cuboid outside which Q = log10(|f_n| / max |f_n|) < Q0, with the part
+  beyond the focus kept whole (the post-focal length is never shrunk).
+- The error is measured along the x axis relative to the first harmonic,
+  ||p_n - p_n^r|| / ||p_1^r||, by the midpoint rule on the reference mesh's
+  axis voxels.
+- A domain's size is given as fractions of the reference domain's:
+  fraction_x = L' / L (pre-focal lengths), fraction_yz = w' / w (widths).
 
-    error = || p_n - p_n^r || / || p_1^r ||   (discrete L2 over the axis voxels).
+Where the paper is silent the study runs each reading side by side, so that
+the one that reproduces the printed table can be named:
+- lower harmonics: the source f_n of a truncated p_n is built from the
+  reference solutions of the lower harmonics ("ref"), or from lower harmonics
+  computed on their own domains of the same Q0 ("trunc");
+- the truncated p_n on the axis: the potential of the cut source evaluated
+  along the whole axis ("everywhere"), or p_n taken as zero on the part of the
+  axis outside its domain, where the nested method never computes it
+  ("inside").
 
-The fractions of the reference domain that a box needs for an error below 1%
-are the study's result (the paper's table of domain sizes); the paper reads
-them off its convergence plots.  The incident field is the GPU monopole sum,
-normalised to the prescribed radiated power.
-
-Every numeric step runs in the library (incident field, power, cascade plan,
-source terms, localisation boxes, volume potentials); this module chooses the
-boxes, masks the sources and reduces the axis norms.
+Every numeric step runs in the library (incident field and its power, the
+cascade, source terms, localisation boxes, and the volume potential of the
+source restricted to a box, scaled by C_n); this module chooses the boxes and
+reduces the axis norms of the results for the report.
 """
 
 import math
@@ -26,7 +37,7 @@ import math
 import numpy as np
 import torch
 
-from . import boxpred, nvp
+from . import nvp
 
 # Transducers of the paper's Table of transducers (f0, focal length l, outer radius R).
 H131 = dict(f0=1.1e6, l=35e-3, R=16.5e-3)
@@ -34,7 +45,8 @@ H101 = dict(f0=1.1e6, l=63.2e-3, R=32e-3)
 # Post-focal distance d of H131's reference domain: the paper's mesh of 901 x 732 x 732 voxels
 # at lambda_5 / 6 has an x extent of L + d with L = sqrt(l^2 - R^2).
 H131_D = 9.8e-3
-Q0_LADDER = tuple(-0.25 * i for i in range(1, 33))
+EPS = 1.0e-4  # the paper's displacement of the reference domain from the bowl (0.1 mm)
+Q0_LADDER = tuple(-0.125 * i for i in range(1, 65))
 TARGET = 0.01
 
 
@@ -53,82 +65,139 @@ def normalised_incident(ctx, T, med, power, points, n_r=256, n_theta=256):
     return s * math.sqrt(power / pw)
 
 
-def study(ctx, T, med, power, d, points, n_max=5, q0=Q0_LADDER, order=1, log=None):
-    """Axis errors of every ladder box of every harmonic; returns a list of per-harmonic records.
+def reference_mesh(T, med, d, n_max=5, eps=EPS):
+    """The one mesh of the reference domain D_2 at lambda_{n_max} / 6, and the focal voxel."""
+    l, R = T["l"], T["R"]
+    L = math.sqrt(l * l - R * R) - eps
+    lo, hi = (l - L, -R, -R), (l + d, R, R)
+    h = nvp.spacing(med, T["f0"], n_max)
+    g, i_f = nvp.grid_from_box((l, 0.0, 0.0), lo, hi, h)
+    return g, tuple(int(v) for v in i_f), L
 
-    points: the bowl's source points (float64 CUDA tensor [n, 3]); d: post-focal distance of the
-    reference domain; order: transfer order (the paper's is linear)."""
-    lam1 = med["c0"] / T["f0"]
-    tr = boxpred.Transducer(R=T["R"], l=T["l"], f0=T["f0"], p0=0.0, n_harm=n_max)
-    geo = boxpred.Geometry(tr, med, window=(1e9, d / lam1, 1e9))
-    g1 = geo.g1()
-    grids = [geo.grid(n) for n in range(2, n_max + 1)]
-    pts = points
-    s = normalised_incident(ctx, T, med, power, pts)
+
+def domain_box(qbox, i_f, n):
+    """The truncated integration domain for a localisation box: its pre-focal start and width, with
+    everything beyond the focus along x kept (inclusive voxel indices lo_x, lo_y, lo_z, hi_x, hi_y, hi_z)."""
+    return (min(int(qbox[0]), i_f[0]), int(qbox[1]), int(qbox[2]), int(n[0]) - 1, int(qbox[4]), int(qbox[5]))
+
+
+def fractions(box, i_f, n):
+    """fraction_x = L' / L by voxel edges (pre-focal), fraction_yz = w' / w (the wider of y and z)."""
+    fx = (i_f[0] - box[0] + 0.5) / (i_f[0] + 0.5)
+    fyz = max((box[4] - box[1] + 1) / n[1], (box[5] - box[2] + 1) / n[2])
+    return fx, fyz
+
+
+def crossing(fr, err, target=TARGET):
+    """The fraction at which the error curve (errors at increasing fractions) last falls below the
+    target, read off by linear interpolation of log(error) between the two bracketing boxes."""
+    ok = err < target
+    i = len(ok)
+    while i > 0 and ok[i - 1]:
+        i -= 1
+    if i == len(ok):
+        return float("nan")
+    if i == 0:
+        return float(fr[0])
+    a, b = math.log(err[i - 1]), math.log(max(err[i], 1e-300))
+    t = (a - math.log(target)) / (a - b) if a != b else 1.0
+    return float(fr[i - 1] + t * (fr[i] - fr[i - 1]))
+
+
+def study(ctx, T, med, power, d, points, n_max=5, q0=Q0_LADDER, order=1, readings=("ref",), log=None):
+    """Axis errors of every ladder domain of every harmonic, per reading of the lower harmonics.
+
+    Returns {reading: [per-harmonic record]}; each record holds the ladder's boxes, fractions and the
+    two axis errors ("everywhere", "inside") and, per error, the smallest ladder domain from which on
+    every larger one meets 1% and the interpolated 1% crossing."""
+    g, i_f, L = reference_mesh(T, med, d, n_max)
+    N = [int(v) for v in g.n]
+    s = normalised_incident(ctx, T, med, power, points)
     k1 = nvp.wavenumber(med, T["f0"], 1)
-    p1 = nvp.incident_field(ctx, k1, s, pts, g1)
-    plan = nvp.CascadePlan(ctx, med, T["f0"], g1, grids, prec=nvp.NVP_C64, order=order)
-    fields = [p1]
-    out = []
+    p1 = nvp.incident_field(ctx, k1, s, points, g)
+    if log:
+        log("reference mesh %s at %.2f um, focus voxel %s" % (N, g.h * 1e6, i_f))
+    plan = nvp.CascadePlan(ctx, med, T["f0"], g, [g] * (n_max - 1), prec=nvp.NVP_C64, order=order)
     try:
+        ref = [p1] + [t for t in plan.execute(p1)]
+        axis = lambda t: t[:, i_f[1], i_f[2]].to(torch.complex128).cpu().numpy()  # noqa: E731
+        ref_axis = [axis(t) for t in ref]
+        norm1 = float(np.linalg.norm(ref_axis[0]))
+        # the ladder's domains of every harmonic, from the localisation boxes of its reference source
+        boxes = {}
         for n in range(2, n_max + 1):
-            g = grids[n - 2]
-            pre, _, hy, hz = geo.half_counts(n, (1.0, 1.0, 1.0))
-            xs = g.origin[0] + np.arange(int(g.n[0])) * g.h
-            axis_pts = torch.tensor(np.stack([xs, np.zeros_like(xs), np.zeros_like(xs)], axis=1), device="cuda")
-            p1_axis = nvp.incident_at(ctx, k1, s, pts, axis_pts, prec=nvp.NVP_C128)
-            norm1 = float(torch.linalg.vector_norm(p1_axis))
-            f = plan.source_term(n, fields)
-            k, C = nvp.wavenumber(med, T["f0"], n), nvp.cascade_constant(med, T["f0"], n)
-            # p_n = C_n sum K f = -C_n u, with u the raw operator's output
-            ref = -C * nvp.volume_potential(ctx, k, g, f)[:, hy, hz].to(torch.complex128)
-            boxes = nvp.qbox(ctx, f, q0)
-            errs, fracs, sizes = [], [], []
-            for b in boxes:
-                sizes.append(((b[3] - b[0] + 1) / g.n[0], max((b[4] - b[1] + 1) / g.n[1], (b[5] - b[2] + 1) / g.n[2])))
-                fm = torch.zeros_like(f)
-                sl = (slice(b[0], b[3] + 1), slice(b[1], b[4] + 1), slice(b[2], b[5] + 1))
-                fm[sl] = f[sl]
-                u = -C * nvp.volume_potential(ctx, k, g, fm)[:, hy, hz].to(torch.complex128)
-                errs.append(float(torch.linalg.vector_norm(u - ref)) / norm1)
-                fracs.append(geo.fractions_of(n, b))
-            errs, fracs = np.asarray(errs), np.asarray(fracs)
-            # the smallest ladder box from which on every larger box meets the target
-            ok = errs < TARGET
-            i = len(ok)
-            while i > 0 and ok[i - 1]:
-                i -= 1
-            need = fracs[i] if i < len(ok) else np.ones(3)
-            size = sizes[i] if i < len(ok) else (1.0, 1.0)
-            # need_x / need_yz: pre-focal length and half-width as fractions of the reference
-            # domain's; size_x / size_yz: the box's whole x extent and width as fractions of the
-            # reference domain's (the paper's L' = fraction_x L, w' = fraction_yz w)
-            rec = dict(n=n, grid=[int(v) for v in g.n], q0=np.asarray(q0), err=errs, fractions=fracs,
-                       need_x=float(need[0]), need_yz=float(max(need[1], need[2])),
-                       size_x=float(size[0]), size_yz=float(size[1]),
-                       rel_norm=float(torch.linalg.vector_norm(ref)) / norm1)
-            out.append(rec)
-            if log:
-                log("p%d on %s, < 1%% axis error: extent x %.2f, y/z %.2f (pre-focal %.2f, half-width %.2f) of the "
-                    "reference domain; ||p%d|| / ||p1|| = %.3g" % (n, rec["grid"], rec["size_x"], rec["size_yz"],
-                                                                  rec["need_x"], rec["need_yz"], n, rec["rel_norm"]))
-            if n < n_max:
-                fields.append(plan.execute_harmonic(n, fields))
+            f_ref = plan.source_term(n, ref[:n - 1])
+            qb = [b for i in range(0, len(q0), 32) for b in nvp.qbox(ctx, f_ref, q0[i:i + 32])]
+            boxes[n] = [domain_box(b, i_f, N) for b in qb]
+            del f_ref
+        out = {}
+        for reading in readings:
+            errs = {n: np.zeros((len(q0), 2)) for n in range(2, n_max + 1)}
+
+            def measure(n, j, p):
+                a = axis(p)
+                box = boxes[n][j]
+                inside = np.zeros_like(a)
+                inside[box[0]:box[3] + 1] = a[box[0]:box[3] + 1]
+                errs[n][j, 0] = np.linalg.norm(a - ref_axis[n - 1]) / norm1
+                errs[n][j, 1] = np.linalg.norm(inside - ref_axis[n - 1]) / norm1
+
+            if reading == "ref":  # the truncated p_n from the reference lower harmonics
+                for n in range(2, n_max + 1):
+                    k, C = nvp.wavenumber(med, T["f0"], n), nvp.cascade_constant(med, T["f0"], n)
+                    f = plan.source_term(n, ref[:n - 1])
+                    for j in range(len(q0)):
+                        measure(n, j, nvp.volume_potential_box(ctx, k, g, f, boxes[n][j], C))
+                    del f
+            elif reading == "trunc":  # every harmonic of the chain on its own domain of the same Q0
+                for j in range(len(q0)):
+                    chain = [p1]
+                    for n in range(2, n_max + 1):
+                        k, C = nvp.wavenumber(med, T["f0"], n), nvp.cascade_constant(med, T["f0"], n)
+                        f = plan.source_term(n, chain)
+                        p = nvp.volume_potential_box(ctx, k, g, f, boxes[n][j], C)
+                        del f
+                        measure(n, j, p)
+                        chain.append(p)
+                    del chain
+            else:
+                raise ValueError("reading must be 'ref' or 'trunc'")
+            recs = []
+            for n in range(2, n_max + 1):
+                fr = np.array([fractions(b, i_f, N) for b in boxes[n]])
+                rec = dict(n=n, q0=np.asarray(q0), boxes=boxes[n], fractions=fr, err=errs[n],
+                           rel_norm=float(np.linalg.norm(ref_axis[n - 1])) / norm1)
+                for e, name in ((0, "everywhere"), (1, "inside")):
+                    ok = errs[n][:, e] < TARGET
+                    i = len(ok)
+                    while i > 0 and ok[i - 1]:
+                        i -= 1
+                    need = fr[i] if i < len(ok) else np.ones(2)
+                    rec[name] = dict(ladder=(float(need[0]), float(need[1])),
+                                     crossing=(crossing(fr[:, 0], errs[n][:, e]), crossing(fr[:, 1], errs[n][:, e])))
+                recs.append(rec)
+                if log:
+                    log("%s p%d: 1%% at x %.2f y/z %.2f (error everywhere on the axis), x %.2f y/z %.2f (zero "
+                        "outside the domain); ||p%d|| / ||p1|| = %.3g" % (
+                            reading, n, *rec["everywhere"]["ladder"], *rec["inside"]["ladder"], n, rec["rel_norm"]))
+            out[reading] = recs
+        return dict(mesh=N, h=g.h, i_f=i_f, L=L, readings=out)
     finally:
         plan.close()
-    return out
 
 
-def table(ctx, configs, n_points=4096, log=None):
-    """Rows (name, per-harmonic (x, y/z) fractions) for a list of (name, transducer, medium, power, d).
-
-    The bowl carries about n_points monopoles in Deserno's regular placement, as in the paper."""
+def table(ctx, configs, n_points=4096, readings=("ref", "trunc"), log=None):
+    """Per configuration (name, transducer, medium, power, d): the study's fractions per reading."""
     from workload import bowl
     rows = []
     for name, T, med, power, d in configs:
         pts = torch.from_numpy(bowl.bowl_points_deserno(T["R"], T["l"], n_points)).to("cuda")
-        recs = study(ctx, T, med, power, d, pts, log=log)
-        rows.append(dict(name=name, extent=[(r["size_x"], r["size_yz"]) for r in recs],
-                         prefocal=[(r["need_x"], r["need_yz"]) for r in recs],
-                         rel_norms=[r["rel_norm"] for r in recs], grids=[r["grid"] for r in recs]))
+        res = study(ctx, T, med, power, d, pts, readings=readings, log=log)
+        row = dict(name=name, mesh=res["mesh"], h=res["h"])
+        for reading, recs in res["readings"].items():
+            for e in ("everywhere", "inside"):
+                row["%s/%s" % (reading, e)] = [r[e] for r in recs]
+            row["%s/rel_norms" % reading] = [r["rel_norm"] for r in recs]
+        rows.append(row)
+        torch.cuda.empty_cache()
     return rows

@@ -80,13 +80,27 @@ def test_transfer_tables_bit_exact_indices(order):
 
 
 def test_circulant_sizes():
-    for n in (1, 2, 7, 8, 9, 16, 17, 32, 48, 80, 96, 100, 128, 160, 200, 256, 320, 384, 448, 512, 640, 641, 768,
-              769, 1024):
+    lengths = P.transform_lengths()
+    assert lengths == sorted(lengths) and lengths[0] == 16 and lengths[-1] == 8192
+    for L in lengths:  # even and 2,3,5,7-smooth, each with a radix plan
+        r = L
+        for p in (2, 3, 5, 7):
+            while r % p == 0:
+                r //= p
+        assert r == 1 and L % 8 == 0, L
+    for n in range(1, 4097):
         m = P.circulant_size(n)
-        assert m >= 2 * n - 1 and m % 2 == 0
-    assert P.circulant_size(640) == 1280 and P.circulant_size(641) == 1536 and P.circulant_size(769) == 2048
-    with pytest.raises(P.NvpError):
-        P.circulant_size(1025)
+        assert m >= 2 * n - 1 and m % 2 == 0 and m in lengths
+        # the smallest compiled length that embeds the axis (Section 3.1: any M >= 2n - 1 is exact)
+        assert not [L for L in lengths if 2 * n - 1 <= L < m]
+        if n >= 128:
+            assert m <= 1.125 * (2 * n - 1), (n, m)
+    assert P.circulant_size(640) == 1280 and P.circulant_size(641) == 1344 and P.circulant_size(769) == 1728
+    # the paper's H101 nested meshes (576..716 x 568^2)
+    assert [P.circulant_size(n) for n in (568, 576, 623, 669, 716)] == [1152, 1152, 1280, 1344, 1440]
+    with pytest.raises(P.NvpError) as e:
+        P.circulant_size(4097)
+    assert e.value.status == 4
     for n in (0, -3):  # empty or negative axes
         with pytest.raises(P.NvpError):
             P.circulant_size(n)
