@@ -227,6 +227,26 @@ nvp_status nvp_field_lin3(nvp_ctx *ctx, int64_t n, void *out_dev, const void *a_
 nvp_status nvp_field_diff_norms(nvp_ctx *ctx, int64_t n, const void *a_dev, const void *b_dev, nvp_prec prec,
                                 double out[2]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operator and arguments as nvp_volume_potential, computed with the same
+ * kernels, but with every work buffer (the kernel-spectrum octant and the two
+ * pass buffers) inside one fixed device array of NVP_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each device it runs on until the process ends.
+ * The call allocates nothing and keeps no cache: the kernel spectrum is made
+ * again on every call.  Grids whose buffers exceed the array are refused with
+ * NVP_E_UNSUPPORTED (the message gives both sizes); complex64 cubes up to
+ * 128^3 voxels fit, complex128 cubes up to 96^3 (the exact limit follows
+ * from the circulant lengths, nvp_circulant_size).  Every call on one GPU
+ * shares that GPU's array, so calls that may overlap on one GPU (other
+ * streams, other contexts, other threads) race; calls on one stream run in
+ * turn.  Each call writes every scratch byte before reading it.  The transform
+ * tables come from the context (made at nvp_ctx_create).  Enqueued on the
+ * context stream; errors as nvp_volume_potential. */
+#define NVP_NOALLOC_SCRATCH_BYTES (128u << 20)
+nvp_status nvp_volume_potential_noalloc(nvp_ctx *ctx, double k_re, double k_im, const nvp_grid *g,
+                                        const void *f_dev, void *u_dev, nvp_prec prec);
+
 /* Volume integral equation of an inhomogeneous medium (Section 7, the
  * equations of the harmonics in an inhomogeneous domain): with background
  * wavenumber kb (Im kb >= 0) and contrast q_j = k(x_j)^2 - kb^2 per voxel,

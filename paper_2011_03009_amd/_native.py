@@ -50,6 +50,7 @@ SIGNATURES = {
     "nvp_circulant_size": (_st, [_i64, _i64p]),
     "nvp_transform_lengths": (_st, [ctypes.POINTER(ctypes.c_int32), _i, ctypes.POINTER(_i)]),
     "nvp_volume_potential": (_st, [_vp, _d, _d, ctypes.POINTER(Grid), _vp, _vp, _i]),
+    "nvp_volume_potential_noalloc": (_st, [_vp, _d, _d, ctypes.POINTER(Grid), _vp, _vp, _i]),
     "nvp_volume_potential_box": (_st, [_vp, _d, _d, ctypes.POINTER(Grid), _vp, _i64p, _d, _vp, _i]),
     "nvp_field_lin3": (_st, [_vp, _i64, _vp, _vp, _vp, _vp, _dp, _dp, _i]),
     "nvp_field_diff_norms": (_st, [_vp, _i64, _vp, _vp, _i, _dp]),

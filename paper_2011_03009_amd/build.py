@@ -64,7 +64,7 @@ def jobs_list():
         jobs.append((obj, [HIPCC] + COMMON + ["-DNVP_L=%d" % L, "-c", inst, "-o", obj], sorted(_deps(inst))))
     for name, extra in (("kspec.hip", []), ("dispatch.cpp", []), ("runtime.cpp", ["-ffp-contract=off"]),
                         ("qbox.hip", []), ("boxnet.hip", []), ("learn.cpp", []),
-                        ("incident.hip", []), ("vie.hip", []), ("difference.hip", ["-ffp-contract=off"])):
+                        ("incident.hip", []), ("vie.hip", []), ("noalloc.hip", []), ("difference.hip", ["-ffp-contract=off"])):
         obj = os.path.join(OBJ, os.path.splitext(name)[0] + ".o")
         jobs.append((obj, [HIPCC] + COMMON + extra + ["-c", os.path.join(CSRC, name), "-o", obj],
                      sorted(_deps(os.path.join(CSRC, name)))))

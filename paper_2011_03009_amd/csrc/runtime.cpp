@@ -655,6 +655,10 @@ SourceArgs source_args(const nvp_plan *plan, int n, const void *const *fields) {
 
 namespace nvp {
 
+// Looks up the fixed scratch array of nvp_volume_potential_noalloc on the
+// context's device (noalloc.hip).
+nvp_status noalloc_setup(nvp_ctx *ctx);
+
 // Context access for the other translation units behind the C ABI.
 int ctx_device(const nvp_ctx *c) { return c->device; }
 hipStream_t ctx_stream(const nvp_ctx *c) { return c->stream; }
@@ -663,6 +667,31 @@ nvp_status ctx_hip_fail(nvp_ctx *c, const char *what, hipError_t e) { return hip
 void ctx_quad_weights(const nvp_ctx *c, double kr, double ki, double h, double *sr, double *si, double *fr,
                       double *fi) {
     quad_weights(c->quad, kr, ki, h, sr, si, fr, fi);
+}
+
+// The volume potential of nvp_volume_potential in buffers the caller places:
+// checks the arguments, reports the bytes of the three buffers (kernel-spectrum
+// octant, pass buffer A, pass buffer B), and, when the buffers are given,
+// computes the kernel spectrum into them and convolves, with the same kernels,
+// tables and launch choices as nvp_volume_potential (no cache: the spectrum is
+// made on every call).  Allocates nothing.
+nvp_status vp_buffers(nvp_ctx *ctx, double k_re, double k_im, const nvp_grid *g, const void *f_dev, void *u_dev,
+                      nvp_prec prec, size_t bytes[3], void *khat, void *A, void *B) {
+    if (!ctx) return NVP_E_INVALID;
+    if (!grid_ok(g) || !f_dev || !u_dev || f_dev == u_dev || (prec != NVP_C64 && prec != NVP_C128) ||
+        !std::isfinite(k_re) || !std::isfinite(k_im) || k_im < 0 || (k_re == 0 && k_im == 0))
+        return fail(ctx, NVP_E_INVALID, "volume potential: bad argument");
+    int64_t M[3];
+    nvp_status st = check_grid_lengths(ctx, g, M);
+    if (st) return st;
+    bytes[0] = khat_bytes(M, prec);
+    bytes[1] = bytesA(g, M, prec);
+    bytes[2] = bytesB(g, M, prec);
+    if (!khat || !A || !B) return NVP_OK;
+    NVP_HIP(ctx, hipSetDevice(ctx->device));
+    if ((st = kernel_spectrum(ctx, nullptr, ctx->quad, k_re, k_im, g, M, prec, khat, B, A))) return st;
+    const double scale = -1.0 / ((double)M[0] * (double)M[1] * (double)M[2]);
+    return convolve(ctx, nullptr, prec, g, M, khat, A, B, f_dev, nullptr, u_dev, scale);
 }
 
 }  // namespace nvp
@@ -701,6 +730,7 @@ nvp_status nvp_ctx_create(int device, void *hip_stream, nvp_ctx **out) {
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->max_lds = prop.sharedMemPerBlock;
     nvp_status st = make_twiddles(c);
+    if (!st) st = nvp::noalloc_setup(c);
     if (st) {
         g_create_err_buf = c->err;
         g_create_err = g_create_err_buf.c_str();

@@ -332,6 +332,20 @@ def field_diff_norms(ctx, a, b):
     return float(out[0]), float(out[1])
 
 
+def volume_potential_noalloc(ctx, k, g, f, out):
+    """nvp_volume_potential_noalloc: the operator of volume_potential with the library's fixed device
+    scratch (no device allocation in the call); `out` is the caller's output tensor."""
+    g = grid(g)
+    n = tuple(g.n)
+    prec = prec_of(f.dtype)
+    _need(f, f.dtype, n[0] * n[1] * n[2], "f")
+    _need(out, f.dtype, n[0] * n[1] * n[2], "out")
+    k = complex(k)
+    _check(_native.lib().nvp_volume_potential_noalloc(ctx.handle, k.real, k.imag, ctypes.byref(g), _ptr(f),
+                                                      _ptr(out), prec), ctx.handle)
+    return out
+
+
 class CascadePlan:
     """nvp_plan of harmonics 2..n_harm on their own grids."""
 
