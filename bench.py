@@ -172,6 +172,87 @@ def time_steps(torch, plan, p1, outs, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
+def per_harmonic_rates(P, torch, plan, p1, outs, g1, gn, order, stream, reps=5):
+    """Each harmonic's convolution step alone (kernel spectrum cached): voxels/s and the fraction of
+    8 TB/s its algorithmic bytes (transfer + source build and the five passes) move at."""
+    fields = [p1] + list(outs)
+    rows = {}
+    for i, g in enumerate(gn):
+        n = i + 2
+        plan.execute_harmonic(n, fields[:n - 1], outs[i])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.execute_harmonic(n, fields[:n - 1], outs[i])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        b = alg_bytes(P, g1, gn[:i + 1], order)
+        conv = sum(b[k] for k in ("src", "xfwd", "yfwd", "zconv", "yinv", "xinv"))
+        if i:  # alg_bytes sums over the grids given: keep harmonic n's share
+            prev = alg_bytes(P, g1, gn[:i], order)
+            conv -= sum(prev[k] for k in ("src", "xfwd", "yfwd", "zconv", "yinv", "xinv"))
+        rows[str(n)] = {"grid": [int(v) for v in g.n], "ms": ms, "voxels_per_s": nsz(g) / (ms * 1e-3),
+                        "alg_GBs": conv / (ms * 1e-3) / 1e9, "frac_hbm": conv / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    return rows
+
+
+def copy_ceiling(torch, stream, gib=4, reps=5):
+    """A device-to-device copy of `gib` GiB (read + write bytes over time): the HBM rate a plain
+    streaming kernel reaches, beside the 8 TB/s datasheet peak."""
+    src = torch.ones((gib << 30) // 8, dtype=torch.complex64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2.0 * src.numel() * 8 / (ms * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_copied": (gib << 30), "ms": ms, "GBs_read_plus_write": gbs, "frac_of_peak": gbs / PEAK_HBM_GBS}
+
+
+def amplitude_order_sweep(P, torch, ctx, stream, pfs=(2.0e6, 3.5e6, 5.0e6), orders=(1, 3)):
+    """The headline workload at the other focal pressures and with the paper's linear transfer: the
+    nested step time and the focal error e_n against the uniform 640^3 run of the same input."""
+    from workload import configs
+    rows = []
+    for pf in pfs:
+        cfg = configs.paper_scale(P_f=pf)
+        W = cfg["medium"]
+        g1, gn, gu, p1 = build_inputs(P, torch, cfg, torch.device("cuda", 0))
+        i1 = tuple(cfg["p1_grid"]["i_f"])
+        p1f = abs(complex(p1[i1].item()))
+        for order in orders:
+            plan = P.CascadePlan(ctx, W, cfg["f0"], g1, gn, prec=P.NVP_C64, order=order)
+            plan.set_kernel_cache(False)
+            outs = [torch.empty(tuple(g.n), dtype=torch.complex64, device="cuda") for g in gn]
+            ms = time_steps(torch, plan, p1, outs, 5, 2, stream)
+            plan.close()
+            plan_u = P.CascadePlan(ctx, W, cfg["f0"], g1, gu, prec=P.NVP_C64, order=order)
+            plan_u.set_kernel_cache(False)
+            outs_u = [torch.empty(tuple(g.n), dtype=torch.complex64, device="cuda") for g in gu]
+            ms_u = time_steps(torch, plan_u, p1, outs_u, 2, 1, stream)
+            plan_u.close()
+            e = {}
+            for i in range(len(gn)):
+                a_n = complex(outs[i][tuple(cfg["grids"][i + 2]["i_f"])].item())
+                b_n = complex(outs_u[i][tuple(cfg["uniform_grids"][i + 2]["i_f"])].item())
+                e[str(i + 2)] = abs(a_n - b_n) / p1f
+            rows.append({"P_f_MPa": pf / 1e6, "order": order, "ms_nested": ms, "ms_uniform": ms_u,
+                         "ratio": ms_u / ms, "focal_err": e, "max_focal_err": max(e.values()),
+                         "p1_focal_Pa": p1f})
+            del outs, outs_u
+            torch.cuda.empty_cache()
+    return rows
+
+
 def cpu_baseline(cfg, g1_p, gn_p, p1_dev, budget_s, order):
     """The FP64 oracle on a bounded sample: p2 at random voxels of its 256^3 grid.
 
@@ -428,6 +509,7 @@ def main():
     ap.add_argument("--no-uniform", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the focal-pressure and transfer-order sweep")
     ap.add_argument("--corrected-quadrature", action="store_true",
                     help="also run the nested cascade under the corrected quadrature and report how far the "
                          "paper's rule is from it")
@@ -483,6 +565,7 @@ def main():
     ms_conv = time_steps(torch, plan, p1, outs, a.steps, 1, stream)
     ctx.sync()
     nested = [o.clone() for o in outs]
+    per_harmonic = per_harmonic_rates(P, torch, plan, p1, outs, g1, gn, a.order, stream)
 
     # roofline of the dominant kernel kind
     ab = alg_bytes(P, g1, gn, a.order)
@@ -515,6 +598,8 @@ def main():
         "conv_only": {"ms_per_step": ms_conv, "voxels_per_s": voxels / (ms_conv * 1e-3),
                       "five_pass_alg_GBs": conv_gbs, "five_pass_frac": conv_gbs / PEAK_HBM_GBS},
         "per_kernel": per_kind,
+        "per_harmonic": per_harmonic,
+        "copy_ceiling": copy_ceiling(torch, stream),
     }
     del plan
 
@@ -554,6 +639,10 @@ def main():
             "p1_focal_Pa": p1f}
         del plan_u, outs_u
         torch.cuda.empty_cache()
+
+    if not a.no_sweep:
+        log("bench: focal pressures 2 / 3.5 / 5 MPa and transfer orders 1 / 3 against the uniform run")
+        result["amplitude_order_sweep"] = amplitude_order_sweep(P, torch, ctx, stream)
 
     if a.corrected_quadrature:
         log("bench: nested cascade under the corrected quadrature")

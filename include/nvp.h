@@ -258,7 +258,8 @@ nvp_status nvp_volume_potential_noalloc(nvp_ctx *ctx, double k_re, double k_im, 
  * true relative residual ||rhs - A p|| / ||rhs|| of the returned p (check it:
  * reaching max_iter is not an error).  q_dev, rhs_dev, p_dev: N complex values
  * in prec (device, caller-owned; p may not alias q or rhs).  Synchronous:
- * every inner product waits for the context stream.  Allocates 8 N complex
+ * the recurrence's scalars stay on the device and each iteration waits once
+ * for the context stream, to read the residual norm.  Allocates 8 N complex
  * values for the call; uses the context's volume-potential cache.
  * NVP_E_INVALID: bad arguments; NVP_E_STATE: a breakdown of the recurrence. */
 nvp_status nvp_vie_solve(nvp_ctx *ctx, double kb_re, double kb_im, const nvp_grid *g, const void *q_dev,

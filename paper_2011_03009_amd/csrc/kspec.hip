@@ -3,6 +3,7 @@
 #include <stdlib.h>
 
 #include "passes_impl.hpp"
+#include "source.hpp"
 
 namespace nvp {
 
@@ -33,6 +34,20 @@ hipError_t launch_kradial(double2 *ktab, int64_t n, double h, double kr, double 
     return hipGetLastError();
 }
 
+template <typename R, int K, int NF>
+static hipError_t source_nf(const LdSource<R, K> &ld, const SourceArgs &a, void *out, int Ny, int64_t lds_elems,
+                            hipStream_t s) {
+    auto kern = k_source<R, K, NF, NVP_SRC_TX, NVP_SRC_TY, NVP_SRC_TZ>;
+    const size_t lds = (size_t)lds_elems * sizeof(cx<R>);
+    hipError_t e = allow_lds(kern, lds > 65536 ? 163840 : lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)((a.Nz + NVP_SRC_TZ - 1) / NVP_SRC_TZ), (unsigned)((Ny + NVP_SRC_TY - 1) / NVP_SRC_TY),
+              (unsigned)((a.Nx + NVP_SRC_TX - 1) / NVP_SRC_TX));
+    hipLaunchKernelGGL(kern, grid, dim3(NVP_SRC_TY * NVP_SRC_TZ), lds, s, ld, static_cast<cx<R> *>(out), Ny,
+                       lds_elems);
+    return hipGetLastError();
+}
+
 template <typename R, int K>
 static hipError_t source_k(const SourceArgs &a, void *out, int Ny, int64_t lds_elems, hipStream_t s) {
     LdSource<R, K> ld;
@@ -50,15 +65,16 @@ static hipError_t source_k(const SourceArgs &a, void *out, int Ny, int64_t lds_e
     ld.nf = a.nf;
     ld.Nx = a.Nx;
     ld.Nz = a.Nz;
-    auto kern = k_source<R, K, NVP_SRC_TX, NVP_SRC_TY, NVP_SRC_TZ>;
-    const size_t lds = (size_t)lds_elems * sizeof(cx<R>);
-    hipError_t e = allow_lds(kern, lds > 65536 ? 163840 : lds);
-    if (e != hipSuccess) return e;
-    dim3 grid((unsigned)((a.Nz + NVP_SRC_TZ - 1) / NVP_SRC_TZ), (unsigned)((Ny + NVP_SRC_TY - 1) / NVP_SRC_TY),
-              (unsigned)((a.Nx + NVP_SRC_TX - 1) / NVP_SRC_TX));
-    hipLaunchKernelGGL(kern, grid, dim3(NVP_SRC_TY * NVP_SRC_TZ), lds, s, ld, static_cast<cx<R> *>(out), Ny,
-                       lds_elems);
-    return hipGetLastError();
+    switch (a.nf) {
+    case 1: return source_nf<R, K, 1>(ld, a, out, Ny, lds_elems, s);
+    case 2: return source_nf<R, K, 2>(ld, a, out, Ny, lds_elems, s);
+    case 3: return source_nf<R, K, 3>(ld, a, out, Ny, lds_elems, s);
+    case 4: return source_nf<R, K, 4>(ld, a, out, Ny, lds_elems, s);
+    case 5: return source_nf<R, K, 5>(ld, a, out, Ny, lds_elems, s);
+    case 6: return source_nf<R, K, 6>(ld, a, out, Ny, lds_elems, s);
+    case 7: return source_nf<R, K, 7>(ld, a, out, Ny, lds_elems, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_source_c64(const SourceArgs &a, void *out, int Ny, int64_t lds_elems, hipStream_t s) {

@@ -505,6 +505,17 @@ nvp_status vp_prepare(nvp_ctx *ctx, double k_re, double k_im, const nvp_grid *g,
     const bool hit = c.valid && c.quad == ctx->quad && c.kr == k_re && c.ki == k_im && c.prec == (int)prec &&
                      same_grid(c.g, *g);
     if (hit) return NVP_OK;
+    // same grid and precision: keep the buffers, remake only the spectrum
+    if (c.khat && c.prec == (int)prec && same_grid(c.g, *g)) {
+        c.valid = false;
+        nvp_status st = kernel_spectrum(ctx, nullptr, ctx->quad, k_re, k_im, g, M, prec, c.khat, c.B, c.A);
+        if (st) return st;
+        c.valid = true;
+        c.quad = ctx->quad;
+        c.kr = k_re;
+        c.ki = k_im;
+        return NVP_OK;
+    }
     NVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (c.khat) (void)hipFree(c.khat);
     if (c.A) (void)hipFree(c.A);

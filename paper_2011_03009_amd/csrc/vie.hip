@@ -5,9 +5,9 @@
 // discretised with the same midpoint-rule kernel as the volume potential:
 //     p_i - sum_j K_kb(x_i - x_j) q_j p_j = rhs_i.
 // Solved by BiCGStab (van der Vorst's stabilised bi-conjugate gradients) with
-// the library's FFT volume potential as the operator.  The vector updates
-// and the inner products (accumulated in FP64) are the kernels below; the
-// scalar recurrences run on the host.
+// the library's FFT volume potential as the operator.  The vector updates,
+// the inner products (accumulated in FP64) and the scalar recurrence are the
+// kernels below; an iteration waits once, for the residual norm.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -130,6 +130,88 @@ struct DevMem {
     }
 };
 
+// out = a + al[0] b + be[0] c with the coefficients read from device memory
+// (the recurrence's scalars never leave the device); as k_lin3 otherwise.
+// Nothing is written once the recurrence has flagged a breakdown, so that the
+// iterate stays the last good one.
+template <typename V>
+__global__ void __launch_bounds__(kBlock) k_lin3d(V *out, const V *a, const V *b, const V *c,
+                                                  const double2 *__restrict__ al, const double2 *__restrict__ be,
+                                                  const double2 *__restrict__ flag, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n || flag->x != 0.0) return;
+    const double2 A2 = al ? *al : make_double2(0.0, 0.0), B2 = be ? *be : make_double2(0.0, 0.0);
+    const V A = a ? a[i] : mk<V>(0.0, 0.0), B = b ? b[i] : mk<V>(0.0, 0.0), C = c ? c[i] : mk<V>(0.0, 0.0);
+    const V p = mk<V>(A2.x, A2.y), r = mk<V>(B2.x, B2.y);
+    out[i] = V{A.x + p.x * B.x - p.y * B.y + r.x * C.x - r.y * C.y, A.y + p.x * B.y + p.y * B.x + r.x * C.y + r.y * C.x};
+}
+
+// The scalar state of BiCGStab on the device, one double2 (complex) each.
+enum Sc { RHO, ALPHA, OMEGA, RHO1, RV, TS, TT, RN2, RNI, BETA, NBO, NAL, NOM, FLAG, NSC };
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ double2 cmuld(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Sums the kDotBlocks-or-fewer partial dot products into sc[slot] (one
+// workgroup, fixed order), then takes the step of the recurrence that this
+// dot product completes:
+//   RHO1: beta = (rho1 / rho) (alpha / omega), coefficients beta and -beta omega
+//         for p = r + beta (p - omega v); flags a breakdown (rho1 or omega zero);
+//   RV:   alpha = rho1 / rv (flag rv zero), coefficient -alpha for s = r - alpha v;
+//   TT:   omega = ts / tt (0 when tt is 0), coefficient -omega for r = s - omega t;
+//   RNI:  the iteration's residual norm squared, kept in RN2, and rho = rho1 for
+//         the next iteration (RN2 alone: a norm with no step of the recurrence).
+__global__ void __launch_bounds__(kBlock) k_dot_finish(const double2 *__restrict__ part, int nb, double2 *sc,
+                                                       int slot) {
+    __shared__ double sr[kBlock], si[kBlock];
+    double re = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kBlock) re += part[i].x, im += part[i].y;
+    sr[threadIdx.x] = re;
+    si[threadIdx.x] = im;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sr[threadIdx.x] += sr[threadIdx.x + w];
+            si[threadIdx.x] += si[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x) return;
+    const double2 v = make_double2(sr[0], si[0]);
+    sc[slot] = v;
+    if (slot == RHO1) {
+        const double2 rho = sc[RHO], al = sc[ALPHA], om = sc[OMEGA];
+        if ((v.x == 0.0 && v.y == 0.0) || (om.x == 0.0 && om.y == 0.0)) {
+            sc[FLAG].x = 1.0;
+            return;
+        }
+        const double2 beta = cmuld(cdiv(v, rho), cdiv(al, om));
+        sc[BETA] = beta;
+        const double2 bo = cmuld(beta, om);
+        sc[NBO] = make_double2(-bo.x, -bo.y);
+    } else if (slot == RV) {
+        if (v.x == 0.0 && v.y == 0.0) {
+            sc[FLAG].x = 1.0;
+            return;
+        }
+        const double2 al = cdiv(sc[RHO1], v);
+        sc[ALPHA] = al;
+        sc[NAL] = make_double2(-al.x, -al.y);
+    } else if (slot == TT) {
+        const double2 om = v.x > 0.0 ? cdiv(sc[TS], v) : make_double2(0.0, 0.0);
+        sc[OMEGA] = om;
+        sc[NOM] = make_double2(-om.x, -om.y);
+    } else if (slot == RNI) {
+        sc[RN2] = v;
+        sc[RHO] = sc[RHO1];
+    }
+}
+
 // The solver's state for one call: vectors of n complex values of type V.
 template <typename V> struct Solver {
     nvp_ctx *ctx;
@@ -140,6 +222,7 @@ template <typename V> struct Solver {
     nvp_prec prec;
     const V *q;
     double2 *part;  // kDotBlocks partial sums
+    double2 *sc;    // NSC scalars
     V *tmp, *u;     // operator scratch
     nvp_status st = NVP_OK;
 
@@ -153,6 +236,11 @@ template <typename V> struct Solver {
                            make_double2(al.real(), al.imag()), make_double2(be.real(), be.imag()), n);
         return ok(hipGetLastError(), "k_lin3");
     }
+    bool lin3d(V *out, const V *a, const V *b, const V *c, int al, int be) {
+        hipLaunchKernelGGL(k_lin3d<V>, dim3(blocks()), dim3(kBlock), 0, s, out, a, b, c, al < 0 ? nullptr : sc + al,
+                           be < 0 ? nullptr : sc + be, sc + FLAG, n);
+        return ok(hipGetLastError(), "k_lin3d");
+    }
     // y = A x = x - V[q x] = x + u, with u = -V[q x] the raw operator's output
     bool apply(V *y, const V *x) {
         hipLaunchKernelGGL(k_mul<V>, dim3(blocks()), dim3(kBlock), 0, s, tmp, q, x, n);
@@ -164,83 +252,82 @@ template <typename V> struct Solver {
         }
         return lin3(y, x, u, nullptr, 1.0, 0.0);
     }
-    bool dot(const V *a, const V *b, cd *out) {
+    // sc[slot] = sum conj(a) b, and the recurrence step it completes (device only)
+    bool dot(const V *a, const V *b, int slot) {
         const unsigned nb = (unsigned)std::min<int64_t>(kDotBlocks, blocks());
         hipLaunchKernelGGL(k_dot<V>, dim3(nb), dim3(kBlock), 0, s, a, b, n, part);
         if (!ok(hipGetLastError(), "k_dot")) return false;
-        std::vector<double2> h(nb);
-        if (!ok(hipMemcpyAsync(h.data(), part, nb * sizeof(double2), hipMemcpyDeviceToHost, s), "dot copy")) return false;
-        if (!ok(hipStreamSynchronize(s), "dot sync")) return false;
-        double re = 0.0, im = 0.0;
-        for (const double2 &v : h) re += v.x, im += v.y;
-        *out = cd(re, im);
-        return true;
+        hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(kBlock), 0, s, part, (int)nb, sc, slot);
+        return ok(hipGetLastError(), "k_dot_finish");
     }
-    bool norm(const V *a, double *out) {
-        cd d;
-        if (!dot(a, a, &d)) return false;
-        *out = std::sqrt(std::max(0.0, d.real()));
+    // reads sc[RN2] and the breakdown flag: the one wait of an iteration
+    bool read(double *rn2, bool *broke) {
+        double2 h[2];
+        if (!ok(hipMemcpyAsync(&h[0], sc + RN2, sizeof(double2), hipMemcpyDeviceToHost, s), "residual copy") ||
+            !ok(hipMemcpyAsync(&h[1], sc + FLAG, sizeof(double2), hipMemcpyDeviceToHost, s), "flag copy") ||
+            !ok(hipStreamSynchronize(s), "residual sync"))
+            return false;
+        *rn2 = std::max(0.0, h[0].x);
+        *broke = h[1].x != 0.0;
         return true;
     }
 };
 
+__global__ void k_scalars_init(double2 *sc) {
+    const int i = threadIdx.x;
+    if (i < NSC) sc[i] = (i == RHO || i == ALPHA || i == OMEGA) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+}
+
+// BiCGStab (van der Vorst) with the recurrence's scalars kept on the device:
+// each iteration enqueues its two operator applications, five dot products
+// with their scalar steps and the vector updates, and waits once, to read the
+// residual norm and the breakdown flag.
 template <typename V>
 nvp_status bicgstab(nvp_ctx *ctx, double kr, double ki, const nvp_grid *g, nvp_prec prec, const void *q_dev,
                     const void *rhs_dev, void *p_dev, double tol, int max_iter, int *iters, double *relres) {
     const int64_t n = g->n[0] * g->n[1] * g->n[2];
     DevMem mem;
-    hipError_t e = hipMalloc(&mem.p, 8 * n * sizeof(V) + kDotBlocks * sizeof(double2));
+    hipError_t e = hipMalloc(&mem.p, 8 * n * sizeof(V) + (kDotBlocks + NSC) * sizeof(double2));
     if (e != hipSuccess) return nvp::ctx_hip_fail(ctx, "nvp_vie_solve: work vectors", e);
     V *w = static_cast<V *>(mem.p);
     V *r = w, *rh = w + n, *pv = w + 2 * n, *v = w + 3 * n, *sv = w + 4 * n, *t = w + 5 * n;
-    Solver<V> S{ctx, nvp::ctx_stream(ctx), n, kr, ki, g, prec, static_cast<const V *>(q_dev),
-                reinterpret_cast<double2 *>(w + 8 * n), w + 6 * n, w + 7 * n};
+    double2 *part = reinterpret_cast<double2 *>(w + 8 * n);
+    Solver<V> S{ctx, nvp::ctx_stream(ctx), n, kr, ki, g, prec, static_cast<const V *>(q_dev), part,
+                part + kDotBlocks, w + 6 * n, w + 7 * n};
     const V *b = static_cast<const V *>(rhs_dev);
     V *x = static_cast<V *>(p_dev);
     *iters = 0;
-    double bn = 0.0, rn = 0.0;
-    if (!S.norm(b, &bn)) return S.st;
+    hipLaunchKernelGGL(k_scalars_init, dim3(1), dim3(64), 0, S.s, S.sc);
+    if (!S.ok(hipGetLastError(), "k_scalars_init")) return S.st;
+    double bn2 = 0.0, rn2 = 0.0;
+    bool broke = false;
+    if (!S.dot(b, b, RN2) || !S.read(&bn2, &broke)) return S.st;
+    const double bn = std::sqrt(bn2);
     if (bn == 0.0) {  // the solution is zero
         S.lin3(x, nullptr, nullptr, nullptr, 0.0, 0.0);
         *relres = 0.0;
         return S.st;
     }
-    // r = b - A x, rh = r
+    // r = b - A x, rh = r, p = v = 0
     if (!S.apply(t, x) || !S.lin3(r, b, t, nullptr, -1.0, 0.0) || !S.lin3(rh, r, nullptr, nullptr, 0.0, 0.0) ||
         !S.lin3(pv, nullptr, nullptr, nullptr, 0.0, 0.0) || !S.lin3(v, nullptr, nullptr, nullptr, 0.0, 0.0) ||
-        !S.norm(r, &rn))
+        !S.dot(r, r, RN2) || !S.read(&rn2, &broke))
         return S.st;
-    cd rho = 1.0, alpha = 1.0, omega = 1.0;
     int it = 0;
-    while (rn / bn > tol && it < max_iter) {
+    while (std::sqrt(rn2) / bn > tol && it < max_iter) {
         ++it;
-        cd rho1;
-        if (!S.dot(rh, r, &rho1)) return S.st;
-        if (std::abs(rho1) == 0.0 || std::abs(omega) == 0.0)
-            return nvp::ctx_fail(ctx, NVP_E_STATE, "nvp_vie_solve: BiCGStab breakdown");
-        const cd beta = (rho1 / rho) * (alpha / omega);
-        cd rv;
-        if (!S.lin3(pv, r, pv, v, beta, -beta * omega) || !S.apply(v, pv) || !S.dot(rh, v, &rv)) return S.st;
-        if (std::abs(rv) == 0.0) return nvp::ctx_fail(ctx, NVP_E_STATE, "nvp_vie_solve: BiCGStab breakdown");
-        alpha = rho1 / rv;
-        double sn;
-        if (!S.lin3(sv, r, v, nullptr, -alpha, 0.0) || !S.norm(sv, &sn)) return S.st;
-        if (sn / bn <= tol) {
-            if (!S.lin3(x, x, pv, nullptr, alpha, 0.0)) return S.st;
-            rn = sn;
-            break;
-        }
-        cd ts, tt;
-        if (!S.apply(t, sv) || !S.dot(t, sv, &ts) || !S.dot(t, t, &tt)) return S.st;
-        omega = tt.real() > 0.0 ? ts / tt : cd(0.0);
-        if (!S.lin3(x, x, pv, sv, alpha, omega) || !S.lin3(r, sv, t, nullptr, -omega, 0.0) || !S.norm(r, &rn))
+        if (!S.dot(rh, r, RHO1) || !S.lin3d(pv, r, pv, v, BETA, NBO) || !S.apply(v, pv) || !S.dot(rh, v, RV) ||
+            !S.lin3d(sv, r, v, nullptr, NAL, -1) || !S.apply(t, sv) || !S.dot(t, sv, TS) || !S.dot(t, t, TT) ||
+            !S.lin3d(x, x, pv, sv, ALPHA, OMEGA) || !S.lin3d(r, sv, t, nullptr, NOM, -1) || !S.dot(r, r, RNI) ||
+            !S.read(&rn2, &broke))
             return S.st;
-        rho = rho1;
+        if (broke) return nvp::ctx_fail(ctx, NVP_E_STATE, "nvp_vie_solve: BiCGStab breakdown");
     }
     *iters = it;
     // the true residual of the returned solution
-    if (!S.apply(t, x) || !S.lin3(r, b, t, nullptr, -1.0, 0.0) || !S.norm(r, &rn)) return S.st;
-    *relres = rn / bn;
+    if (!S.apply(t, x) || !S.lin3(r, b, t, nullptr, -1.0, 0.0) || !S.dot(r, r, RN2) || !S.read(&rn2, &broke))
+        return S.st;
+    *relres = std::sqrt(rn2) / bn;
     return NVP_OK;
 }
 

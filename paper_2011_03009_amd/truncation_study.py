@@ -54,14 +54,35 @@ def cap_height(T):
     return T["l"] - math.sqrt(T["l"] ** 2 - T["R"] ** 2)
 
 
-def normalised_incident(ctx, T, med, power, points, n_r=256, n_theta=256):
+def normalised_incident(ctx, T, med, power, points, n_r=256, n_theta=256, reading="abs2"):
     """Scale of the bowl's monopole sum (points: float64 CUDA tensor [n, 3] on the cap) that makes it
-    radiate `power` watts through the rim-plane disc: the paper's (A / n) sum G times sqrt(P0 / P)."""
+    radiate `power` watts through the rim-plane disc: the paper's (A / n) sum G times sqrt(P0 / P).
+
+    reading: how the garbled power integral of Section 3.2 is read.  "abs2" (the library's
+    nvp_radiated_power): 1/(2 rho0 c0) int |p|^2 r dr dtheta.  The two alternatives, for the
+    domain study's comparison of readings: "sq", the printed p^2 taken literally (complex),
+    |1/(2 rho0 c0) int p^2 r dr dtheta|; "abs2_nor", |p|^2 without the area element r.  These
+    two sum the library's field at the same midpoint nodes on the host."""
     k1 = nvp.wavenumber(med, T["f0"], 1)
     area = 2.0 * math.pi * T["l"] * cap_height(T)
     s = area / points.shape[0]
     centre = (cap_height(T), 0.0, 0.0)
-    pw = nvp.radiated_power(ctx, k1, s, points, centre, T["R"], med["rho0"], med["c0"], n_r, n_theta)
+    if reading == "abs2":
+        pw = nvp.radiated_power(ctx, k1, s, points, centre, T["R"], med["rho0"], med["c0"], n_r, n_theta)
+    else:
+        dr, dth = T["R"] / n_r, 2.0 * math.pi / n_theta
+        r = (np.arange(n_r) + 0.5) * dr
+        th = (np.arange(n_theta) + 0.5) * dth
+        R_, TH = np.meshgrid(r, th, indexing="ij")
+        tg = np.stack([np.full(R_.size, centre[0]), (R_ * np.cos(TH)).ravel(), (R_ * np.sin(TH)).ravel()], axis=1)
+        p = nvp.incident_at(ctx, k1, s, points, torch.from_numpy(tg).to("cuda"), prec=nvp.NVP_C128)
+        p = p.cpu().numpy().reshape(n_r, n_theta)
+        if reading == "sq":
+            pw = abs(np.sum(p * p * R_)) * dr * dth / (2.0 * med["rho0"] * med["c0"])
+        elif reading == "abs2_nor":
+            pw = float(np.sum(np.abs(p) ** 2)) * dr * dth / (2.0 * med["rho0"] * med["c0"])
+        else:
+            raise ValueError("unknown power reading %r" % reading)
     return s * math.sqrt(power / pw)
 
 
@@ -104,7 +125,8 @@ def crossing(fr, err, target=TARGET):
     return float(fr[i - 1] + t * (fr[i] - fr[i - 1]))
 
 
-def study(ctx, T, med, power, d, points, n_max=5, q0=Q0_LADDER, order=1, readings=("ref",), log=None):
+def study(ctx, T, med, power, d, points, n_max=5, q0=Q0_LADDER, order=1, readings=("ref",), power_reading="abs2",
+          log=None):
     """Axis errors of every ladder domain of every harmonic, per reading of the lower harmonics.
 
     Returns {reading: [per-harmonic record]}; each record holds the ladder's boxes, fractions and the
@@ -112,7 +134,7 @@ def study(ctx, T, med, power, d, points, n_max=5, q0=Q0_LADDER, order=1, reading
     every larger one meets 1% and the interpolated 1% crossing."""
     g, i_f, L = reference_mesh(T, med, d, n_max)
     N = [int(v) for v in g.n]
-    s = normalised_incident(ctx, T, med, power, points)
+    s = normalised_incident(ctx, T, med, power, points, reading=power_reading)
     k1 = nvp.wavenumber(med, T["f0"], 1)
     p1 = nvp.incident_field(ctx, k1, s, points, g)
     if log:
@@ -186,18 +208,59 @@ def study(ctx, T, med, power, d, points, n_max=5, q0=Q0_LADDER, order=1, reading
         plan.close()
 
 
-def table(ctx, configs, n_points=4096, readings=("ref", "trunc"), log=None):
-    """Per configuration (name, transducer, medium, power, d): the study's fractions per reading."""
+def table(ctx, configs, n_points=4096, readings=("ref", "trunc"), power_reading="abs2", log=None):
+    """Per configuration (name, transducer, medium, power, d): the study's fractions per reading, and
+    every harmonic's error curve (thresholds, fractions, both axis errors)."""
     from workload import bowl
     rows = []
     for name, T, med, power, d in configs:
         pts = torch.from_numpy(bowl.bowl_points_deserno(T["R"], T["l"], n_points)).to("cuda")
-        res = study(ctx, T, med, power, d, pts, readings=readings, log=log)
-        row = dict(name=name, mesh=res["mesh"], h=res["h"])
+        res = study(ctx, T, med, power, d, pts, readings=readings, power_reading=power_reading, log=log)
+        row = dict(name=name, mesh=res["mesh"], h=res["h"], power_W=power, power_reading=power_reading)
         for reading, recs in res["readings"].items():
             for e in ("everywhere", "inside"):
                 row["%s/%s" % (reading, e)] = [r[e] for r in recs]
             row["%s/rel_norms" % reading] = [r["rel_norm"] for r in recs]
+            row["%s/curves" % reading] = [dict(q0=r["q0"], fractions=r["fractions"], err=r["err"]) for r in recs]
         rows.append(row)
         torch.cuda.empty_cache()
     return rows
+
+
+# The paper's three configurations of the domain table (Section 5).
+def paper_configs(water):
+    from workload import configs
+    W, Lv = water, configs.LIVER
+    return [("H131 water 100W", H131, W, 100.0, H131_D), ("H131 water 150W", H131, W, 150.0, H131_D),
+            ("H131 liver 100W", H131, Lv, 100.0, H131_D)]
+
+
+def main():
+    import argparse
+    import json
+    import time
+    from workload import configs
+    ap = argparse.ArgumentParser(description="Section 5 domain study on the paper's H131 configurations")
+    ap.add_argument("--out", default="truncation_study.json")
+    ap.add_argument("--water", choices=("build", "table"), default="build",
+                    help="water constants: the build's c 1487 / rho 998, or the paper's table c 1480 / rho 1000")
+    ap.add_argument("--readings", default="ref,trunc")
+    ap.add_argument("--only", default="", help="comma-separated configuration names")
+    ap.add_argument("--power-reading", choices=("abs2", "sq", "abs2_nor"), default="abs2")
+    ap.add_argument("--power-scale", type=float, default=1.0, help="multiplies every configuration's power")
+    a = ap.parse_args()
+    water = dict(configs.WATER) if a.water == "build" else dict(configs.WATER, c0=1480.0, rho0=1000.0)
+    cfgs = [(nm, T, med, pw * a.power_scale, d) for nm, T, med, pw, d in paper_configs(water)
+            if not a.only or nm in a.only.split(",")]
+    t0 = time.time()
+    with nvp.Context(0) as ctx:
+        rows = table(ctx, cfgs, readings=tuple(a.readings.split(",")), power_reading=a.power_reading,
+                     log=lambda m: print(m, flush=True))
+    out = dict(water=water, seconds=time.time() - t0, rows=rows)
+    with open(a.out, "w") as fh:
+        json.dump(out, fh, indent=1, default=lambda v: v.tolist() if hasattr(v, "tolist") else float(v))
+    print("wrote %s in %.0f s" % (a.out, time.time() - t0), flush=True)
+
+
+if __name__ == "__main__":
+    main()
