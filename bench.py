@@ -493,6 +493,15 @@ def batch_bench(P, torch, ctx, W, steps, log):
     best = min(res["eager_ms"], res["graph_ms"], res["tuned_graph_ms"], res["tuned_eager_ms"],
                res["grouped_graph_ms"], res["grouped_eager_ms"])
     res["voxels_per_s"] = vox / (best * 1e-3)
+    # the algorithmic bytes of the timed work (spectra cached: transfer + source builds and the five
+    # passes of every harmonic of every transducer) over the best time, against 8 TB/s
+    conv = 0.0
+    for p in probs:
+        ab = alg_bytes(P, p["g1"], p["grids"], 3)
+        conv += sum(ab[k] for k in ("src", "xfwd", "yfwd", "zconv", "yinv", "xinv"))
+    res["alg_bytes"] = conv
+    res["alg_GBs"] = conv / (best * 1e-3) / 1e9
+    res["frac_hbm"] = res["alg_GBs"] / PEAK_HBM_GBS
     b.close()
     log("bench: batched %s" % res)
     return res

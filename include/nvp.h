@@ -295,6 +295,18 @@ nvp_status nvp_difference_term(nvp_ctx *ctx, const nvp_grid *gt, void *out_dev, 
 nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int n_harm,
                             const nvp_grid *g1, const nvp_grid *gn, nvp_prec prec,
                             int transfer_order, nvp_plan **out);
+/* Replaces the grid of harmonic n (2 <= n <= n_harm) of a plan with g, as if
+ * the plan had been made with it: the transfer tables of every harmonic are
+ * laid out again (later harmonics transfer from harmonic n), harmonic n's
+ * kernel spectrum and launch choices start afresh, and the other harmonics
+ * keep their kernel spectra.  Device memory is reused where it is large
+ * enough and grown where not.  Waits for the plan's queued work.  For the
+ * guarded runs of predicted truncation boxes, whose fallback replaces one
+ * harmonic's box with the full one.  NVP_E_INVALID: a bad n or grid, a source
+ * axis shorter than the transfer stencil, or a caller workspace too small
+ * for the new grid (the plan then unchanged); NVP_E_NOMEM: allocation failed
+ * (the plan unchanged). */
+nvp_status nvp_plan_regrid(nvp_plan *plan, int n, const nvp_grid *g);
 /* Device bytes held by the plan: its tables and kernel spectra, plus its own
  * work buffers unless a caller workspace replaces them. */
 nvp_status nvp_plan_workspace_bytes(const nvp_plan *plan, size_t *bytes);

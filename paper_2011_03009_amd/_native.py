@@ -63,6 +63,7 @@ SIGNATURES = {
     "nvp_plan_cascade": (_st, [_vp, ctypes.POINTER(Medium), _d, _i, ctypes.POINTER(Grid), ctypes.POINTER(Grid),
                                _i, _i, ctypes.POINTER(_vp)]),
     "nvp_plan_workspace_bytes": (_st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "nvp_plan_regrid": (_st, [_vp, _i, ctypes.POINTER(Grid)]),
     "nvp_plan_set_kernel_cache": (_st, [_vp, _i]),
     "nvp_plan_set_overlap": (_st, [_vp, _i]),
     "nvp_plan_work_bytes": (_st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),

@@ -266,11 +266,12 @@ def run_boxes(ctx, T, med, incident, fractions, guard=None, shrink=GUARD_SHRINK,
                 u = nvp.box_potential(ctx, nvp.wavenumber(med, T.f0, n), g, f, _focal_index(geo, n, frac[n]),
                                       [whole, small])
                 if abs(u[0] - u[1]) > guard * abs(u[0]):
+                    # fall back to the full box for this harmonic only: the plan is re-laid
+                    # out for its grid, the kernel spectra of the others are kept
                     fallbacks.append(n)
                     frac[n] = (1.0, 1.0, 1.0)
                     grids[n - 2] = geo.grid(n)
-                    plan.close()
-                    plan = nvp.CascadePlan(ctx, med, T.f0, g1, grids, prec=nvp.NVP_C64, order=order)
+                    plan.regrid(n, grids[n - 2])
                     p = plan.execute_harmonic(n, fields)
                     vox += voxels(grids[n - 2])
             fields.append(p)

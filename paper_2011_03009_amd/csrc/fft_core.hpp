@@ -299,11 +299,38 @@ __host__ __device__ constexpr PlanDesc plan_for(int L) {
     }
 }
 
-__host__ __device__ constexpr int plan_threads(int L) { return plan_for(L).P; }
-// Whether a column's threads fit one wavefront with no column straddling two.
-__host__ __device__ constexpr bool plan_wave_local(int L) {
-    return plan_threads(L) > 0 && plan_threads(L) <= 64 && 64 % plan_threads(L) == 0;
+// Registers (complex values) per thread of the plan of length L run by P
+// threads per column: the largest butterfly share times its radix.
+__host__ __device__ constexpr int plan_regs(int L, int P) {
+    const PlanDesc d = plan_for(L);
+    int e = 0;
+    for (int s = 0; s < d.S; ++s) {
+        const int r = d.r[s], per = (L / r + P - 1) / P;
+        e = per * r > e ? per * r : e;
+    }
+    return e;
 }
+__host__ __device__ constexpr int plan_rmax(int L) {
+    const PlanDesc d = plan_for(L);
+    int m = 0;
+    for (int s = 0; s < d.S; ++s) m = d.r[s] > m ? d.r[s] : m;
+    return m;
+}
+
+// Threads per column of the plan.
+template <typename R> __host__ __device__ constexpr int col_threads(int L) { return plan_for(L).P; }
+// Threads per column of the FP64 octant-row pass of the kernel spectrum (its
+// first pass, fused with the tabulation): twice the plan's wherever a thread
+// would otherwise hold more than 8 complex values and every thread keeps a
+// butterfly in every stage, staying within one wavefront where the plan's
+// column does.  (The FP64 strided passes measured faster on the plan's own.)
+__host__ __device__ constexpr int kz_threads(int L) {
+    const int P = plan_for(L).P;
+    return (plan_regs(L, P) > 8 && 2 * P <= L / plan_rmax(L) && (2 * P <= 64 || P > 64)) ? 2 * P : P;
+}
+// Whether P threads per column fit one wavefront with no column straddling two.
+__host__ __device__ constexpr bool wave_local_p(int P) { return P > 0 && P <= 64 && 64 % P == 0; }
+template <typename R> __host__ __device__ constexpr bool wave_local(int L) { return wave_local_p(col_threads<R>(L)); }
 
 // Radix of stage s and product of the radices before it, for the plan run
 // forward (rev = false) or in reverse radix order (rev = true).
@@ -385,10 +412,11 @@ __device__ __forceinline__ void wave_sync() {
 // WAVE = true: each column's P <= 64 threads lie in one wavefront (and no
 // other wave touches its LDS slot), so stages synchronise per wave instead of
 // per workgroup.  Tw: tw(e) -> entry e of this direction's twiddle table.
-template <typename R, int L, bool REV = false, bool WAVE = false> struct Fft {
+// PT: threads per column, 0 for the plan's own.
+template <typename R, int L, bool REV = false, bool WAVE = false, int PT = 0> struct Fft {
     static constexpr PlanDesc D = plan_for(L);
     static constexpr int S = D.S;
-    static constexpr int P = D.P;  // threads per column
+    static constexpr int P = PT ? PT : col_threads<R>(L);  // threads per column
     static_assert(S > 0, "unsupported FFT length");
     static_assert(!WAVE || (P <= 64 && 64 % P == 0), "a wave-local column needs at most 64 threads, 64 % P == 0");
     static constexpr int TW_BASE = REV ? plan_tw_len(L, false) : 0;  // offset in the two-direction table

@@ -211,7 +211,7 @@ __device__ __forceinline__ void strided_tile(Ld ld, St st, const cx<R> *__restri
 }
 
 template <typename R, int L, int T, int SG, bool MIRROR, class Ld, class St>
-__global__ void __launch_bounds__(T *plan_threads(L))
+__global__ void __launch_bounds__(T *col_threads<R>(L))
 k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, int64_t inner) {
     strided_tile<R, L, T, SG, MIRROR>(ld, st, tw, inner, blockIdx.x, blockIdx.y);
 }
@@ -221,7 +221,7 @@ k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, int64_t inner) {
 // its tile (bx, o) follows from the block's offset in that range.  Each
 // task's arguments are read once per workgroup (uniform loads).
 template <typename R, int L, int T, int SG, bool SC>
-__global__ void __launch_bounds__(T *plan_threads(L))
+__global__ void __launch_bounds__(T *col_threads<R>(L))
 k_strided_multi(const StridedTaskArgs *__restrict__ tasks, int ntasks, const cx<R> *__restrict__ tw) {
     const int64_t b = blockIdx.x;
     int k = 0;
@@ -238,7 +238,7 @@ k_strided_multi(const StridedTaskArgs *__restrict__ tasks, int ntasks, const cx<
 // column's LDS slot (a rolled loop, so the interpolation code exists once),
 // then the FFT reads its first stage from there.  Column col = iy * Nz + iz.
 template <typename R, int L, int T, int K, class St>
-__global__ void __launch_bounds__(T *plan_threads(L))
+__global__ void __launch_bounds__(T *col_threads<R>(L))
 k_xsrc(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t inner) {
     using F = Fft<R, L>;
     constexpr int NT = plan_tw_len(L, false);
@@ -272,7 +272,7 @@ k_xsrc(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t inner) {
 // written to rows 0 .. Nx-1.  The host picks `chunk` so that the staged rows
 // of all fields fit in L - Nx rows.
 template <typename R, int L, int T, int K, class St>
-__global__ void __launch_bounds__(T *plan_threads(L))
+__global__ void __launch_bounds__(T *col_threads<R>(L))
 k_xsrc_staged(LdSource<R, K> src, St st, const cx<R> *__restrict__ tw, int64_t inner, int chunk) {
     using F = Fft<R, L>;
     constexpr int P = F::P;
@@ -374,7 +374,7 @@ template <typename R, int L, int SLOTS>
 __device__ __forceinline__ void zconv_block(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx,
                                             int64_t My, int Nz, int64_t Hy, int64_t n_quads,
                                             const cx<R> *__restrict__ tw, int64_t block) {
-    constexpr bool WL = plan_wave_local(L);
+    constexpr bool WL = wave_local<R>(L);
     using F = Fft<R, L, false, WL>;
     using G = Fft<R, L, true, WL>;
     constexpr int EO = F::EOUT;
@@ -437,7 +437,7 @@ __device__ __forceinline__ void zconv_block(cx<R> *__restrict__ buf, const cx<R>
 }
 
 template <typename R, int L, int SLOTS>
-__global__ void __launch_bounds__(SLOTS *plan_threads(L))
+__global__ void __launch_bounds__(SLOTS *col_threads<R>(L))
 k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int64_t My, int Nz, int64_t Hy,
         int64_t n_quads, const cx<R> *__restrict__ tw) {
     zconv_block<R, L, SLOTS>(buf, khat, Mx, My, Nz, Hy, n_quads, tw, blockIdx.x);
@@ -445,7 +445,7 @@ k_zconv(cx<R> *__restrict__ buf, const cx<R> *__restrict__ khat, int64_t Mx, int
 
 // Multi-task z pass (batches), laid out like k_strided_multi.
 template <typename R, int L, int SLOTS>
-__global__ void __launch_bounds__(SLOTS *plan_threads(L))
+__global__ void __launch_bounds__(SLOTS *col_threads<R>(L))
 k_zconv_multi(const ZconvTaskArgs *__restrict__ tasks, int ntasks, const cx<R> *__restrict__ tw) {
     const int64_t b = blockIdx.x;
     int k = 0;
@@ -463,11 +463,11 @@ k_zconv_multi(const ZconvTaskArgs *__restrict__ tasks, int ntasks, const cx<R> *
 // the FFT of the even extension to length L is written back as the row's first
 // Hz outputs.
 template <int L, int PW, bool TWL>
-__global__ void __launch_bounds__(PW *plan_threads(L))
+__global__ void __launch_bounds__(PW *kz_threads(L))
 k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, int64_t Nz,
      const double2 *__restrict__ ktab, const double2 *__restrict__ tw) {
-    constexpr bool WL = plan_wave_local(L);
-    using F = Fft<double, L, false, WL>;
+    constexpr bool WL = wave_local_p(kz_threads(L));
+    using F = Fft<double, L, false, WL, kz_threads(L)>;
     constexpr int HZ = L / 2 + 1;
     constexpr int SL = slot_len<double>(L);
     constexpr int NT = plan_tw_len(L, false);

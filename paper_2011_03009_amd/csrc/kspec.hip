@@ -98,7 +98,6 @@ int zconv_quads_override() {
     }();
     return v;
 }
-int threads_per_column(int L) { return plan_threads(L); }
 
 int strided_tile_cols(int L, int dbl) { return dbl ? strided_cols<double>(L) : strided_cols<float>(L); }
 

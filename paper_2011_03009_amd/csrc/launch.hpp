@@ -19,7 +19,6 @@ bool length_supported(int L);
 // Tuning switch read once from the environment (NVP_ZCONV_QUADS): 1 forces one
 // pencil quad per z-pass workgroup; anything else keeps the default.
 int zconv_quads_override();
-int threads_per_column(int L);
 
 // Generic strided pass: element m of column (o, col) is read at
 // in[o*in_os + m*in_ms + col] and written to out[o*out_os + m*out_ms + col],

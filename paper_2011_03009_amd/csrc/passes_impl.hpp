@@ -9,10 +9,10 @@ namespace nvp {
 // per row access, about 256 threads per workgroup.
 template <typename R> constexpr int strided_cols(int L) {
     const int lo = sizeof(R) == 4 ? 16 : 8, hi = sizeof(R) == 4 ? 64 : 32;
-    const int t = 256 / plan_threads(L);
+    const int t = 256 / col_threads<R>(L);
     int c = t < lo ? lo : (t > hi ? hi : t);
     // the workgroup's columns must fit the 160 KiB of LDS and 1024 threads
-    while (c > 1 && ((size_t)c * L * sizeof(cx<R>) > 163840 || c * plan_threads(L) > 1024)) c /= 2;
+    while (c > 1 && ((size_t)c * L * sizeof(cx<R>) > 163840 || c * col_threads<R>(L) > 1024)) c /= 2;
     return c;
 }
 
@@ -26,12 +26,12 @@ template <typename R> constexpr bool contig_tw_lds(int L) {
 // LDS <= 128 KiB (with the staged twiddles), and whole wavefronts (a multiple
 // of 64 / P pencils where a pencil is wave-local).
 template <typename R> constexpr int contig_pencils(int L) {
-    const int P = plan_threads(L);
+    const int P = kz_threads(L);
     const int by_threads = 256 / P > 0 ? 256 / P : 1;
     const int tw = contig_tw_lds<R>(L) ? twiddle_table_len(L) * (int)sizeof(cx<R>) : 0;
     const int by_lds = (int)((131072 - tw) / (slot_len<R>(L) * (int)sizeof(cx<R>)));
     int p = by_threads < by_lds ? by_threads : by_lds;
-    const int unit = plan_wave_local(L) ? 64 / P : 1;
+    const int unit = wave_local_p(P) ? 64 / P : 1;
     p = (p / unit) * unit;
     return p > 0 ? p : unit;
 }
@@ -65,7 +65,7 @@ hipError_t strided_v(const StridedArgs &a, const void *tw, hipStream_t s) {
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
     dim3 grid((unsigned)((a.inner + T - 1) / T), (unsigned)a.outer);
-    hipLaunchKernelGGL(kern, grid, dim3(T * plan_threads(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
+    hipLaunchKernelGGL(kern, grid, dim3(T * col_threads<R>(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
                        a.inner);
     return hipGetLastError();
 }
@@ -127,13 +127,13 @@ template <typename R, int L, int K> hipError_t xsrc_impl_k(const SourceArgs &a, 
         auto kern = k_xsrc_staged<R, L, T, K, St>;
         static const hipError_t attr = allow_lds(kern, lds);
         if (attr != hipSuccess) return attr;
-        hipLaunchKernelGGL(kern, grid, dim3(T * plan_threads(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
+        hipLaunchKernelGGL(kern, grid, dim3(T * col_threads<R>(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
                            a.inner, a.chunk);
     } else {
         auto kern = k_xsrc<R, L, T, K, St>;
         static const hipError_t attr = allow_lds(kern, lds);
         if (attr != hipSuccess) return attr;
-        hipLaunchKernelGGL(kern, grid, dim3(T * plan_threads(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
+        hipLaunchKernelGGL(kern, grid, dim3(T * col_threads<R>(L)), lds, s, ld, st, static_cast<const cx<R> *>(tw),
                            a.inner);
     }
     return hipGetLastError();
@@ -149,12 +149,12 @@ template <typename R, int L, int SLOTS>
 hipError_t zconv_slots(void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw, hipStream_t s) {
     auto kern = k_zconv<R, L, SLOTS>;
     constexpr size_t lds = (size_t)SLOTS * slot_len<R>(L) * sizeof(cx<R>);
-    static_assert(lds <= 163840 && SLOTS * plan_threads(L) <= 1024, "z-pass workgroup too large");
+    static_assert(lds <= 163840 && SLOTS * col_threads<R>(L) <= 1024, "z-pass workgroup too large");
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
     const int64_t Hx = Mx / 2 + 1, Hy = My / 2 + 1, nq = Hx * Hy;
     if (4 * nq > 0x7fffffff - SLOTS) return hipErrorInvalidValue;  // pencil indices are 32-bit in the kernel
-    hipLaunchKernelGGL(kern, dim3((unsigned)((4 * nq + SLOTS - 1) / SLOTS)), dim3(SLOTS * plan_threads(L)), lds, s,
+    hipLaunchKernelGGL(kern, dim3((unsigned)((4 * nq + SLOTS - 1) / SLOTS)), dim3(SLOTS * col_threads<R>(L)), lds, s,
                        static_cast<cx<R> *>(buf), static_cast<const cx<R> *>(khat), Mx, My, Nz, Hy, nq,
                        static_cast<const cx<R> *>(tw));
     return hipGetLastError();
@@ -164,14 +164,14 @@ hipError_t zconv_slots(void *buf, const void *khat, int64_t Mx, int64_t My, int 
 // of esz bytes within `lds_cap` bytes and `thr_cap` threads.
 constexpr bool zconv_fits(int L, size_t esz, int slots, size_t lds_cap, int thr_cap) {
     const size_t slot = (size_t)(esz == sizeof(float2) ? slot_len<float>(L) : slot_len<double>(L)) * esz;
-    return (size_t)slots * slot <= lds_cap && slots * plan_threads(L) <= thr_cap;
+    return (size_t)slots * slot <= lds_cap && slots * plan_for(L).P <= thr_cap;
 }
 
 // Pencils per z-pass workgroup by default: two quads (8) when that keeps the
 // workgroup within 128 threads and 80 KiB of LDS, else one quad (4);
 // transforms too long for a quad in 160 KiB take 2 or 1.
 constexpr int zconv_slots_for(int L, size_t esz) {
-    return 4 * plan_threads(L) <= 128 && zconv_fits(L, esz, 8, 81920, 1024) ? 8
+    return 4 * plan_for(L).P <= 128 && zconv_fits(L, esz, 8, 81920, 1024) ? 8
          : zconv_fits(L, esz, 4, 163840, 1024) ? 4
          : zconv_fits(L, esz, 2, 163840, 1024) ? 2 : 1;
 }
@@ -196,12 +196,12 @@ hipError_t kz_impl(double2 *out, const int64_t H[3], const int64_t N[3], const d
     constexpr bool TWL = contig_tw_lds<double>(L);
     auto kern = k_kz<L, PW, TWL>;
     constexpr size_t lds = ((size_t)PW * slot_len<double>(L) + (TWL ? plan_tw_len(L, false) : 0)) * sizeof(double2);
-    static_assert(lds <= 163840 && PW * plan_threads(L) <= 1024, "kernel-spectrum workgroup too large");
+    static_assert(lds <= 163840 && PW * kz_threads(L) <= 1024, "kernel-spectrum workgroup too large");
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
     const int64_t rows = H[0] * H[1];
     if (rows > 0x7fffffff - PW) return hipErrorInvalidValue;  // row indices are 32-bit in the kernel
-    hipLaunchKernelGGL(kern, dim3((unsigned)((rows + PW - 1) / PW)), dim3(PW * plan_threads(L)), lds, s, out, H[0],
+    hipLaunchKernelGGL(kern, dim3((unsigned)((rows + PW - 1) / PW)), dim3(PW * kz_threads(L)), lds, s, out, H[0],
                        H[1], N[0], N[1], N[2], ktab, static_cast<const double2 *>(tw));
     return hipGetLastError();
 }
@@ -213,7 +213,7 @@ hipError_t strided_multi_v(const StridedTaskArgs *tasks, int ntasks, int64_t blo
     constexpr size_t lds = strided_lds<R, L, T, false>();
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(T * plan_threads(L)), lds, s, tasks, ntasks,
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(T * col_threads<R>(L)), lds, s, tasks, ntasks,
                        static_cast<const cx<R> *>(tw));
     return hipGetLastError();
 }
@@ -235,7 +235,7 @@ hipError_t zconv_multi_impl(const ZconvTaskArgs *tasks, int ntasks, int64_t bloc
     constexpr size_t lds = (size_t)SLOTS * slot_len<R>(L) * sizeof(cx<R>);
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(SLOTS * plan_threads(L)), lds, s, tasks, ntasks,
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(SLOTS * col_threads<R>(L)), lds, s, tasks, ntasks,
                        static_cast<const cx<R> *>(tw));
     return hipGetLastError();
 }

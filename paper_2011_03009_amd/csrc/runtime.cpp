@@ -85,6 +85,7 @@ struct Harm {
     int64_t M[3]{};
     double kr = 0, ki = 0, Cn = 0;
     void *khat = nullptr;
+    size_t khat_cap = 0;  // bytes allocated at khat
     bool khat_ok = false;
     int chunk = 0;  // x-chunk of the staged source build (0: direct gathers)
     int64_t src_lds = 0;  // > 0: separate tiled source kernel with this many LDS entries
@@ -919,60 +920,34 @@ nvp_status nvp_volume_potential_box(nvp_ctx *ctx, double k_re, double k_im, cons
     return convolve(ctx, nullptr, prec, g, M, c.khat, c.A, c.B, f, nullptr, u_dev, sc);
 }
 
-nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int n_harm, const nvp_grid *g1,
-                            const nvp_grid *gn, nvp_prec prec, int transfer_order, nvp_plan **out) {
-    if (!ctx) return NVP_E_INVALID;
-    if (!out) return fail(ctx, NVP_E_INVALID, "out is null");
-    *out = nullptr;
-    if (!medium_ok(med) || !finite_pos(f0) || !grid_ok(g1) || !gn || (prec != NVP_C64 && prec != NVP_C128))
-        return fail(ctx, NVP_E_INVALID, "nvp_plan_cascade: bad argument");
-    if (n_harm < 2 || n_harm > NVP_MAX_FIELDS + 1)
-        return fail(ctx, n_harm < 2 ? NVP_E_INVALID : NVP_E_UNSUPPORTED, "nvp_plan_cascade: n_harm out of range");
-    if (transfer_order != 1 && transfer_order != 3)
-        return fail(ctx, NVP_E_UNSUPPORTED, "nvp_plan_cascade: transfer order must be 1 or 3");
-    for (int i = 0; i < n_harm - 1; ++i)
-        if (!grid_ok(&gn[i])) return fail(ctx, NVP_E_INVALID, "nvp_plan_cascade: bad harmonic grid");
-    NVP_HIP(ctx, hipSetDevice(ctx->device));
-
-    nvp_plan *p = new (std::nothrow) nvp_plan;
-    if (!p) return fail(ctx, NVP_E_NOMEM, "plan allocation");
-    p->ctx = ctx;
-    p->quad = ctx->quad;
-    p->prec = prec;
-    p->order = transfer_order;
-    p->med = *med;
-    p->f0 = f0;
-    p->n_harm = n_harm;
-    p->g1 = *g1;
-    p->h.resize(n_harm - 1);
-    const int K = transfer_order + 1;
-    const size_t rs = prec == NVP_C64 ? 4 : 8;
+// Grids, constants, transfer tables (built on the host into `host`) and
+// source-build choices of every harmonic of plan p for the harmonic grids gn,
+// and the sizes of its pass buffers.  Sets no device memory.
+nvp_status plan_layout(nvp_ctx *ctx, nvp_plan *p, const nvp_grid *gn, std::vector<unsigned char> &host,
+                       size_t *tbytes_out, size_t *maxA_out, size_t *maxB_out) {
+    const int K = p->order + 1;
+    const size_t rs = p->prec == NVP_C64 ? 4 : 8;
     size_t maxA = 0, maxB = 0, tbytes = 0;
     auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    for (int i = 0; i < n_harm - 1; ++i) {
+    for (int i = 0; i < p->n_harm - 1; ++i) {
         Harm &h = p->h[i];
         h.n = i + 2;
         h.g = gn[i];
         nvp_status st = check_grid_lengths(ctx, &h.g, h.M);
-        if (st) {
-            delete p;
-            return st;
-        }
-        nvp_wavenumber(med, f0, h.n, &h.kr, &h.ki);
-        nvp_cascade_constant(med, f0, h.n, &h.Cn);
-        size_t a = bytesA(&h.g, h.M, prec), b = bytesB(&h.g, h.M, prec);
+        if (st) return st;
+        nvp_wavenumber(&p->med, p->f0, h.n, &h.kr, &h.ki);
+        nvp_cascade_constant(&p->med, p->f0, h.n, &h.Cn);
+        size_t a = bytesA(&h.g, h.M, p->prec), b = bytesB(&h.g, h.M, p->prec);
         maxA = a > maxA ? a : maxA;
         maxB = b > maxB ? b : maxB;
         for (int m = 1; m < h.n; ++m) {
-            const nvp_grid &src = m == 1 ? *g1 : gn[m - 2];
+            const nvp_grid &src = m == 1 ? p->g1 : gn[m - 2];
             HarmField &f = h.f[m - 1];
             f.identity = same_grid(src, h.g) ? 1 : 0;
             if (f.identity) continue;
             for (int ax = 0; ax < 3; ++ax) {
-                if (src.n[ax] < K) {
-                    delete p;
+                if (src.n[ax] < K)
                     return fail(ctx, NVP_E_INVALID, "a source grid axis is shorter than the transfer stencil");
-                }
                 f.off_b[ax] = tbytes;
                 tbytes = align(tbytes + (size_t)h.g.n[ax] * sizeof(int));
                 f.off_w[ax] = tbytes;
@@ -981,16 +956,16 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
         }
     }
     // tables on the host, then one upload
-    std::vector<unsigned char> host(tbytes ? tbytes : 1);
+    host.assign(tbytes ? tbytes : 1, 0);
     for (auto &h : p->h) {
         for (int m = 1; m < h.n; ++m) {
-            const nvp_grid &src = m == 1 ? *g1 : gn[m - 2];
+            const nvp_grid &src = m == 1 ? p->g1 : gn[m - 2];
             HarmField &f = h.f[m - 1];
             if (f.identity) continue;
             for (int ax = 0; ax < 3; ++ax) {
                 std::vector<double> w((size_t)h.g.n[ax] * K);
                 int *base = reinterpret_cast<int *>(host.data() + f.off_b[ax]);
-                axis_table(h.g.origin[ax], h.g.h, h.g.n[ax], src.origin[ax], src.h, src.n[ax], transfer_order, base,
+                axis_table(h.g.origin[ax], h.g.h, h.g.n[ax], src.origin[ax], src.h, src.n[ax], p->order, base,
                            w.data());
                 if (rs == 8) std::memcpy(host.data() + f.off_w[ax], w.data(), w.size() * 8);
                 else {
@@ -1055,7 +1030,48 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
         const int64_t elems = msx * msy * msz + msx * msy * T[2];
         if (!small) h.src_lds = 0;
         else if (!any) h.src_lds = 1;  // every field already on the target grid: no staging
-        else if (elems * (int64_t)csize(prec) <= 98304 && msx <= T[0] - 1 + K) h.src_lds = elems;
+        else if (elems * (int64_t)csize(p->prec) <= 98304 && msx <= T[0] - 1 + K) h.src_lds = elems;
+    }
+    *tbytes_out = tbytes;
+    *maxA_out = maxA;
+    *maxB_out = maxB;
+    return NVP_OK;
+}
+
+nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int n_harm, const nvp_grid *g1,
+                            const nvp_grid *gn, nvp_prec prec, int transfer_order, nvp_plan **out) {
+    if (!ctx) return NVP_E_INVALID;
+    if (!out) return fail(ctx, NVP_E_INVALID, "out is null");
+    *out = nullptr;
+    if (!medium_ok(med) || !finite_pos(f0) || !grid_ok(g1) || !gn || (prec != NVP_C64 && prec != NVP_C128))
+        return fail(ctx, NVP_E_INVALID, "nvp_plan_cascade: bad argument");
+    if (n_harm < 2 || n_harm > NVP_MAX_FIELDS + 1)
+        return fail(ctx, n_harm < 2 ? NVP_E_INVALID : NVP_E_UNSUPPORTED, "nvp_plan_cascade: n_harm out of range");
+    if (transfer_order != 1 && transfer_order != 3)
+        return fail(ctx, NVP_E_UNSUPPORTED, "nvp_plan_cascade: transfer order must be 1 or 3");
+    for (int i = 0; i < n_harm - 1; ++i)
+        if (!grid_ok(&gn[i])) return fail(ctx, NVP_E_INVALID, "nvp_plan_cascade: bad harmonic grid");
+    NVP_HIP(ctx, hipSetDevice(ctx->device));
+
+    nvp_plan *p = new (std::nothrow) nvp_plan;
+    if (!p) return fail(ctx, NVP_E_NOMEM, "plan allocation");
+    p->ctx = ctx;
+    p->quad = ctx->quad;
+    p->prec = prec;
+    p->order = transfer_order;
+    p->med = *med;
+    p->f0 = f0;
+    p->n_harm = n_harm;
+    p->g1 = *g1;
+    p->h.resize(n_harm - 1);
+    std::vector<unsigned char> host;
+    size_t tbytes = 0, maxA = 0, maxB = 0;
+    {
+        nvp_status st = plan_layout(ctx, p, gn, host, &tbytes, &maxA, &maxB);
+        if (st) {
+            delete p;
+            return st;
+        }
     }
     hipError_t e = hipSuccess;
     if (tbytes) e = dev_malloc((void **)&p->tables, tbytes);
@@ -1064,7 +1080,8 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
     for (auto &h : p->h) {
         if (e != hipSuccess) break;
         e = dev_malloc((void **)&h.khat, khat_bytes(h.M, prec));
-        p->bytes_khat += khat_bytes(h.M, prec);
+        h.khat_cap = khat_bytes(h.M, prec);
+        p->bytes_khat += h.khat_cap;
     }
     if (e == hipSuccess && tbytes) e = hipMemcpy(p->tables, host.data(), tbytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -1080,6 +1097,103 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
     p->bytes_B = maxB;
     p->bytes_tables = tbytes;
     *out = p;
+    return NVP_OK;
+}
+
+nvp_status nvp_plan_regrid(nvp_plan *plan, int n, const nvp_grid *g) {
+    if (!plan) return NVP_E_INVALID;
+    nvp_ctx *ctx = plan->ctx;
+    if (n < 2 || n > plan->n_harm || !grid_ok(g)) return fail(ctx, NVP_E_INVALID, "nvp_plan_regrid: bad argument");
+    NVP_HIP(ctx, hipSetDevice(ctx->device));
+    // queued work of the plan may still read its tables and buffers
+    NVP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (plan->side) NVP_HIP(ctx, hipStreamSynchronize(plan->side));
+    std::vector<nvp_grid> gn(plan->n_harm - 1);
+    for (int i = 0; i < plan->n_harm - 1; ++i) gn[i] = plan->h[i].g;
+    gn[n - 2] = *g;
+    // lay out a copy first, so that a refused grid leaves the plan as it was
+    nvp_plan q;
+    q.ctx = ctx;
+    q.order = plan->order;
+    q.prec = plan->prec;
+    q.med = plan->med;
+    q.f0 = plan->f0;
+    q.n_harm = plan->n_harm;
+    q.g1 = plan->g1;
+    q.h.resize(plan->n_harm - 1);
+    std::vector<unsigned char> host;
+    size_t tbytes = 0, maxA = 0, maxB = 0;
+    nvp_status st = plan_layout(ctx, &q, gn.data(), host, &tbytes, &maxA, &maxB);
+    if (st) return st;
+    if (!plan->own_work && (maxA > plan->bytes_A || maxB > plan->bytes_B))
+        return fail(ctx, NVP_E_INVALID, "nvp_plan_regrid: the caller workspace is too small for this grid");
+    Harm &hn = q.h[n - 2];
+    const size_t kb = khat_bytes(hn.M, plan->prec);
+    // device memory that must grow
+    void *tables = plan->tables, *khat = plan->h[n - 2].khat, *A = nullptr, *B = nullptr;
+    hipError_t e = hipSuccess;
+    if (tbytes > plan->bytes_tables) e = dev_malloc(&tables, tbytes);
+    if (e == hipSuccess && kb > plan->h[n - 2].khat_cap) e = dev_malloc(&khat, kb);
+    if (e == hipSuccess && plan->own_work && maxA > plan->bytes_A) e = dev_malloc(&A, maxA);
+    if (e == hipSuccess && plan->own_work && maxB > plan->bytes_B) e = dev_malloc(&B, maxB);
+    if (e == hipSuccess && tbytes) e = hipMemcpy(tables, host.data(), tbytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (tables != plan->tables) (void)hipFree(tables);
+        if (khat != plan->h[n - 2].khat) (void)hipFree(khat);
+        if (A) (void)hipFree(A);
+        if (B) (void)hipFree(B);
+        return hip_fail(ctx, "nvp_plan_regrid: allocation", e);
+    }
+    if (tables != plan->tables) {
+        (void)hipFree(plan->tables);
+        plan->tables = tables;
+        plan->bytes_tables = tbytes;
+    }
+    if (khat != plan->h[n - 2].khat) {
+        (void)hipFree(plan->h[n - 2].khat);
+        plan->bytes_khat += kb - plan->h[n - 2].khat_cap;
+        plan->h[n - 2].khat = khat;
+        plan->h[n - 2].khat_cap = kb;
+    }
+    if (A) {
+        (void)hipFree(plan->A);
+        plan->A = A;
+        plan->bytes_A = maxA;
+    }
+    if (B) {
+        (void)hipFree(plan->B);
+        plan->B = B;
+        plan->bytes_B = maxB;
+    }
+    // the side stream's scratch is sized for the grids: made again when next needed
+    if (plan->own_work && plan->kscr) {
+        size_t ks, kt;
+        side_sizes(&q, &ks, &kt);
+        if (ks + kt > plan->bytes_side) {
+            (void)hipFree(plan->kscr);
+            (void)hipFree(plan->ktab);
+            plan->kscr = plan->ktab = nullptr;
+            plan->bytes_side = 0;
+        }
+    }
+    // every harmonic takes the new layout (later harmonics transfer from harmonic n's new grid);
+    // harmonic n's spectrum and launch choices start afresh, the others keep theirs
+    for (int i = 0; i < plan->n_harm - 1; ++i) {
+        Harm &h = plan->h[i];
+        const Harm &o = q.h[i];
+        h.g = o.g;
+        std::memcpy(h.M, o.M, sizeof h.M);
+        h.kr = o.kr;
+        h.ki = o.ki;
+        h.Cn = o.Cn;
+        h.chunk = o.chunk;
+        h.src_lds = o.src_lds;
+        std::memcpy(h.f, o.f, sizeof h.f);
+        if (i == n - 2) {
+            h.khat_ok = false;
+            h.tune = Tune{};
+        }
+    }
     return NVP_OK;
 }
 

@@ -366,6 +366,13 @@ class CascadePlan:
         g = self.g1 if n == 1 else self.grids[n - 2]
         return tuple(g.n)
 
+    def regrid(self, n, g):
+        """Replace harmonic n's grid (nvp_plan_regrid): tables laid out again, the other
+        harmonics' kernel spectra kept."""
+        g = grid(g)
+        _check(_native.lib().nvp_plan_regrid(self.handle, int(n), ctypes.byref(g)), self.ctx.handle)
+        self.grids[n - 2] = g
+
     def workspace_bytes(self):
         b = ctypes.c_size_t()
         _check(_native.lib().nvp_plan_workspace_bytes(self.handle, ctypes.byref(b)))

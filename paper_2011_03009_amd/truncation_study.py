@@ -14,7 +14,9 @@ fractions):
   ||p_n - p_n^r|| / ||p_1^r||, by the midpoint rule on the reference mesh's
   axis voxels.
 - A domain's size is given as fractions of the reference domain's:
-  fraction_x = L' / L (pre-focal lengths), fraction_yz = w' / w (widths).
+  fraction_x = L' / L (pre-focal lengths), fraction_yz = w' / w (widths),
+  and the whole x extent (L' + d) / (L + d) (the paper's plots put "the
+  fraction of the total domain in the x-direction" on their axis).
 
 Where the paper is silent the study runs each reading side by side, so that
 the one that reproduces the printed table can be named:
@@ -103,10 +105,13 @@ def domain_box(qbox, i_f, n):
 
 
 def fractions(box, i_f, n):
-    """fraction_x = L' / L by voxel edges (pre-focal), fraction_yz = w' / w (the wider of y and z)."""
+    """(fraction_x, fraction_yz, extent_x): fraction_x = L' / L by voxel edges (the pre-focal lengths),
+    fraction_yz = w' / w (the wider of y and z), extent_x = (L' + d) / (L + d) (the whole x extents,
+    the post-focal part being the same)."""
     fx = (i_f[0] - box[0] + 0.5) / (i_f[0] + 0.5)
     fyz = max((box[4] - box[1] + 1) / n[1], (box[5] - box[2] + 1) / n[2])
-    return fx, fyz
+    ex = (box[3] - box[0] + 1) / n[0]
+    return fx, fyz, ex
 
 
 def crossing(fr, err, target=TARGET):
@@ -123,6 +128,25 @@ def crossing(fr, err, target=TARGET):
     a, b = math.log(err[i - 1]), math.log(max(err[i], 1e-300))
     t = (a - math.log(target)) / (a - b) if a != b else 1.0
     return float(fr[i - 1] + t * (fr[i] - fr[i - 1]))
+
+
+def read_off(fr, err, q0, step=1.0, target=TARGET):
+    """The fractions at which the error curve crosses the target, read as off a plot of it: only the
+    thresholds on whole multiples of `step` (the paper's figures show its convergence at whole
+    values of Q0), the smallest box from which on every larger one meets the target, and a straight
+    line in error between it and the next smaller box."""
+    idx = [i for i, q in enumerate(q0) if abs(q / step - round(q / step)) < 1e-9]
+    fr, err = np.asarray(fr)[idx], np.asarray(err)[idx]
+    ok = err < target
+    i = len(ok)
+    while i > 0 and ok[i - 1]:
+        i -= 1
+    if i == len(ok):
+        return tuple(float("nan") for _ in range(fr.shape[1]))
+    if i == 0:
+        return tuple(float(v) for v in fr[0])
+    t = (err[i - 1] - target) / (err[i - 1] - err[i]) if err[i - 1] != err[i] else 1.0
+    return tuple(float(v) for v in fr[i - 1] + t * (fr[i] - fr[i - 1]))
 
 
 def study(ctx, T, med, power, d, points, n_max=5, q0=Q0_LADDER, order=1, readings=("ref",), power_reading="abs2",
@@ -194,13 +218,14 @@ def study(ctx, T, med, power, d, points, n_max=5, q0=Q0_LADDER, order=1, reading
                     i = len(ok)
                     while i > 0 and ok[i - 1]:
                         i -= 1
-                    need = fr[i] if i < len(ok) else np.ones(2)
-                    rec[name] = dict(ladder=(float(need[0]), float(need[1])),
-                                     crossing=(crossing(fr[:, 0], errs[n][:, e]), crossing(fr[:, 1], errs[n][:, e])))
+                    need = fr[i] if i < len(ok) else np.ones(3)
+                    rec[name] = dict(ladder=tuple(float(v) for v in need),
+                                     crossing=tuple(crossing(fr[:, c], errs[n][:, e]) for c in range(3)),
+                                     read_off=read_off(fr, errs[n][:, e], q0))
                 recs.append(rec)
                 if log:
-                    log("%s p%d: 1%% at x %.2f y/z %.2f (error everywhere on the axis), x %.2f y/z %.2f (zero "
-                        "outside the domain); ||p%d|| / ||p1|| = %.3g" % (
+                    log("%s p%d: 1%% at L'/L %.2f, w'/w %.2f, extent %.2f (error everywhere on the axis); "
+                        "%.2f, %.2f, %.2f (zero outside the domain); ||p%d|| / ||p1|| = %.3g" % (
                             reading, n, *rec["everywhere"]["ladder"], *rec["inside"]["ladder"], n, rec["rel_norm"]))
             out[reading] = recs
         return dict(mesh=N, h=g.h, i_f=i_f, L=L, readings=out)

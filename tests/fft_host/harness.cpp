@@ -200,7 +200,7 @@ template <typename R> struct Checker {
 
     // the z pass: forward kept in registers, product, reverse-order inverse
     void conv() {
-        constexpr bool WL = plan_wave_local(L);
+        constexpr bool WL = wave_local<R>(L);
         using F = Fft<R, L, false, WL>;
         using G = Fft<R, L, true, WL>;
         auto x = random_column<R>(L, L / 2, 3);
@@ -275,8 +275,9 @@ template <typename R> struct Checker {
     // L/2+1 entries are staged as complex values, column-interleaved, in the
     // LDS array that the transform then reuses as one real plane per exchange.
     void kz() {
-        constexpr bool WL = plan_wave_local(L);
-        using F = Fft<R, L, false, WL>;
+        constexpr int PK = sizeof(R) == 8 ? kz_threads(L) : plan_for(L).P;
+        constexpr bool WL = wave_local_p(PK);
+        using F = Fft<R, L, false, WL, PK>;
         auto h = random_column<R>(L, L / 2 + 1, 6);
         std::vector<cld> x(L);
         for (int m = 0; m < L; ++m) x[m] = h[m <= L / 2 ? m : L - m];
@@ -378,6 +379,8 @@ int main() {
         c.cols();
     }
     if (g_fail) return 1;
-    std::printf("OK %d P=%d E=%d\n", NVP_HOST_L, plan_threads(NVP_HOST_L), Fft<float, NVP_HOST_L>::E);
+    std::printf("OK %d P=%d E=%d (FP64 octant rows: P=%d E=%d)\n", NVP_HOST_L, Fft<float, NVP_HOST_L>::P,
+                Fft<float, NVP_HOST_L>::E, kz_threads(NVP_HOST_L),
+                Fft<double, NVP_HOST_L, false, false, kz_threads(NVP_HOST_L)>::E);
     return 0;
 }

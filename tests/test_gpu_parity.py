@@ -427,3 +427,36 @@ def test_error_codes(ctx):
         with pytest.raises(P.NvpError) as e:
             call()
         assert e.value.status == 1
+
+
+@pytest.mark.parametrize("prec", [P.NVP_C128, P.NVP_C64])
+def test_regrid_equals_a_fresh_plan(ctx, prec):
+    """nvp_plan_regrid replaces one harmonic's grid (a guarded run's fallback to the full box): the
+    cascade then equals, bit for bit, that of a plan made with the new grids, and matches the oracle;
+    a refused regrid leaves the plan working as before."""
+    focus, g1, gn = nested_grids()
+    big = oracle.grid_from_counts(focus, gn[3].h, (30, 23, 20), (12, 10, 9))  # harmonic 3, larger box
+    k1 = oracle.wavenumber(1, F0, WATER)
+    pts = bowl.bowl_points(7.5e-3, 15e-3, 128, 1)
+    p1 = bowl.incident_field(pts, 7.5e-3, 15e-3, k1, 1e6, g1.coords(0), g1.coords(1), g1.coords(2)).numpy()
+    say("case regrid prec=%d" % prec)
+    plan = P.CascadePlan(ctx, WATER, F0, g1, [gn[n] for n in range(2, 6)], prec=prec, order=3)
+    first = [t.clone() for t in plan.execute(dev(p1, prec))]  # spectra of the small boxes computed
+    plan.regrid(3, big)
+    got = plan.execute(dev(p1, prec))
+    with pytest.raises(P.NvpError):
+        plan.regrid(7, big)  # no harmonic 7: refused, plan unchanged
+    again = plan.execute(dev(p1, prec))
+    grids2 = {2: gn[2], 3: big, 4: gn[4], 5: gn[5]}
+    fresh = P.CascadePlan(ctx, WATER, F0, g1, [grids2[n] for n in range(2, 6)], prec=prec, order=3)
+    want = fresh.execute(dev(p1, prec))
+    torch.cuda.synchronize()
+    assert tuple(got[1].shape) == tuple(big.n)
+    assert torch.equal(got[0], first[0])  # harmonic 2 untouched
+    for a, b, c in zip(got, want, again):
+        assert torch.equal(a, b) and torch.equal(a, c)
+    ref = oracle.cascade(p1, g1, grids2, F0, WATER, 3, method="direct")
+    for n in range(2, 6):
+        assert oracle.rel_l2(host(got[n - 2]), ref[n]) < TOL[prec], n
+    plan.close()
+    fresh.close()
