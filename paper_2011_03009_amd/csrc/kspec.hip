@@ -35,21 +35,22 @@ hipError_t launch_kradial(double2 *ktab, int64_t n, double h, double kr, double 
 }
 
 template <typename R, int K, int NF>
-static hipError_t source_nf(const LdSource<R, K> &ld, const SourceArgs &a, void *out, int Ny, int64_t lds_elems,
-                            hipStream_t s) {
-    auto kern = k_source<R, K, NF, NVP_SRC_TX, NVP_SRC_TY, NVP_SRC_TZ>;
-    const size_t lds = (size_t)lds_elems * sizeof(cx<R>);
-    hipError_t e = allow_lds(kern, lds > 65536 ? 163840 : lds);
-    if (e != hipSuccess) return e;
+static hipError_t source_nf(const LdSource<R, K> &ld, const SourceArgs &a, void *out, int Ny, int cxl, hipStream_t s) {
+    auto kern = k_source<R, K, NF, NVP_SRC_TY, NVP_SRC_TZ, NVP_SRC_PRE, NVP_SRC_CXM>;
+    constexpr size_t lds = SrcLds<R, K, NF, NVP_SRC_TY, NVP_SRC_TZ, NVP_SRC_PRE, NVP_SRC_CXM>::BYTES;
+    static_assert(lds >= 1, "layout");
+    if (lds != source_lds_bytes(NF, K, sizeof(R)) || cxl < 1 || cxl > NVP_SRC_CXM) return hipErrorInvalidValue;
+    if (lds > 98304) return hipErrorInvalidValue;
+    static const hipError_t attr = allow_lds(kern, lds);
+    if (attr != hipSuccess) return attr;
     dim3 grid((unsigned)((a.Nz + NVP_SRC_TZ - 1) / NVP_SRC_TZ), (unsigned)((Ny + NVP_SRC_TY - 1) / NVP_SRC_TY),
-              (unsigned)((a.Nx + NVP_SRC_TX - 1) / NVP_SRC_TX));
-    hipLaunchKernelGGL(kern, grid, dim3(NVP_SRC_TY * NVP_SRC_TZ), lds, s, ld, static_cast<cx<R> *>(out), Ny,
-                       lds_elems);
+              (unsigned)((a.Nx + cxl - 1) / cxl));
+    hipLaunchKernelGGL(kern, grid, dim3(NVP_SRC_TY * NVP_SRC_TZ), lds, s, ld, static_cast<cx<R> *>(out), Ny, cxl);
     return hipGetLastError();
 }
 
 template <typename R, int K>
-static hipError_t source_k(const SourceArgs &a, void *out, int Ny, int64_t lds_elems, hipStream_t s) {
+static hipError_t source_k(const SourceArgs &a, void *out, int Ny, int cxl, hipStream_t s) {
     LdSource<R, K> ld;
     for (int i = 0; i < NVP_MAX_FIELDS; ++i) {
         const FieldArgs &f = a.f[i < a.nf ? i : 0];
@@ -66,26 +67,26 @@ static hipError_t source_k(const SourceArgs &a, void *out, int Ny, int64_t lds_e
     ld.Nx = a.Nx;
     ld.Nz = a.Nz;
     switch (a.nf) {
-    case 1: return source_nf<R, K, 1>(ld, a, out, Ny, lds_elems, s);
-    case 2: return source_nf<R, K, 2>(ld, a, out, Ny, lds_elems, s);
-    case 3: return source_nf<R, K, 3>(ld, a, out, Ny, lds_elems, s);
-    case 4: return source_nf<R, K, 4>(ld, a, out, Ny, lds_elems, s);
-    case 5: return source_nf<R, K, 5>(ld, a, out, Ny, lds_elems, s);
-    case 6: return source_nf<R, K, 6>(ld, a, out, Ny, lds_elems, s);
-    case 7: return source_nf<R, K, 7>(ld, a, out, Ny, lds_elems, s);
+    case 1: return source_nf<R, K, 1>(ld, a, out, Ny, cxl, s);
+    case 2: return source_nf<R, K, 2>(ld, a, out, Ny, cxl, s);
+    case 3: return source_nf<R, K, 3>(ld, a, out, Ny, cxl, s);
+    case 4: return source_nf<R, K, 4>(ld, a, out, Ny, cxl, s);
+    case 5: return source_nf<R, K, 5>(ld, a, out, Ny, cxl, s);
+    case 6: return source_nf<R, K, 6>(ld, a, out, Ny, cxl, s);
+    case 7: return source_nf<R, K, 7>(ld, a, out, Ny, cxl, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_source_c64(const SourceArgs &a, void *out, int Ny, int64_t lds_elems, hipStream_t s) {
-    if (a.order == 1) return source_k<float, 2>(a, out, Ny, lds_elems, s);
-    if (a.order == 3) return source_k<float, 4>(a, out, Ny, lds_elems, s);
+hipError_t launch_source_c64(const SourceArgs &a, void *out, int Ny, int cxl, hipStream_t s) {
+    if (a.order == 1) return source_k<float, 2>(a, out, Ny, cxl, s);
+    if (a.order == 3) return source_k<float, 4>(a, out, Ny, cxl, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_source_c128(const SourceArgs &a, void *out, int Ny, int64_t lds_elems, hipStream_t s) {
-    if (a.order == 1) return source_k<double, 2>(a, out, Ny, lds_elems, s);
-    if (a.order == 3) return source_k<double, 4>(a, out, Ny, lds_elems, s);
+hipError_t launch_source_c128(const SourceArgs &a, void *out, int Ny, int cxl, hipStream_t s) {
+    if (a.order == 1) return source_k<double, 2>(a, out, Ny, cxl, s);
+    if (a.order == 3) return source_k<double, 4>(a, out, Ny, cxl, s);
     return hipErrorInvalidValue;
 }
 

@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define NVP_MAX_FIELDS 7  // harmonics up to 8
+#include "common.hpp"
 
 // Transform lengths with a compiled radix plan.
 #define NVP_FOR_EACH_LENGTH(X) \
@@ -90,13 +90,23 @@ hipError_t launch_strided_f64_c64(int L, const StridedArgs &a, const void *tw, h
 hipError_t launch_xsrc_c64(int L, const SourceArgs &a, const void *tw, hipStream_t s);
 hipError_t launch_xsrc_c128(int L, const SourceArgs &a, const void *tw, hipStream_t s);
 
-// Transfer + source build (k_source): f_n written to `out` [Nx][Ny][Nz]; tiles
-// of SRC_TX x SRC_TY x SRC_TZ target voxels, lds_elems complex entries of LDS.
-#define NVP_SRC_TX 4
+// Transfer + source build (k_source): f_n written to `out` [Nx][Ny][Nz];
+// workgroups of SRC_TY x SRC_TZ target columns walking cx <= SRC_CXM x planes,
+// each thread loading up to SRC_PRE entries of a source plane's block.
 #define NVP_SRC_TY 8
 #define NVP_SRC_TZ 32
-hipError_t launch_source_c64(const SourceArgs &a, void *out, int Ny, int64_t lds_elems, hipStream_t s);
-hipError_t launch_source_c128(const SourceArgs &a, void *out, int Ny, int64_t lds_elems, hipStream_t s);
+#define NVP_SRC_PRE 2
+#define NVP_SRC_CXM 64
+// LDS bytes of a launch for nf fields, K-point stencils and reals of rsize
+// bytes (4 or 8): the kernel's fixed layout.
+inline size_t source_lds_bytes(int nf, int K, size_t rsize) {
+    const size_t nt = (size_t)NVP_SRC_TY * NVP_SRC_TZ;
+    return (size_t)nf * (((size_t)NVP_SRC_PRE * nt + 2 * nt) * 2 * rsize +
+                         ((size_t)(NVP_SRC_TZ + NVP_SRC_TY) * K + (size_t)NVP_SRC_CXM * K) * rsize +
+                         (size_t)NVP_SRC_CXM * sizeof(int));
+}
+hipError_t launch_source_c64(const SourceArgs &a, void *out, int Ny, int cx, hipStream_t s);
+hipError_t launch_source_c128(const SourceArgs &a, void *out, int Ny, int cx, hipStream_t s);
 
 // quads: pencil quads per workgroup (0 default, 1 or 2).
 hipError_t launch_zconv_c64(int L, void *buf, const void *khat, int64_t Mx, int64_t My, int Nz, const void *tw,

@@ -88,7 +88,8 @@ struct Harm {
     size_t khat_cap = 0;  // bytes allocated at khat
     bool khat_ok = false;
     int chunk = 0;  // x-chunk of the staged source build (0: direct gathers)
-    int64_t src_lds = 0;  // > 0: separate tiled source kernel with this many LDS entries
+    int64_t src_lds = 0;  // > 0: the separate source kernel applies, with this many bytes of LDS
+    int src_cx = 0;       // and this many target x planes per workgroup
     HarmField f[NVP_MAX_FIELDS];
 };
 
@@ -413,7 +414,7 @@ size_t kscratch_bytes(const int64_t M[3]) {
 // y inv, x inv with `scale` into u.
 nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid *g, const int64_t M[3],
                     const void *khat, void *A, void *B, const void *f, const SourceArgs *src, void *u,
-                    double scale, int64_t src_lds = 0, const Tune &tn = Tune{}, hipEvent_t kready = nullptr) {
+                    double scale, int src_cx = 0, const Tune &tn = Tune{}, hipEvent_t kready = nullptr) {
     const int64_t Nx = g->n[0], Ny = g->n[1], Nz = g->n[2];
     const int64_t Mx = M[0], My = M[1], Mz = M[2];
     const bool dbl = prec == NVP_C128;
@@ -423,11 +424,11 @@ nvp_status convolve(nvp_ctx *ctx, nvp_plan *timed, nvp_prec prec, const nvp_grid
     if ((st = twiddles(ctx, (int)My, dbl, &twy))) return st;
     if ((st = twiddles(ctx, (int)Mz, dbl, &twz))) return st;
     auto strided = dbl ? nvp::launch_strided_c128 : nvp::launch_strided_c64;
-    if (src && src_lds > 0) {
+    if (src && src_cx > 0) {
         // transfer + source into the first Nx rows of A, then the x pass in place
         {
             Timer t(timed, NVP_T_SRC);
-            NVP_HIP(ctx, (dbl ? nvp::launch_source_c128 : nvp::launch_source_c64)(*src, A, (int)Ny, src_lds,
+            NVP_HIP(ctx, (dbl ? nvp::launch_source_c128 : nvp::launch_source_c64)(*src, A, (int)Ny, src_cx,
                                                                                 ctx->stream));
         }
         f = A;
@@ -920,6 +921,21 @@ nvp_status nvp_volume_potential_box(nvp_ctx *ctx, double k_re, double k_im, cons
     return convolve(ctx, nullptr, prec, g, M, c.khat, c.A, c.B, f, nullptr, u_dev, sc);
 }
 
+// Target x planes per source-kernel workgroup: enough x chunks for about
+// 2048 workgroups per launch (the environment variable NVP_SRC_WGS, read
+// once, sets another count), and at most SRC_CXM planes.
+int source_chunk(const int64_t n[3]) {
+    static const int64_t want = [] {
+        const char *e = getenv("NVP_SRC_WGS");
+        const long v = e ? atol(e) : 0;
+        return v > 0 ? (int64_t)v : (int64_t)2048;
+    }();
+    const int64_t tiles = ((n[1] + NVP_SRC_TY - 1) / NVP_SRC_TY) * ((n[2] + NVP_SRC_TZ - 1) / NVP_SRC_TZ);
+    int64_t chunks = std::max<int64_t>(1, std::min<int64_t>((want + tiles - 1) / tiles, n[0]));
+    chunks = std::max<int64_t>(chunks, (n[0] + NVP_SRC_CXM - 1) / NVP_SRC_CXM);  // at most SRC_CXM planes each
+    return (int)((n[0] + chunks - 1) / chunks);
+}
+
 // Grids, constants, transfer tables (built on the host into `host`) and
 // source-build choices of every harmonic of plan p for the harmonic grids gn,
 // and the sizes of its pass buffers.  Sets no device memory.
@@ -999,38 +1015,36 @@ nvp_status plan_layout(nvp_ctx *ctx, nvp_plan *p, const nvp_grid *gn, std::vecto
             if (ok) h.chunk = (int)c;
         }
     }
-    // Tiled source kernel: the largest source block any tile touches, per axis,
-    // over the fields that need interpolating; used when its LDS fits 96 KiB,
-    // the x span of every tile's stencils fits TX - 1 + K rows and every grid
-    // involved has fewer than 2^32 elements.
+    // Source kernel: per field, the largest source block (SY x SZ) that a tile
+    // of SRC_TY x SRC_TZ target columns touches; used when every block fits
+    // the kernel's per-thread loads and two z rows per thread, its LDS fits 96
+    // KiB and every grid involved has fewer than 2^32 elements.
     for (auto &h : p->h) {
-        int64_t msx = 0, msy = 0, msz = 0;
-        bool any = false;
-        const int64_t T[3] = {NVP_SRC_TX, NVP_SRC_TY, NVP_SRC_TZ};
-        bool small = true;  // every grid involved below 2^32 elements (32-bit offsets)
+        const int64_t TY = NVP_SRC_TY, TZ = NVP_SRC_TZ;
+        bool small = true;  // 32-bit offsets
         for (int m = 1; m <= h.n; ++m) {
             const nvp_grid &gm = m == 1 ? p->g1 : p->h[m - 2].g;
             small = small && gm.n[0] * gm.n[1] * gm.n[2] < (int64_t(1) << 32);
         }
+        int64_t msy = 0, mblk = 0;
         for (int m = 1; m < h.n; ++m) {
             if (h.f[m - 1].identity) continue;
-            any = true;
-            int64_t *mx[3] = {&msx, &msy, &msz};
-            for (int ax = 0; ax < 3; ++ax) {
+            int64_t span[3] = {0, 0, 0};
+            const int64_t T[3] = {1, TY, TZ};
+            for (int ax = 1; ax < 3; ++ax) {
                 const int *b = reinterpret_cast<const int *>(host.data() + h.f[m - 1].off_b[ax]);
                 const int64_t n = h.g.n[ax];
                 for (int64_t i0 = 0; i0 < n; i0 += T[ax]) {
                     const int64_t i1 = i0 + T[ax] < n ? i0 + T[ax] : n;
-                    const int64_t span = b[i1 - 1] + K - b[i0];
-                    if (span > *mx[ax]) *mx[ax] = span;
+                    span[ax] = std::max(span[ax], (int64_t)b[i1 - 1] + K - b[i0]);
                 }
             }
+            msy = std::max(msy, span[1]);
+            mblk = std::max(mblk, span[1] * span[2]);
         }
-        h.src_lds = 0;
-        const int64_t elems = msx * msy * msz + msx * msy * T[2];
-        if (!small) h.src_lds = 0;
-        else if (!any) h.src_lds = 1;  // every field already on the target grid: no staging
-        else if (elems * (int64_t)csize(p->prec) <= 98304 && msx <= T[0] - 1 + K) h.src_lds = elems;
+        const size_t lds = nvp::source_lds_bytes(h.n - 1, K, csize(p->prec) / 2);
+        h.src_cx = source_chunk(h.g.n);
+        h.src_lds = small && msy <= 2 * TY && mblk <= NVP_SRC_PRE * TY * TZ && lds <= 98304 ? (int64_t)lds : 0;
     }
     *tbytes_out = tbytes;
     *maxA_out = maxA;
@@ -1188,6 +1202,7 @@ nvp_status nvp_plan_regrid(nvp_plan *plan, int n, const nvp_grid *g) {
         h.Cn = o.Cn;
         h.chunk = o.chunk;
         h.src_lds = o.src_lds;
+        h.src_cx = o.src_cx;
         std::memcpy(h.f, o.f, sizeof h.f);
         if (i == n - 2) {
             h.khat_ok = false;
@@ -1278,7 +1293,7 @@ nvp_status run_harmonic(nvp_plan *plan, int n, const void *const *fields, void *
     const double scale = h.Cn / ((double)h.M[0] * (double)h.M[1] * (double)h.M[2]);
     const bool tiled_src = plan->use_source_kernel && h.tune.src != 0;
     return convolve(ctx, plan, plan->prec, &h.g, h.M, h.khat, plan->A, plan->B, nullptr, &src, pn_dev, scale,
-                    tiled_src ? h.src_lds : 0, h.tune, kready);
+                    tiled_src && h.src_lds > 0 ? h.src_cx : 0, h.tune, kready);
 }
 
 // Side-stream resources of the overlapped spectra (created on first use).
@@ -1381,11 +1396,11 @@ nvp_status nvp_source_term(nvp_plan *plan, int n, const void *const *fields, voi
             return fail(ctx, NVP_E_INVALID, "nvp_source_term: null or aliased field");
     const Harm &h = plan->h[n - 2];
     if (h.src_lds <= 0)
-        return fail(ctx, NVP_E_UNSUPPORTED, "nvp_source_term: the source block of this grid pair exceeds LDS");
+        return fail(ctx, NVP_E_UNSUPPORTED, "nvp_source_term: the source blocks of this grid pair do not fit the source kernel");
     NVP_HIP(ctx, hipSetDevice(ctx->device));
     const SourceArgs src = source_args(plan, n, fields);
     NVP_HIP(ctx, (plan->prec == NVP_C128 ? nvp::launch_source_c128 : nvp::launch_source_c64)(
-                     src, f_dev, (int)h.g.n[1], h.src_lds, ctx->stream));
+                     src, f_dev, (int)h.g.n[1], h.src_cx, ctx->stream));
     return NVP_OK;
 }
 
@@ -1782,7 +1797,7 @@ nvp_status run_grouped(nvp_batch *b, const std::vector<GroupStep> &steps, const 
             }
             const Harm &h = p->h[g.n - 2];
             const SourceArgs src = source_args(p, g.n, fields.data());
-            NVP_HIP(ctx, (dbl ? nvp::launch_source_c128 : nvp::launch_source_c64)(src, p->A, (int)h.g.n[1], h.src_lds,
+            NVP_HIP(ctx, (dbl ? nvp::launch_source_c128 : nvp::launch_source_c64)(src, p->A, (int)h.g.n[1], h.src_cx,
                                                                                 ctx->stream));
             continue;
         }

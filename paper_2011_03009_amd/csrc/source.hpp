@@ -1,194 +1,237 @@
-// The transfer + source-build kernel (k_source), specialised on the number
-// of transferred fields; launched from kspec.hip only.
+// The transfer + source-build kernel (k_source), specialised on the number of
+// transferred fields; launched from kspec.hip only.  The body is a plain
+// function of its thread and workgroup indices so that it also runs on host
+// threads (tests/fft_host/source_harness.cpp).
 #pragma once
 
-#include "kernels.hpp"
+#include "field_dev.hpp"
 
 namespace nvp {
 
-// Transfer + source build as a kernel of its own (writes f_n, read by a plain
-// forward x pass afterwards), compiled for each field count NF = n - 1.  One workgroup per target tile of TX x TY x TZ
-// voxels (z fastest); for every field that needs interpolating it loads the
-// source block the tile's stencils touch into LDS once (coalesced along z),
-// interpolates along z inside LDS, then along y and x in registers (a thread
-// owns one (y, z) column of the tile); fields on the target grid are read
-// directly.  Two workgroup barriers per field.  Each thread keeps its voxels'
-// interpolated values in registers and finally writes sum_m v_m v_{n-m}.  The
-// host checks that the source blocks of every tile fit the LDS budget given
-// at launch and that their x spans fit the registers.
 // floor(a / b) for 0 <= a < 2^22 and b >= 1, given inv_b = 1/b in float:
 // (a + 1/2) / b lies at least 1/(2b) from an integer, far more than the
 // rounding of the float product.
 __device__ __forceinline__ int div_small(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
 
-template <typename R, int K, int NF, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(TY *TZ)
-k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int64_t lds_elems) {
-    cx<R> *lds = reinterpret_cast<cx<R> *>(nvp_smem);
+// f_n = sum_{m=1}^{n-1} T_m[p_m] T_{n-m}[p_{n-m}] on the target grid (the
+// source of equation "cascade_2", Section 2), with T_m the separable K-point
+// transfer of Section 6 from p_m's own grid.  NF = n - 1 fields.
+//
+// A workgroup owns a TY x TZ tile of target (y, z) columns and walks cx
+// target x planes.  Because an axis table's base index never decreases along
+// the axis, the source x planes a field needs arrive in order: each one is
+// loaded once per workgroup (its SY x SZ block for the tile, coalesced along
+// z, through LDS), interpolated along z and then y, and kept in a circular
+// ring of the field's last K planes that every thread holds in registers for
+// its own (y, z).  A target plane's x interpolation then reads only the
+// ring.  A field's next plane is loaded into registers as soon as the
+// current one is in LDS, so its latency overlaps the interpolation work in
+// between; the tile's y and z weights and the chunk's x tables sit in LDS,
+// so the only loads the loop waits for are the planes it consumes.  (Those
+// loads are issued without branches, from addresses clamped into the block,
+// and the ring is written and read at a workgroup-uniform position through
+// uniform branches, so that the compiler never copies a register a load is
+// still writing and never shifts the ring.)  All fields that advance at a
+// target plane share two workgroup barriers.  Fields already on the target
+// grid are read directly, each plane's value loaded before the plane's
+// interpolation work and used after it.
+//
+// LDS (SrcLds, fixed offsets): per field a source-plane region of PRE TY TZ
+// entries and a z-row region of 2 TY TZ entries, then per field the z and y
+// weights ((TZ + TY) K reals), the x weights (CXM K reals) and the x
+// stencils' ends (CXM ints).  Limits the host checks: SY <= 2 TY,
+// SY * SZ <= PRE * TY * TZ, cx <= CXM and every grid below 2^32 elements
+// (32-bit offsets).
+template <typename R, int K, int NF, int TY, int TZ, int PRE, int CXM> struct SrcLds {
+    static constexpr int NT = TY * TZ, SREG = PRE * NT, TREG = 2 * NT;
+    static constexpr size_t WOFF = (size_t)NF * (SREG + TREG) * sizeof(cx<R>);  // bytes
+    static constexpr size_t WPER = (size_t)((TZ + TY) * K + CXM * K) * sizeof(R);
+    static constexpr size_t XOFF = WOFF + NF * WPER;
+    static constexpr size_t BYTES = XOFF + (size_t)NF * CXM * sizeof(int);
+    unsigned char *base;
+    __device__ __forceinline__ cx<R> *plane(int i) const { return reinterpret_cast<cx<R> *>(base) + i * SREG; }
+    __device__ __forceinline__ cx<R> *zrows(int i) const {
+        return reinterpret_cast<cx<R> *>(base) + NF * SREG + i * TREG;
+    }
+    __device__ __forceinline__ R *wz(int i) const { return reinterpret_cast<R *>(base + WOFF + i * WPER); }
+    __device__ __forceinline__ R *wy(int i) const { return wz(i) + TZ * K; }
+    __device__ __forceinline__ R *wx(int i) const { return wz(i) + (TZ + TY) * K; }
+    __device__ __forceinline__ int *xend(int i) const { return reinterpret_cast<int *>(base + XOFF) + i * CXM; }
+};
+
+template <typename R, int K, int NF, int TY, int TZ, int PRE, int CXM>
+__device__ __forceinline__ void source_tile(const LdSource<R, K> &src, cx<R> *__restrict__ out, int Ny, int cxl,
+                                            unsigned char *lds, int tid, int bz, int by, int bx) {
+    using L = SrcLds<R, K, NF, TY, TZ, PRE, CXM>;
+    constexpr int NT = L::NT;
+    static_assert(NT >= TY * K && NT >= TZ * K, "one weight per thread at set-up");
+    static_assert(K == 2 || K == 4, "ring positions are taken modulo K with a mask");
+    const L lay{lds};
     const int Nx = src.Nx, Nz = src.Nz;
-    const int tz = threadIdx.x % TZ, ty = threadIdx.x / TZ;
-    const int ix0 = blockIdx.z * TX, iy0 = blockIdx.y * TY, iz0 = blockIdx.x * TZ;
-    const int ix1 = min(ix0 + TX, Nx), iy1 = min(iy0 + TY, Ny), iz1 = min(iz0 + TZ, Nz);
+    const int tz = tid % TZ, ty = tid / TZ;
+    const int iz0 = bz * TZ, iy0 = by * TY, ix0 = bx * cxl;
+    const int iz1 = min(iz0 + TZ, Nz), iy1 = min(iy0 + TY, Ny), ix1 = min(ix0 + cxl, Nx);
     const int iy = iy0 + ty, iz = iz0 + tz;
-    const bool inyz = iy < Ny && iz < Nz;
-    // element offsets in 32 bits: the host checks that every grid involved
-    // has fewer than 2^32 elements
-    auto at = [](const FieldDev<R> &g, int x, int y, int z) {
-        return g.p + ((uint32_t)x * (uint32_t)g.s0 + (uint32_t)y * (uint32_t)g.s1 + (uint32_t)z);
-    };
-    cx<R> v[NF][TX];
-#pragma unroll
-    for (int i = 0; i < NF; ++i)
-#pragma unroll
-        for (int a = 0; a < TX; ++a) v[i][a] = czero<R>();
-    // A field's source block [sx0, sx0+SX) x [sy0, sy0+SY) x [sz0, sz0+SZ).
-    struct Block {
-        int sx0, sy0, sz0, SX, SY, SZ;
-    };
-    auto block_of = [&](const FieldDev<R> &g) {
-        Block b;
-        b.sx0 = g.b[0][ix0];
-        b.sy0 = g.b[1][iy0];
-        b.sz0 = g.b[2][iz0];
-        b.SX = g.b[0][ix1 - 1] + K - b.sx0;
-        b.SY = g.b[1][iy1 - 1] + K - b.sy0;
-        b.SZ = g.b[2][iz1 - 1] + K - b.sz0;
-        return b;
-    };
-    // The next field's block is loaded into registers (up to PR rows of PZ
-    // z-values per thread) while this one is interpolated, so that its load
-    // latency overlaps the work; a larger block is loaded when it is reached.
-    // (complex64 only: complex128 values would spill registers)
-    constexpr bool PIPE = sizeof(R) == 4;
-    constexpr int PR = PIPE ? 10 : 1, PZ = 1;
-    cx<R> pre[PR][PZ];
-    int pre_field = -1;
-    auto fits = [&](const Block &b) { return PIPE && b.SX * b.SY <= PR * TY && b.SZ <= PZ * TZ; };
+    const bool oky = iy < Ny, okz = iz < Nz;
+    auto plane = [](const FieldDev<R> &g, int x) { return g.p + (uint32_t)x * (uint32_t)g.s0; };
+
+    int nxt[NF], endx[NF], blk[NF], szs[NF], sys[NF];  // workgroup-uniform
+    int oz[NF], oy[NF];
+    uint32_t goff[NF][PRE];  // this thread's share of a plane's block, relative to the plane
+    cx<R> pre[NF][PRE];      // the field's next plane, in flight
+    cx<R> ring[NF][K];       // source plane p, interpolated at (iy, iz), at ring[i][p % K]
+    // a field on the target grid is read at (ix, iyc, izc), in bounds for every thread
+    const uint32_t idoff = (uint32_t)min(iy, Ny - 1) * (uint32_t)Nz + (uint32_t)min(iz, Nz - 1);
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
         const FieldDev<R> &g = src.f[i];
-        if (g.identity) {
 #pragma unroll
-            for (int a = 0; a < TX; ++a)
-                if (inyz && ix0 + a < Nx) v[i][a] = *at(g, ix0 + a, iy, iz);
+        for (int k = 0; k < K; ++k) ring[i][k] = czero<R>();
+#pragma unroll
+        for (int j = 0; j < PRE; ++j) pre[i][j] = czero<R>();
+        if (g.identity) {
+            nxt[i] = endx[i] = blk[i] = szs[i] = sys[i] = oz[i] = oy[i] = 0;
+#pragma unroll
+            for (int j = 0; j < PRE; ++j) goff[i][j] = 0;
             continue;
         }
-        const Block bk = block_of(g);
-        const int sx0 = bk.sx0, sy0 = bk.sy0, sz0 = bk.sz0, SX = bk.SX, SY = bk.SY, SZ = bk.SZ;
-        const int rows = SX * SY;
-        const float inv_sy = 1.0f / (float)SY;
-        cx<R> *S = lds;                         // [SX][SY][SZ]
-        cx<R> *T1 = lds + (lds_elems - (int64_t)rows * TZ);  // [SX][SY][TZ]
-        // the tile's z and y stencils: one per thread (z = tz, y = ty), loaded
-        // before the block so that their latency overlaps its loads
-        const int zz = iz0 + tz, yy = iy0 + ty;
-        const bool okz = zz < Nz, oky = yy < Ny;
-        const int oz = okz ? g.b[2][zz] - sz0 : 0, oy = oky ? g.b[1][yy] - sy0 : 0;
-        // a voxel's K weights are contiguous and aligned to their size (the
-        // host aligns each table to 256 bytes): one vector load each
-        struct alignas(sizeof(R) * K) Wk {
-            R v[K];
-        };
-        R wx[TX][K];
-        int ox[TX];
-        const Wk wzv = okz ? *reinterpret_cast<const Wk *>(g.w[2] + zz * K) : Wk{};
-        const Wk wyv = oky ? *reinterpret_cast<const Wk *>(g.w[1] + yy * K) : Wk{};
-        const R *wz = wzv.v, *wy = wyv.v;
+        const int sy0 = g.b[1][iy0], sz0 = g.b[2][iz0];
+        sys[i] = g.b[1][iy1 - 1] + K - sy0;
+        szs[i] = g.b[2][iz1 - 1] + K - sz0;
+        blk[i] = sys[i] * szs[i];
+        nxt[i] = g.b[0][ix0];
+        endx[i] = g.b[0][ix1 - 1] + K;
+        const float inv = 1.0f / (float)szs[i];
 #pragma unroll
-        for (int a = 0; a < TX; ++a) {
-            const bool okx = ix0 + a < Nx;
-            ox[a] = okx ? g.b[0][ix0 + a] - sx0 : 0;
-#pragma unroll
-            for (int b = 0; b < K; ++b) wx[a][b] = okx ? g.w[0][(ix0 + a) * K + b] : R(0);
+        for (int j = 0; j < PRE; ++j) {
+            const int e = tid + j * NT;
+            const int r = div_small(e, inv), c = e - r * szs[i];
+            // beyond the block: the block's first entry (loaded, never stored)
+            goff[i][j] = e < blk[i] ? (uint32_t)(sy0 + r) * (uint32_t)g.s1 + (uint32_t)(sz0 + c)
+                                    : (uint32_t)sy0 * (uint32_t)g.s1 + (uint32_t)sz0;
+            pre[i][j] = plane(g, nxt[i])[goff[i][j]];
         }
-        // rows of SZ contiguous source values, TZ lanes per row
-        if (pre_field == i) {
+        oz[i] = okz ? g.b[2][iz] - sz0 : 0;
+        oy[i] = oky ? g.b[1][iy] - sy0 : 0;
+        // the tile's z and y weights (zero beyond the grid) and the chunk's x tables
+        R *wz = lay.wz(i), *wy = lay.wy(i), *wx = lay.wx(i);
+        int *xe = lay.xend(i);
+        if (tid < TZ * K) wz[tid] = iz0 + tid / K < Nz ? g.w[2][iz0 * K + tid] : R(0);
+        if (tid < TY * K) wy[tid] = iy0 + tid / K < Ny ? g.w[1][iy0 * K + tid] : R(0);
+        for (int e = tid; e < (ix1 - ix0) * K; e += NT) wx[e] = g.w[0][ix0 * K + e];
+        for (int e = tid; e < ix1 - ix0; e += NT) xe[e] = g.b[0][ix0 + e] + K;
+    }
+    __syncthreads();
+
+    for (int ix = ix0; ix < ix1; ++ix) {
+        cx<R> idv[NF];
 #pragma unroll
-            for (int r = 0; r < PR; ++r) {
-                const int row = ty + r * TY;
+        for (int i = 0; i < NF; ++i)
+            if (src.f[i].identity) idv[i] = plane(src.f[i], ix)[idoff];
+        int need[NF];
 #pragma unroll
-                for (int z = 0; z < PZ; ++z) {
-                    const int sz = tz + z * TZ;
-                    if (row < rows && sz < SZ) S[row * SZ + sz] = pre[r][z];
-                }
+        for (int i = 0; i < NF; ++i)
+            need[i] = src.f[i].identity ? 0 : __builtin_amdgcn_readfirstlane(lay.xend(i)[ix - ix0]);
+        // advance every field whose ring does not yet end at its stencil's last plane
+        for (;;) {
+            unsigned act = 0;  // bit i: field i advances
+#pragma unroll
+            for (int i = 0; i < NF; ++i) act |= nxt[i] < need[i] ? 1u << i : 0u;
+            if (!act) break;
+#pragma unroll
+            for (int i = 0; i < NF; ++i) {
+                if (!(act >> i & 1)) continue;
+                cx<R> *S = lay.plane(i);
+#pragma unroll
+                for (int j = 0; j < PRE; ++j)
+                    if (tid + j * NT < blk[i]) S[tid + j * NT] = pre[i][j];
+                // the next plane (the last one again at the chunk's end)
+                const cx<R> *P = plane(src.f[i], min(nxt[i] + 1, endx[i] - 1));
+#pragma unroll
+                for (int j = 0; j < PRE; ++j) pre[i][j] = P[goff[i][j]];
             }
-        } else {
-            for (int row = ty; row < rows; row += TY) {
-                const int sx = div_small(row, inv_sy), sy = row - sx * SY;
-                const cx<R> *sp = at(g, sx0 + sx, sy0 + sy, sz0);
-                for (int sz = tz; sz < SZ; sz += TZ) S[row * SZ + sz] = sp[sz];
-            }
-        }
-        __syncthreads();
-        if (i + 1 < NF && !src.f[i + 1 < NF ? i + 1 : i].identity) {
-            const FieldDev<R> &gn = src.f[i + 1 < NF ? i + 1 : i];
-            const Block nb = block_of(gn);
-            if (fits(nb)) {
+            __syncthreads();
+            // z: rows ty and ty + TY of the block, at this thread's z stencil
 #pragma unroll
-                for (int r = 0; r < PR; ++r) {
-                    const int row = ty + r * TY;
-                    const int sx = div_small(row, 1.0f / (float)nb.SY), sy = row - sx * nb.SY;
-                    const cx<R> *sp = at(gn, nb.sx0 + sx, nb.sy0 + sy, nb.sz0);
+            for (int i = 0; i < NF; ++i) {
+                if (!(act >> i & 1)) continue;
+                const cx<R> *S = lay.plane(i);
+                cx<R> *T = lay.zrows(i);
+                const R *wz = lay.wz(i) + tz * K;
+                R w[K];
 #pragma unroll
-                    for (int z = 0; z < PZ; ++z) {
-                        const int sz = tz + z * TZ;
-                        if (row < nb.SX * nb.SY && sz < nb.SZ) pre[r][z] = sp[sz];
+                for (int d = 0; d < K; ++d) w[d] = wz[d];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int row = ty + h * TY;
+                    if (row < sys[i]) {
+                        cx<R> acc = czero<R>();
+#pragma unroll
+                        for (int d = 0; d < K; ++d) acc = cadd<R>(acc, cscale<R>(S[row * szs[i] + oz[i] + d], w[d]));
+                        T[row * TZ + tz] = acc;
                     }
                 }
-                pre_field = i + 1;
             }
-        }
-        // z interpolation: T1[row][z] for this thread's z
-        for (int row = ty; row < rows; row += TY) {
-            cx<R> acc = czero<R>();
+            __syncthreads();
+            // y: this thread's (iy, iz), into the ring at the plane's position
 #pragma unroll
-            for (int d = 0; d < K; ++d) acc = cadd<R>(acc, cscale<R>(S[row * SZ + oz + d], wz[d]));
-            T1[row * TZ + tz] = acc;
-        }
-        __syncthreads();
-        // y interpolation of this thread's (y, z) for every source x-row of
-        // the block, kept in registers: the x stencils of a tile span at most
-        // TX - 1 + K rows (the host checks it)
-        constexpr int SXM = TX - 1 + K;
-        cx<R> t2[SXM];
-#pragma unroll
-        for (int sx = 0; sx < SXM; ++sx) {
-            cx<R> acc = czero<R>();
-            if (sx < SX) {
-#pragma unroll
-                for (int c = 0; c < K; ++c)
-                    acc = cadd<R>(acc, cscale<R>(T1[((sx * SY) + oy + c) * TZ + tz], wy[c]));
-            }
-            t2[sx] = acc;
-        }
-        // x interpolation: the stencil offset of target row a is the same for
-        // the whole workgroup, so the branch on it is uniform
-#pragma unroll
-        for (int a = 0; a < TX; ++a) {
-            if (ix0 + a < Nx) {
-                const int o = __builtin_amdgcn_readfirstlane(ox[a]);
+            for (int i = 0; i < NF; ++i) {
+                if (!(act >> i & 1)) continue;
+                const cx<R> *T = lay.zrows(i);
+                const R *wy = lay.wy(i) + ty * K;
                 cx<R> acc = czero<R>();
 #pragma unroll
-                for (int q = 0; q < TX; ++q)
-                    if (o == q) {
+                for (int c = 0; c < K; ++c) acc = cadd<R>(acc, cscale<R>(T[(oy[i] + c) * TZ + tz], wy[c]));
+                const int pos = nxt[i] & (K - 1);
 #pragma unroll
-                        for (int b = 0; b < K; ++b) acc = cadd<R>(acc, cscale<R>(t2[q + b], wx[a][b]));
-                    }
-                v[i][a] = acc;
+                for (int k = 0; k < K; ++k)
+                    if (pos == k) ring[i][k] = acc;
+                ++nxt[i];
             }
         }
-    }
-    if (!inyz) return;
+        // x: the ring holds planes need - K .. need - 1, the stencil of ix;
+        // plane need - K + b sits at (need + b) % K
+        cx<R> v[NF];
 #pragma unroll
-    for (int a = 0; a < TX; ++a) {
-        const int ix = ix0 + a;
-        if (ix >= Nx) break;
-        // sum_{b + c = NF - 1} v_b v_c, the source term of harmonic NF + 1
-        cx<R> f = czero<R>();
+        for (int i = 0; i < NF; ++i) {
+            const FieldDev<R> &g = src.f[i];
+            if (g.identity) {
+                v[i] = idv[i];
+                continue;
+            }
+            const R *wx = lay.wx(i) + (ix - ix0) * K;
+            R w[K];
 #pragma unroll
-        for (int b = 0; b < NF; ++b) f = cadd<R>(f, cmul<R>(v[b][a], v[NF - 1 - b][a]));
-        out[((uint32_t)ix * (uint32_t)Ny + (uint32_t)iy) * (uint32_t)Nz + (uint32_t)iz] = f;
+            for (int b = 0; b < K; ++b) w[b] = wx[b];
+            const int pos = need[i] & (K - 1);
+            cx<R> acc = czero<R>();
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (pos == k) {
+#pragma unroll
+                    for (int b = 0; b < K; ++b) acc = cadd<R>(acc, cscale<R>(ring[i][(k + b) & (K - 1)], w[b]));
+                }
+            v[i] = acc;
+        }
+        if (oky && okz) {
+            // sum_{b + c = NF - 1} v_b v_c, the source term of harmonic NF + 1
+            cx<R> f = czero<R>();
+#pragma unroll
+            for (int b = 0; b < NF; ++b) f = cadd<R>(f, cmul<R>(v[b], v[NF - 1 - b]));
+            out[((uint32_t)ix * (uint32_t)Ny + (uint32_t)iy) * (uint32_t)Nz + (uint32_t)iz] = f;
+        }
     }
 }
+
+#ifndef NVP_HOST_EMULATION
+extern __shared__ __align__(16) unsigned char nvp_smem[];
+
+template <typename R, int K, int NF, int TY, int TZ, int PRE, int CXM>
+__global__ void __launch_bounds__(TY *TZ)
+k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int cxl) {
+    source_tile<R, K, NF, TY, TZ, PRE, CXM>(src, out, Ny, cxl, nvp_smem, (int)threadIdx.x, (int)blockIdx.x,
+                                            (int)blockIdx.y, (int)blockIdx.z);
+}
+#endif
 
 }  // namespace nvp

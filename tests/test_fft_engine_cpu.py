@@ -1,4 +1,4 @@
-"""The Stockham FFT engine's index arithmetic and synchronisation, on the CPU.
+"""The Stockham FFT engine's and the source kernel's index arithmetic and synchronisation, on the CPU.
 
 tests/fft_host/harness.cpp compiles the engine header of the library
 (csrc/fft_core.hpp) for the host, runs each lane of a column as a host thread
@@ -73,3 +73,22 @@ def test_engine_catches_a_wrong_constant(tmp_path):
     subprocess.run(cmd, check=True)
     r = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=120)
     assert r.returncode != 0 and "FAIL" in r.stdout
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_source_kernel_on_host_threads():
+    """The source kernel (csrc/source.hpp) run workgroup by workgroup on host threads against the
+    transfer and source product summed directly (tests/fft_host/source_harness.cpp)."""
+    os.makedirs(BUILD, exist_ok=True)
+    exe = os.path.join(BUILD, "source_harness")
+    srcs = [os.path.join(HERE, "source_harness.cpp"), os.path.join(CSRC, "source.hpp"),
+            os.path.join(CSRC, "field_dev.hpp"), os.path.join(CSRC, "common.hpp"),
+            os.path.join(CSRC, "fft_core.hpp"), os.path.join(HERE, "hip", "hip_runtime.h")]
+    if not os.path.exists(exe) or any(os.path.getmtime(s) > os.path.getmtime(exe) for s in srcs):
+        cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer", "-pthread",
+               "-I" + HERE, "-I" + CSRC, srcs[0], "-o", exe + ".tmp"]
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+        assert r.returncode == 0, "compile failed:\n" + r.stdout[-3000:]
+        os.replace(exe + ".tmp", exe)
+    r = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=600)
+    assert r.returncode == 0 and r.stdout.startswith("OK"), r.stdout[-3000:]
