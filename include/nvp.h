@@ -43,7 +43,7 @@ typedef int32_t nvp_status;
 #define NVP_E_INVALID 1     /* bad argument: null pointer, h <= 0, n < 1, bad precision, ... */
 #define NVP_E_NOMEM 2       /* device or host allocation failed; no partial state kept */
 #define NVP_E_HIP 3         /* a HIP runtime call or kernel launch failed */
-#define NVP_E_UNSUPPORTED 4 /* valid request outside what this build handles: an axis beyond 4096 voxels, a grid beyond a fixed scratch, a transfer order other than 1 or 3 */
+#define NVP_E_UNSUPPORTED 4 /* valid request outside what this build handles: an axis beyond 4096 voxels, a grid beyond a fixed scratch, a transfer order other than 1 or 3, the source kernel for grids only the fused path takes */
 #define NVP_E_STATE 5       /* call out of order (e.g. timing read while disabled) */
 /* Fault injection for tests: with the environment variable
  * NVP_DEVICE_ALLOC_LIMIT set to a byte count, every device allocation of the
@@ -427,8 +427,10 @@ nvp_status nvp_boxnet_destroy(nvp_boxnet *bn);
 
 /* Times the launch choices of every harmonic of the plan and keeps the
  * fastest: the column tile of the x and the y passes (default or half), the
- * pencil quads per z-pass workgroup (1 or 2) and the source build (its own
- * tiled kernel or fused into the x pass).  Each choice is timed over reps
+ * pencil quads per z-pass workgroup (1 or 2), the source build (its own
+ * kernel or fused into the x pass) and, with its own kernel, the target x
+ * planes per source workgroup (the default, or chunks for about half or
+ * twice as many workgroups).  Each choice is timed over reps
  * executions on zero-filled fields (the kernels have no data-dependent
  * control flow).  cache_path (optional): a text file of earlier choices,
  * keyed by device, precision, transfer order and shapes; entries found there
@@ -436,9 +438,17 @@ nvp_status nvp_boxnet_destroy(nvp_boxnet *bn);
  * Results of a tuned plan differ from the default only by the rounding order
  * of the source build. */
 nvp_status nvp_plan_autotune(nvp_plan *plan, const char *cache_path, int reps);
-/* The launch choices of harmonic n: choice[4] = x tile, y tile (0 default,
- * 1 half), z quads (0 default, 1, 2), source (-1 default, 1 tiled, 0 fused). */
+/* The launch choices of harmonic n: choice[5] = x tile, y tile (0 default,
+ * 1 half), z quads (0 default, 1, 2), source (-1 default, 1 its own kernel,
+ * 0 fused into the x pass), source x chunk (0 default, else 1..64 target x
+ * planes per workgroup of the source kernel). */
 nvp_status nvp_plan_get_tuning(const nvp_plan *plan, int n, int *choice);
+/* Sets the launch choices of harmonic n (choice[5], as above), e.g. ones
+ * found by nvp_plan_autotune in an earlier process.  NVP_E_INVALID for a
+ * choice out of range; NVP_E_UNSUPPORTED for the source kernel (1) where the
+ * plan's grids take the fused path only.  Results differ from the default's
+ * only by the rounding order of the source build. */
+nvp_status nvp_plan_set_tuning(nvp_plan *plan, int n, const int *choice);
 
 /* One problem of a batch: the arguments of nvp_plan_cascade. */
 typedef struct {

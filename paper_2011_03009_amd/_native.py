@@ -76,6 +76,7 @@ SIGNATURES = {
     "nvp_source_term": (_st, [_vp, _i, ctypes.POINTER(_vp), _vp]),
     "nvp_plan_autotune": (_st, [_vp, ctypes.c_char_p, _i]),
     "nvp_plan_get_tuning": (_st, [_vp, _i, ctypes.POINTER(_i)]),
+    "nvp_plan_set_tuning": (_st, [_vp, _i, ctypes.POINTER(_i)]),
     "nvp_batch_create": (_st, [_vp, _i, ctypes.POINTER(Problem), _i, _i, ctypes.POINTER(_vp)]),
     "nvp_batch_outputs": (_st, [_vp, _i64p]),
     "nvp_batch_set_graph": (_st, [_vp, _i, _i]),

@@ -75,7 +75,8 @@ struct HarmField {
 struct Tune {
     int x_tile = 0, y_tile = 0;  // strided passes: 0 default columns per workgroup, 1 half
     int quads = 0;               // z pass: pencil quads per workgroup (0 default, 1, 2)
-    int src = -1;                // source build: -1 default, 1 its own tiled kernel, 0 fused into the x pass
+    int src = -1;                // source build: -1 default, 1 its own kernel, 0 fused into the x pass
+    int src_cx = 0;              // source kernel: target x planes per workgroup (0 default)
 };
 
 struct Harm {
@@ -92,6 +93,9 @@ struct Harm {
     int src_cx = 0;       // and this many target x planes per workgroup
     HarmField f[NVP_MAX_FIELDS];
 };
+
+// The source kernel's x chunk of harmonic h: the tuned one, else the default.
+int src_cx_of(const Harm &h) { return h.tune.src_cx > 0 ? h.tune.src_cx : h.src_cx; }
 
 struct TimedEvent {
     int kind;
@@ -922,19 +926,21 @@ nvp_status nvp_volume_potential_box(nvp_ctx *ctx, double k_re, double k_im, cons
 }
 
 // Target x planes per source-kernel workgroup: enough x chunks for about
-// 2048 workgroups per launch (the environment variable NVP_SRC_WGS, read
-// once, sets another count), and at most SRC_CXM planes.
-int source_chunk(const int64_t n[3]) {
-    static const int64_t want = [] {
+// `want` workgroups per launch (0: 2048, or the environment variable
+// NVP_SRC_WGS, read once), and at most SRC_CXM planes.
+int source_chunk(const int64_t n[3], int64_t want = 0) {
+    static const int64_t dflt = [] {
         const char *e = getenv("NVP_SRC_WGS");
         const long v = e ? atol(e) : 0;
         return v > 0 ? (int64_t)v : (int64_t)2048;
     }();
+    if (want <= 0) want = dflt;
     const int64_t tiles = ((n[1] + NVP_SRC_TY - 1) / NVP_SRC_TY) * ((n[2] + NVP_SRC_TZ - 1) / NVP_SRC_TZ);
     int64_t chunks = std::max<int64_t>(1, std::min<int64_t>((want + tiles - 1) / tiles, n[0]));
     chunks = std::max<int64_t>(chunks, (n[0] + NVP_SRC_CXM - 1) / NVP_SRC_CXM);  // at most SRC_CXM planes each
     return (int)((n[0] + chunks - 1) / chunks);
 }
+
 
 // Grids, constants, transfer tables (built on the host into `host`) and
 // source-build choices of every harmonic of plan p for the harmonic grids gn,
@@ -1293,7 +1299,7 @@ nvp_status run_harmonic(nvp_plan *plan, int n, const void *const *fields, void *
     const double scale = h.Cn / ((double)h.M[0] * (double)h.M[1] * (double)h.M[2]);
     const bool tiled_src = plan->use_source_kernel && h.tune.src != 0;
     return convolve(ctx, plan, plan->prec, &h.g, h.M, h.khat, plan->A, plan->B, nullptr, &src, pn_dev, scale,
-                    tiled_src && h.src_lds > 0 ? h.src_cx : 0, h.tune, kready);
+                    tiled_src && h.src_lds > 0 ? src_cx_of(h) : 0, h.tune, kready);
 }
 
 // Side-stream resources of the overlapped spectra (created on first use).
@@ -1400,7 +1406,7 @@ nvp_status nvp_source_term(nvp_plan *plan, int n, const void *const *fields, voi
     NVP_HIP(ctx, hipSetDevice(ctx->device));
     const SourceArgs src = source_args(plan, n, fields);
     NVP_HIP(ctx, (plan->prec == NVP_C128 ? nvp::launch_source_c128 : nvp::launch_source_c64)(
-                     src, f_dev, (int)h.g.n[1], h.src_cx, ctx->stream));
+                     src, f_dev, (int)h.g.n[1], src_cx_of(h), ctx->stream));
     return NVP_OK;
 }
 
@@ -1469,7 +1475,10 @@ void read_tune_cache(const char *path, std::map<std::string, Tune> &out) {
         std::istringstream ls(line);
         std::string key;
         Tune t;
-        if (ls >> key >> t.x_tile >> t.y_tile >> t.quads >> t.src) out[key] = t;
+        if (ls >> key >> t.x_tile >> t.y_tile >> t.quads >> t.src) {
+            if (!(ls >> t.src_cx) || t.src_cx < 0 || t.src_cx > NVP_SRC_CXM) t.src_cx = 0;  // older files: none
+            out[key] = t;
+        }
     }
 }
 
@@ -1480,7 +1489,7 @@ bool write_tune_cache(const char *path, const std::map<std::string, Tune> &m) {
         if (!o) return false;
         for (const auto &kv : m)
             o << kv.first << " " << kv.second.x_tile << " " << kv.second.y_tile << " " << kv.second.quads << " "
-              << kv.second.src << "\n";
+              << kv.second.src << " " << kv.second.src_cx << "\n";
         if (!o) return false;
     }
     return std::rename(tmp.c_str(), path) == 0;
@@ -1545,6 +1554,27 @@ nvp_status autotune_plan(nvp_plan *plan, std::map<std::string, Tune> &cache, int
         }
         float best = 1e30f;
         Tune best_t{};
+        // one choice: a warm-up run, then reps timed runs
+        auto try_choice = [&](const Tune &t) {
+            h.tune = t;
+            if ((st = nvp_execute_harmonic(plan, n, fields.data(), out))) return;
+            if (hipEventRecord(e0, ctx->stream) != hipSuccess) {
+                st = NVP_E_HIP;
+                return;
+            }
+            for (int r = 0; r < reps && st == NVP_OK; ++r) st = nvp_execute_harmonic(plan, n, fields.data(), out);
+            if (st) return;
+            float ms = 0;
+            if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                st = hip_fail(ctx, "autotune timing", hipGetLastError());
+                return;
+            }
+            if (ms < best) {
+                best = ms;
+                best_t = t;
+            }
+        };
         const int src_opts = (plan->use_source_kernel && h.src_lds > 0) ? 2 : 1;
         for (int xt = 0; xt < 2 && st == NVP_OK; ++xt)
             for (int yt = 0; yt < 2 && st == NVP_OK; ++yt)
@@ -1555,22 +1585,18 @@ nvp_status autotune_plan(nvp_plan *plan, std::map<std::string, Tune> &cache, int
                         t.y_tile = yt;
                         t.quads = q;
                         t.src = src_opts == 2 ? 1 - so : 0;
-                        h.tune = t;
-                        if ((st = nvp_execute_harmonic(plan, n, fields.data(), out))) break;  // warm-up
-                        if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = NVP_E_HIP; break; }
-                        for (int r = 0; r < reps && st == NVP_OK; ++r) st = nvp_execute_harmonic(plan, n, fields.data(), out);
-                        if (st) break;
-                        float ms = 0;
-                        if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                            st = hip_fail(ctx, "autotune timing", hipGetLastError());
-                            break;
-                        }
-                        if (ms < best) {
-                            best = ms;
-                            best_t = t;
-                        }
+                        try_choice(t);
                     }
+        // then, with the source kernel chosen, its x chunk: chunks for about a half
+        // and twice the default number of workgroups
+        if (st == NVP_OK && best_t.src == 1) {
+            const Tune base = best_t;
+            for (int64_t want : {(int64_t)1024, (int64_t)4096}) {
+                Tune t = base;
+                t.src_cx = source_chunk(h.g.n, want);
+                if (t.src_cx != h.src_cx && st == NVP_OK) try_choice(t);
+            }
+        }
         h.tune = best_t;
         cache[key] = best_t;
     }
@@ -1797,7 +1823,7 @@ nvp_status run_grouped(nvp_batch *b, const std::vector<GroupStep> &steps, const 
             }
             const Harm &h = p->h[g.n - 2];
             const SourceArgs src = source_args(p, g.n, fields.data());
-            NVP_HIP(ctx, (dbl ? nvp::launch_source_c128 : nvp::launch_source_c64)(src, p->A, (int)h.g.n[1], h.src_cx,
+            NVP_HIP(ctx, (dbl ? nvp::launch_source_c128 : nvp::launch_source_c64)(src, p->A, (int)h.g.n[1], src_cx_of(h),
                                                                                 ctx->stream));
             continue;
         }
@@ -1933,6 +1959,26 @@ nvp_status nvp_plan_get_tuning(const nvp_plan *plan, int n, int *choice) {
     choice[1] = t.y_tile;
     choice[2] = t.quads;
     choice[3] = t.src;
+    choice[4] = t.src_cx;
+    return NVP_OK;
+}
+
+nvp_status nvp_plan_set_tuning(nvp_plan *plan, int n, const int *choice) {
+    if (!plan) return NVP_E_INVALID;
+    if (!choice || n < 2 || n > plan->n_harm) return fail(plan->ctx, NVP_E_INVALID, "nvp_plan_set_tuning: bad argument");
+    Tune t;
+    t.x_tile = choice[0];
+    t.y_tile = choice[1];
+    t.quads = choice[2];
+    t.src = choice[3];
+    t.src_cx = choice[4];
+    if ((t.x_tile | t.y_tile) & ~1 || t.quads < 0 || t.quads > 2 || t.src < -1 || t.src > 1 || t.src_cx < 0 ||
+        t.src_cx > NVP_SRC_CXM)
+        return fail(plan->ctx, NVP_E_INVALID, "nvp_plan_set_tuning: a choice out of range");
+    if (t.src == 1 && (!plan->use_source_kernel || plan->h[n - 2].src_lds <= 0))
+        return fail(plan->ctx, NVP_E_UNSUPPORTED,
+                    "nvp_plan_set_tuning: the source kernel does not take this harmonic's grids");
+    plan->h[n - 2].tune = t;
     return NVP_OK;
 }
 

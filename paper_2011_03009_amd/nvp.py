@@ -448,9 +448,14 @@ class CascadePlan:
                self.ctx.handle)
 
     def tuning(self, n):
-        c = (ctypes.c_int * 4)()
+        c = (ctypes.c_int * 5)()
         _check(_native.lib().nvp_plan_get_tuning(self.handle, n, c))
-        return dict(x_tile=c[0], y_tile=c[1], quads=c[2], src=c[3])
+        return dict(x_tile=c[0], y_tile=c[1], quads=c[2], src=c[3], src_cx=c[4])
+
+    def set_tuning(self, n, x_tile=0, y_tile=0, quads=0, src=-1, src_cx=0):
+        """Launch choices of harmonic n (see tuning())."""
+        c = (ctypes.c_int * 5)(x_tile, y_tile, quads, src, src_cx)
+        _check(_native.lib().nvp_plan_set_tuning(self.handle, n, c), self.ctx.handle)
 
     def execute(self, p1, outs=None):
         """p1 on g1 -> [p_2, ..., p_n_harm]."""

@@ -137,12 +137,18 @@ def test_autotuned_plan_matches_oracle_and_cache_round_trips(ctx, prec, tmp_path
         assert oracle.rel_l2(got, ref[n]) < TOL[prec], n
     plan.close()
     lines = open(cache).read().splitlines()
-    assert len(lines) == 3 and all(len(l.split()) == 5 for l in lines)
+    assert len(lines) == 3 and all(len(l.split()) == 6 for l in lines)
     # a plan of the same shapes takes its choices from the cache
     plan2 = P.CascadePlan(ctx, WATER, f0, g1, [gn[n] for n in range(2, 5)], prec=prec, order=3)
     plan2.autotune(cache, reps=2)
     assert [plan2.tuning(n) for n in range(2, 5)] == choices
     plan2.close()
+    # lines without the source chunk (the earlier format) read as the default chunk
+    open(cache, "w").write("".join(" ".join(l.split()[:5]) + "\n" for l in lines))
+    plan3 = P.CascadePlan(ctx, WATER, f0, g1, [gn[n] for n in range(2, 5)], prec=prec, order=3)
+    plan3.autotune(cache, reps=2)
+    assert [plan3.tuning(n) for n in range(2, 5)] == [dict(c, src_cx=0) for c in choices]
+    plan3.close()
 
 
 def test_batch_autotune_then_graph(ctx, tmp_path):
