@@ -227,9 +227,10 @@ __host__ __device__ constexpr int64_t octant_row(int64_t Mz) { return (Mz / 2 + 
 // ---------------------------------------------------------------- plans
 
 struct PlanDesc {
-    int S;      // number of stages
-    int r[6];   // radix of each stage
-    int P;      // threads per column
+    int S;        // number of stages
+    int r[6];     // radix of each stage
+    int P;        // threads per column
+    int P64 = 0;  // threads per column in FP64, where it differs from P
 };
 
 // Radix plans of the supported lengths.  The first stage reads global memory
@@ -265,11 +266,11 @@ __host__ __device__ constexpr PlanDesc plan_for(int L) {
     case 480: return PlanDesc{4, {16, 5, 3, 2, 0, 0}, 16};
     case 512: return PlanDesc{3, {8, 8, 8, 0, 0, 0}, 32};
     case 576: return PlanDesc{3, {8, 9, 8, 0, 0, 0}, 16};
-    case 640: return PlanDesc{4, {8, 4, 4, 5, 0, 0}, 16};
+    case 640: return PlanDesc{4, {8, 4, 4, 5, 0, 0}, 64, 16};
     case 720: return PlanDesc{3, {16, 9, 5, 0, 0, 0}, 32};
-    case 768: return PlanDesc{4, {3, 4, 8, 8, 0, 0}, 32};
+    case 768: return PlanDesc{4, {3, 4, 8, 8, 0, 0}, 64, 32};
     case 864: return PlanDesc{4, {16, 9, 3, 2, 0, 0}, 32};
-    case 896: return PlanDesc{5, {7, 4, 4, 4, 2, 0}, 32};
+    case 896: return PlanDesc{5, {7, 4, 4, 4, 2, 0}, 64, 32};
     case 960: return PlanDesc{4, {16, 5, 3, 4, 0, 0}, 32};
     case 1024: return PlanDesc{3, {16, 8, 8, 0, 0, 0}, 32};
     case 1152: return PlanDesc{4, {8, 9, 4, 4, 0, 0}, 32};
@@ -317,15 +318,19 @@ __host__ __device__ constexpr int plan_rmax(int L) {
     return m;
 }
 
-// Threads per column of the plan.
-template <typename R> __host__ __device__ constexpr int col_threads(int L) { return plan_for(L).P; }
+// Threads per column of the plan in precision R.  (At 640, 768 and 896 points
+// a complex64 column takes a whole wavefront, so that more columns' waves fit a
+// CU beside their LDS; the FP64 passes measured faster on fewer threads.)
+template <typename R> __host__ __device__ constexpr int col_threads(int L) {
+    return sizeof(R) == 8 && plan_for(L).P64 ? plan_for(L).P64 : plan_for(L).P;
+}
 // Threads per column of the FP64 octant-row pass of the kernel spectrum (its
 // first pass, fused with the tabulation): twice the plan's wherever a thread
 // would otherwise hold more than 8 complex values and every thread keeps a
 // butterfly in every stage, staying within one wavefront where the plan's
 // column does.  (The FP64 strided passes measured faster on the plan's own.)
 __host__ __device__ constexpr int kz_threads(int L) {
-    const int P = plan_for(L).P;
+    const int P = col_threads<double>(L);
     return (plan_regs(L, P) > 8 && 2 * P <= L / plan_rmax(L) && (2 * P <= 64 || P > 64)) ? 2 * P : P;
 }
 // Whether P threads per column fit one wavefront with no column straddling two.

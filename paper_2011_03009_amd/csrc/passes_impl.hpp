@@ -164,14 +164,17 @@ hipError_t zconv_slots(void *buf, const void *khat, int64_t Mx, int64_t My, int 
 // of esz bytes within `lds_cap` bytes and `thr_cap` threads.
 constexpr bool zconv_fits(int L, size_t esz, int slots, size_t lds_cap, int thr_cap) {
     const size_t slot = (size_t)(esz == sizeof(float2) ? slot_len<float>(L) : slot_len<double>(L)) * esz;
-    return (size_t)slots * slot <= lds_cap && slots * plan_for(L).P <= thr_cap;
+    const int P = esz == sizeof(float2) ? col_threads<float>(L) : col_threads<double>(L);
+    return (size_t)slots * slot <= lds_cap && slots * P <= thr_cap;
 }
 
 // Pencils per z-pass workgroup by default: two quads (8) when that keeps the
 // workgroup within 128 threads and 80 KiB of LDS, else one quad (4);
 // transforms too long for a quad in 160 KiB take 2 or 1.
 constexpr int zconv_slots_for(int L, size_t esz) {
-    return 4 * plan_for(L).P <= 128 && zconv_fits(L, esz, 8, 81920, 1024) ? 8
+    return 4 * (esz == sizeof(float2) ? col_threads<float>(L) : col_threads<double>(L)) <= 128 &&
+                   zconv_fits(L, esz, 8, 81920, 1024)
+               ? 8
          : zconv_fits(L, esz, 4, 163840, 1024) ? 4
          : zconv_fits(L, esz, 2, 163840, 1024) ? 2 : 1;
 }

@@ -275,7 +275,7 @@ template <typename R> struct Checker {
     // L/2+1 entries are staged as complex values, column-interleaved, in the
     // LDS array that the transform then reuses as one real plane per exchange.
     void kz() {
-        constexpr int PK = sizeof(R) == 8 ? kz_threads(L) : plan_for(L).P;
+        constexpr int PK = sizeof(R) == 8 ? kz_threads(L) : col_threads<R>(L);
         constexpr bool WL = wave_local_p(PK);
         using F = Fft<R, L, false, WL, PK>;
         auto h = random_column<R>(L, L / 2 + 1, 6);
@@ -379,8 +379,9 @@ int main() {
         c.cols();
     }
     if (g_fail) return 1;
-    std::printf("OK %d P=%d E=%d (FP64 octant rows: P=%d E=%d)\n", NVP_HOST_L, Fft<float, NVP_HOST_L>::P,
-                Fft<float, NVP_HOST_L>::E, kz_threads(NVP_HOST_L),
+    std::printf("OK %d P=%d E=%d (FP64: P=%d E=%d; FP64 octant rows: P=%d E=%d)\n", NVP_HOST_L,
+                Fft<float, NVP_HOST_L>::P, Fft<float, NVP_HOST_L>::E, Fft<double, NVP_HOST_L>::P,
+                Fft<double, NVP_HOST_L>::E, kz_threads(NVP_HOST_L),
                 Fft<double, NVP_HOST_L, false, false, kz_threads(NVP_HOST_L)>::E);
     return 0;
 }
