@@ -36,15 +36,15 @@ hipError_t launch_kradial(double2 *ktab, int64_t n, double h, double kr, double 
 
 template <typename R, int K, int NF>
 static hipError_t source_nf(const LdSource<R, K> &ld, const SourceArgs &a, void *out, int Ny, int cxl, hipStream_t s) {
-    auto kern = k_source<R, K, NF, NVP_SRC_TY, NVP_SRC_TZ, NVP_SRC_PRE, NVP_SRC_CXM>;
-    constexpr size_t lds = SrcLds<R, K, NF, NVP_SRC_TY, NVP_SRC_TZ, NVP_SRC_PRE, NVP_SRC_CXM>::BYTES;
-    static_assert(lds >= 1, "layout");
+    constexpr int RY = source_rows(sizeof(R)), PRE = source_pre(sizeof(R));
+    auto kern = k_source<R, K, NF, NVP_SRC_TY, NVP_SRC_TZ, RY, PRE, NVP_SRC_CXM>;
+    constexpr size_t lds = SrcLds<R, K, NF, NVP_SRC_TY, NVP_SRC_TZ, RY, PRE, NVP_SRC_CXM>::BYTES;
     if (lds != source_lds_bytes(NF, K, sizeof(R)) || cxl < 1 || cxl > NVP_SRC_CXM) return hipErrorInvalidValue;
     if (lds > 98304) return hipErrorInvalidValue;
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
-    dim3 grid((unsigned)((a.Nz + NVP_SRC_TZ - 1) / NVP_SRC_TZ), (unsigned)((Ny + NVP_SRC_TY - 1) / NVP_SRC_TY),
-              (unsigned)((a.Nx + cxl - 1) / cxl));
+    dim3 grid((unsigned)((a.Nz + NVP_SRC_TZ - 1) / NVP_SRC_TZ),
+              (unsigned)((Ny + RY * NVP_SRC_TY - 1) / (RY * NVP_SRC_TY)), (unsigned)((a.Nx + cxl - 1) / cxl));
     hipLaunchKernelGGL(kern, grid, dim3(NVP_SRC_TY * NVP_SRC_TZ), lds, s, ld, static_cast<cx<R> *>(out), Ny, cxl);
     return hipGetLastError();
 }

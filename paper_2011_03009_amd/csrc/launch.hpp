@@ -91,18 +91,24 @@ hipError_t launch_xsrc_c64(int L, const SourceArgs &a, const void *tw, hipStream
 hipError_t launch_xsrc_c128(int L, const SourceArgs &a, const void *tw, hipStream_t s);
 
 // Transfer + source build (k_source): f_n written to `out` [Nx][Ny][Nz];
-// workgroups of SRC_TY x SRC_TZ target columns walking cx <= SRC_CXM x planes,
-// each thread loading up to SRC_PRE entries of a source plane's block.
+// workgroups of SRC_TY x SRC_TZ threads, each thread owning source_rows target
+// rows (y) of a tile and loading up to source_pre entries of a source plane's
+// block, walking cx <= SRC_CXM x planes.
 #define NVP_SRC_TY 8
 #define NVP_SRC_TZ 32
-#define NVP_SRC_PRE 2
 #define NVP_SRC_CXM 64
+#ifndef NVP_SRC_RY32
+#define NVP_SRC_RY32 1
+#endif
+// Target rows per thread and block entries per thread, for reals of rsize bytes.
+constexpr int source_rows(size_t rsize) { return rsize == 4 ? NVP_SRC_RY32 : 1; }
+constexpr int source_pre(size_t rsize) { return source_rows(rsize) == 2 ? 3 : 2; }
 // LDS bytes of a launch for nf fields, K-point stencils and reals of rsize
 // bytes (4 or 8): the kernel's fixed layout.
 inline size_t source_lds_bytes(int nf, int K, size_t rsize) {
-    const size_t nt = (size_t)NVP_SRC_TY * NVP_SRC_TZ;
-    return (size_t)nf * (((size_t)NVP_SRC_PRE * nt + 2 * nt) * 2 * rsize +
-                         ((size_t)(NVP_SRC_TZ + NVP_SRC_TY) * K + (size_t)NVP_SRC_CXM * K) * rsize +
+    const size_t nt = (size_t)NVP_SRC_TY * NVP_SRC_TZ, ry = (size_t)source_rows(rsize);
+    return (size_t)nf * (((size_t)source_pre(rsize) * nt + 2 * ry * nt) * 2 * rsize +
+                         ((size_t)(NVP_SRC_TZ + ry * NVP_SRC_TY) * K + (size_t)NVP_SRC_CXM * K) * rsize +
                          (size_t)NVP_SRC_CXM * sizeof(int));
 }
 hipError_t launch_source_c64(const SourceArgs &a, void *out, int Ny, int cx, hipStream_t s);

@@ -928,14 +928,15 @@ nvp_status nvp_volume_potential_box(nvp_ctx *ctx, double k_re, double k_im, cons
 // Target x planes per source-kernel workgroup: enough x chunks for about
 // `want` workgroups per launch (0: 2048, or the environment variable
 // NVP_SRC_WGS, read once), and at most SRC_CXM planes.
-int source_chunk(const int64_t n[3], int64_t want = 0) {
+int source_chunk(const int64_t n[3], size_t rsize, int64_t want = 0) {
     static const int64_t dflt = [] {
         const char *e = getenv("NVP_SRC_WGS");
         const long v = e ? atol(e) : 0;
         return v > 0 ? (int64_t)v : (int64_t)2048;
     }();
     if (want <= 0) want = dflt;
-    const int64_t tiles = ((n[1] + NVP_SRC_TY - 1) / NVP_SRC_TY) * ((n[2] + NVP_SRC_TZ - 1) / NVP_SRC_TZ);
+    const int64_t ty = (int64_t)NVP_SRC_TY * nvp::source_rows(rsize);
+    const int64_t tiles = ((n[1] + ty - 1) / ty) * ((n[2] + NVP_SRC_TZ - 1) / NVP_SRC_TZ);
     int64_t chunks = std::max<int64_t>(1, std::min<int64_t>((want + tiles - 1) / tiles, n[0]));
     chunks = std::max<int64_t>(chunks, (n[0] + NVP_SRC_CXM - 1) / NVP_SRC_CXM);  // at most SRC_CXM planes each
     return (int)((n[0] + chunks - 1) / chunks);
@@ -1022,11 +1023,12 @@ nvp_status plan_layout(nvp_ctx *ctx, nvp_plan *p, const nvp_grid *gn, std::vecto
         }
     }
     // Source kernel: per field, the largest source block (SY x SZ) that a tile
-    // of SRC_TY x SRC_TZ target columns touches; used when every block fits
-    // the kernel's per-thread loads and two z rows per thread, its LDS fits 96
-    // KiB and every grid involved has fewer than 2^32 elements.
+    // of (SRC_TY source_rows) x SRC_TZ target columns touches; used when every
+    // block fits the kernel's per-thread loads and z rows, its LDS fits 96 KiB
+    // and every grid involved has fewer than 2^32 elements.
+    const size_t rsize = csize(p->prec) / 2;
     for (auto &h : p->h) {
-        const int64_t TY = NVP_SRC_TY, TZ = NVP_SRC_TZ;
+        const int64_t TY = NVP_SRC_TY * nvp::source_rows(rsize), TZ = NVP_SRC_TZ;
         bool small = true;  // 32-bit offsets
         for (int m = 1; m <= h.n; ++m) {
             const nvp_grid &gm = m == 1 ? p->g1 : p->h[m - 2].g;
@@ -1048,9 +1050,11 @@ nvp_status plan_layout(nvp_ctx *ctx, nvp_plan *p, const nvp_grid *gn, std::vecto
             msy = std::max(msy, span[1]);
             mblk = std::max(mblk, span[1] * span[2]);
         }
-        const size_t lds = nvp::source_lds_bytes(h.n - 1, K, csize(p->prec) / 2);
-        h.src_cx = source_chunk(h.g.n);
-        h.src_lds = small && msy <= 2 * TY && mblk <= NVP_SRC_PRE * TY * TZ && lds <= 98304 ? (int64_t)lds : 0;
+        const size_t lds = nvp::source_lds_bytes(h.n - 1, K, rsize);
+        h.src_cx = source_chunk(h.g.n, rsize);
+        h.src_lds = small && msy <= 2 * TY && mblk <= nvp::source_pre(rsize) * NVP_SRC_TY * TZ && lds <= 98304
+                        ? (int64_t)lds
+                        : 0;
     }
     *tbytes_out = tbytes;
     *maxA_out = maxA;
@@ -1593,7 +1597,7 @@ nvp_status autotune_plan(nvp_plan *plan, std::map<std::string, Tune> &cache, int
             const Tune base = best_t;
             for (int64_t want : {(int64_t)1024, (int64_t)4096}) {
                 Tune t = base;
-                t.src_cx = source_chunk(h.g.n, want);
+                t.src_cx = source_chunk(h.g.n, csize(plan->prec) / 2, want);
                 if (t.src_cx != h.src_cx && st == NVP_OK) try_choice(t);
             }
         }

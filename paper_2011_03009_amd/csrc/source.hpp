@@ -37,15 +37,16 @@ __device__ __forceinline__ int div_small(int a, float inv_b) { return (int)(((fl
 // interpolation work and used after it.
 //
 // LDS (SrcLds, fixed offsets): per field a source-plane region of PRE TY TZ
-// entries and a z-row region of 2 TY TZ entries, then per field the z and y
-// weights ((TZ + TY) K reals), the x weights (CXM K reals) and the x
-// stencils' ends (CXM ints).  Limits the host checks: SY <= 2 TY,
-// SY * SZ <= PRE * TY * TZ, cx <= CXM and every grid below 2^32 elements
-// (32-bit offsets).
-template <typename R, int K, int NF, int TY, int TZ, int PRE, int CXM> struct SrcLds {
-    static constexpr int NT = TY * TZ, SREG = PRE * NT, TREG = 2 * NT;
+// entries and a z-row region of 2 RY TY TZ entries, then per field the z and
+// y weights ((TZ + RY TY) K reals), the x weights (CXM K reals) and the x
+// stencils' ends (CXM ints).  Each thread owns RY target rows of the tile
+// (ty, ty + TY, ...), which spreads the per-plane control and synchronisation
+// over RY voxels.  Limits the host checks: SY <= 2 RY TY, SY * SZ <= PRE TY TZ,
+// cx <= CXM and every grid below 2^32 elements (32-bit offsets).
+template <typename R, int K, int NF, int TY, int TZ, int RY, int PRE, int CXM> struct SrcLds {
+    static constexpr int NT = TY * TZ, TYT = RY * TY, ZR = 2 * RY, SREG = PRE * NT, TREG = ZR * NT;
     static constexpr size_t WOFF = (size_t)NF * (SREG + TREG) * sizeof(cx<R>);  // bytes
-    static constexpr size_t WPER = (size_t)((TZ + TY) * K + CXM * K) * sizeof(R);
+    static constexpr size_t WPER = (size_t)((TZ + TYT) * K + CXM * K) * sizeof(R);
     static constexpr size_t XOFF = WOFF + NF * WPER;
     static constexpr size_t BYTES = XOFF + (size_t)NF * CXM * sizeof(int);
     unsigned char *base;
@@ -55,42 +56,55 @@ template <typename R, int K, int NF, int TY, int TZ, int PRE, int CXM> struct Sr
     }
     __device__ __forceinline__ R *wz(int i) const { return reinterpret_cast<R *>(base + WOFF + i * WPER); }
     __device__ __forceinline__ R *wy(int i) const { return wz(i) + TZ * K; }
-    __device__ __forceinline__ R *wx(int i) const { return wz(i) + (TZ + TY) * K; }
+    __device__ __forceinline__ R *wx(int i) const { return wz(i) + (TZ + TYT) * K; }
     __device__ __forceinline__ int *xend(int i) const { return reinterpret_cast<int *>(base + XOFF) + i * CXM; }
 };
 
-template <typename R, int K, int NF, int TY, int TZ, int PRE, int CXM>
+template <typename R, int K, int NF, int TY, int TZ, int RY, int PRE, int CXM>
 __device__ __forceinline__ void source_tile(const LdSource<R, K> &src, cx<R> *__restrict__ out, int Ny, int cxl,
                                             unsigned char *lds, int tid, int bz, int by, int bx) {
-    using L = SrcLds<R, K, NF, TY, TZ, PRE, CXM>;
-    constexpr int NT = L::NT;
-    static_assert(NT >= TY * K && NT >= TZ * K, "one weight per thread at set-up");
+    using L = SrcLds<R, K, NF, TY, TZ, RY, PRE, CXM>;
+    constexpr int NT = L::NT, TYT = L::TYT, ZR = L::ZR;
+    static_assert(NT >= TYT * K && NT >= TZ * K, "one weight per thread at set-up");
     static_assert(K == 2 || K == 4, "ring positions are taken modulo K with a mask");
     const L lay{lds};
     const int Nx = src.Nx, Nz = src.Nz;
     const int tz = tid % TZ, ty = tid / TZ;
-    const int iz0 = bz * TZ, iy0 = by * TY, ix0 = bx * cxl;
-    const int iz1 = min(iz0 + TZ, Nz), iy1 = min(iy0 + TY, Ny), ix1 = min(ix0 + cxl, Nx);
-    const int iy = iy0 + ty, iz = iz0 + tz;
-    const bool oky = iy < Ny, okz = iz < Nz;
+    const int iz0 = bz * TZ, iy0 = by * TYT, ix0 = bx * cxl;
+    const int iz1 = min(iz0 + TZ, Nz), iy1 = min(iy0 + TYT, Ny), ix1 = min(ix0 + cxl, Nx);
+    const int iz = iz0 + tz;
+    const bool okz = iz < Nz;
+    int iy[RY];
+    bool oky[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        iy[r] = iy0 + ty + r * TY;
+        oky[r] = iy[r] < Ny;
+    }
     auto plane = [](const FieldDev<R> &g, int x) { return g.p + (uint32_t)x * (uint32_t)g.s0; };
 
     int nxt[NF], endx[NF], blk[NF], szs[NF], sys[NF];  // workgroup-uniform
-    int oz[NF], oy[NF];
+    int oz[NF], oy[NF][RY];
     uint32_t goff[NF][PRE];  // this thread's share of a plane's block, relative to the plane
     cx<R> pre[NF][PRE];      // the field's next plane, in flight
-    cx<R> ring[NF][K];       // source plane p, interpolated at (iy, iz), at ring[i][p % K]
+    cx<R> ring[NF][RY][K];   // source plane p, interpolated at (iy[r], iz), at ring[i][r][p % K]
     // a field on the target grid is read at (ix, iyc, izc), in bounds for every thread
-    const uint32_t idoff = (uint32_t)min(iy, Ny - 1) * (uint32_t)Nz + (uint32_t)min(iz, Nz - 1);
+    uint32_t idoff[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) idoff[r] = (uint32_t)min(iy[r], Ny - 1) * (uint32_t)Nz + (uint32_t)min(iz, Nz - 1);
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
         const FieldDev<R> &g = src.f[i];
 #pragma unroll
-        for (int k = 0; k < K; ++k) ring[i][k] = czero<R>();
+        for (int r = 0; r < RY; ++r)
+#pragma unroll
+            for (int k = 0; k < K; ++k) ring[i][r][k] = czero<R>();
 #pragma unroll
         for (int j = 0; j < PRE; ++j) pre[i][j] = czero<R>();
         if (g.identity) {
-            nxt[i] = endx[i] = blk[i] = szs[i] = sys[i] = oz[i] = oy[i] = 0;
+            nxt[i] = endx[i] = blk[i] = szs[i] = sys[i] = oz[i] = 0;
+#pragma unroll
+            for (int r = 0; r < RY; ++r) oy[i][r] = 0;
 #pragma unroll
             for (int j = 0; j < PRE; ++j) goff[i][j] = 0;
             continue;
@@ -112,22 +126,26 @@ __device__ __forceinline__ void source_tile(const LdSource<R, K> &src, cx<R> *__
             pre[i][j] = plane(g, nxt[i])[goff[i][j]];
         }
         oz[i] = okz ? g.b[2][iz] - sz0 : 0;
-        oy[i] = oky ? g.b[1][iy] - sy0 : 0;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) oy[i][r] = oky[r] ? g.b[1][iy[r]] - sy0 : 0;
         // the tile's z and y weights (zero beyond the grid) and the chunk's x tables
         R *wz = lay.wz(i), *wy = lay.wy(i), *wx = lay.wx(i);
         int *xe = lay.xend(i);
         if (tid < TZ * K) wz[tid] = iz0 + tid / K < Nz ? g.w[2][iz0 * K + tid] : R(0);
-        if (tid < TY * K) wy[tid] = iy0 + tid / K < Ny ? g.w[1][iy0 * K + tid] : R(0);
+        if (tid < TYT * K) wy[tid] = iy0 + tid / K < Ny ? g.w[1][iy0 * K + tid] : R(0);
         for (int e = tid; e < (ix1 - ix0) * K; e += NT) wx[e] = g.w[0][ix0 * K + e];
         for (int e = tid; e < ix1 - ix0; e += NT) xe[e] = g.b[0][ix0 + e] + K;
     }
     __syncthreads();
 
     for (int ix = ix0; ix < ix1; ++ix) {
-        cx<R> idv[NF];
+        cx<R> idv[NF][RY];
 #pragma unroll
         for (int i = 0; i < NF; ++i)
-            if (src.f[i].identity) idv[i] = plane(src.f[i], ix)[idoff];
+            if (src.f[i].identity) {
+#pragma unroll
+                for (int r = 0; r < RY; ++r) idv[i][r] = plane(src.f[i], ix)[idoff[r]];
+            }
         int need[NF];
 #pragma unroll
         for (int i = 0; i < NF; ++i)
@@ -151,7 +169,7 @@ __device__ __forceinline__ void source_tile(const LdSource<R, K> &src, cx<R> *__
                 for (int j = 0; j < PRE; ++j) pre[i][j] = P[goff[i][j]];
             }
             __syncthreads();
-            // z: rows ty and ty + TY of the block, at this thread's z stencil
+            // z: rows ty, ty + TY, ... of the block, at this thread's z stencil
 #pragma unroll
             for (int i = 0; i < NF; ++i) {
                 if (!(act >> i & 1)) continue;
@@ -162,7 +180,7 @@ __device__ __forceinline__ void source_tile(const LdSource<R, K> &src, cx<R> *__
 #pragma unroll
                 for (int d = 0; d < K; ++d) w[d] = wz[d];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                for (int h = 0; h < ZR; ++h) {
                     const int row = ty + h * TY;
                     if (row < sys[i]) {
                         cx<R> acc = czero<R>();
@@ -173,30 +191,34 @@ __device__ __forceinline__ void source_tile(const LdSource<R, K> &src, cx<R> *__
                 }
             }
             __syncthreads();
-            // y: this thread's (iy, iz), into the ring at the plane's position
+            // y: this thread's (iy[r], iz), into the ring at the plane's position
 #pragma unroll
             for (int i = 0; i < NF; ++i) {
                 if (!(act >> i & 1)) continue;
                 const cx<R> *T = lay.zrows(i);
-                const R *wy = lay.wy(i) + ty * K;
-                cx<R> acc = czero<R>();
-#pragma unroll
-                for (int c = 0; c < K; ++c) acc = cadd<R>(acc, cscale<R>(T[(oy[i] + c) * TZ + tz], wy[c]));
                 const int pos = nxt[i] & (K - 1);
 #pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (pos == k) ring[i][k] = acc;
+                for (int r = 0; r < RY; ++r) {
+                    const R *wy = lay.wy(i) + (ty + r * TY) * K;
+                    cx<R> acc = czero<R>();
+#pragma unroll
+                    for (int c = 0; c < K; ++c) acc = cadd<R>(acc, cscale<R>(T[(oy[i][r] + c) * TZ + tz], wy[c]));
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        if (pos == k) ring[i][r][k] = acc;
+                }
                 ++nxt[i];
             }
         }
         // x: the ring holds planes need - K .. need - 1, the stencil of ix;
         // plane need - K + b sits at (need + b) % K
-        cx<R> v[NF];
+        cx<R> v[NF][RY];
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
             const FieldDev<R> &g = src.f[i];
             if (g.identity) {
-                v[i] = idv[i];
+#pragma unroll
+                for (int r = 0; r < RY; ++r) v[i][r] = idv[i][r];
                 continue;
             }
             const R *wx = lay.wx(i) + (ix - ix0) * K;
@@ -204,33 +226,38 @@ __device__ __forceinline__ void source_tile(const LdSource<R, K> &src, cx<R> *__
 #pragma unroll
             for (int b = 0; b < K; ++b) w[b] = wx[b];
             const int pos = need[i] & (K - 1);
-            cx<R> acc = czero<R>();
 #pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (pos == k) {
+            for (int r = 0; r < RY; ++r) {
+                cx<R> acc = czero<R>();
 #pragma unroll
-                    for (int b = 0; b < K; ++b) acc = cadd<R>(acc, cscale<R>(ring[i][(k + b) & (K - 1)], w[b]));
-                }
-            v[i] = acc;
+                for (int k = 0; k < K; ++k)
+                    if (pos == k) {
+#pragma unroll
+                        for (int b = 0; b < K; ++b) acc = cadd<R>(acc, cscale<R>(ring[i][r][(k + b) & (K - 1)], w[b]));
+                    }
+                v[i][r] = acc;
+            }
         }
-        if (oky && okz) {
-            // sum_{b + c = NF - 1} v_b v_c, the source term of harmonic NF + 1
-            cx<R> f = czero<R>();
 #pragma unroll
-            for (int b = 0; b < NF; ++b) f = cadd<R>(f, cmul<R>(v[b], v[NF - 1 - b]));
-            out[((uint32_t)ix * (uint32_t)Ny + (uint32_t)iy) * (uint32_t)Nz + (uint32_t)iz] = f;
-        }
+        for (int r = 0; r < RY; ++r)
+            if (oky[r] && okz) {
+                // sum_{b + c = NF - 1} v_b v_c, the source term of harmonic NF + 1
+                cx<R> f = czero<R>();
+#pragma unroll
+                for (int b = 0; b < NF; ++b) f = cadd<R>(f, cmul<R>(v[b][r], v[NF - 1 - b][r]));
+                out[((uint32_t)ix * (uint32_t)Ny + (uint32_t)iy[r]) * (uint32_t)Nz + (uint32_t)iz] = f;
+            }
     }
 }
 
 #ifndef NVP_HOST_EMULATION
 extern __shared__ __align__(16) unsigned char nvp_smem[];
 
-template <typename R, int K, int NF, int TY, int TZ, int PRE, int CXM>
+template <typename R, int K, int NF, int TY, int TZ, int RY, int PRE, int CXM>
 __global__ void __launch_bounds__(TY *TZ)
 k_source(LdSource<R, K> src, cx<R> *__restrict__ out, int Ny, int cxl) {
-    source_tile<R, K, NF, TY, TZ, PRE, CXM>(src, out, Ny, cxl, nvp_smem, (int)threadIdx.x, (int)blockIdx.x,
-                                            (int)blockIdx.y, (int)blockIdx.z);
+    source_tile<R, K, NF, TY, TZ, RY, PRE, CXM>(src, out, Ny, cxl, nvp_smem, (int)threadIdx.x, (int)blockIdx.x,
+                                                (int)blockIdx.y, (int)blockIdx.z);
 }
 #endif
 

@@ -7,7 +7,8 @@
 // tables (source planes advancing by 0, 1 or 2 per target voxel, clamped at
 // both ends, as interpolation onto finer, equal or coarser grids makes them),
 // random weights, fields on the target grid among them, ragged tiles in y and
-// z and ragged x chunks, in FP32 and FP64, for K = 2 and 4 and 1 to 4 and 7
+// z and ragged x chunks, one or two target rows per thread, in FP32 and FP64,
+// for K = 2 and 4 and 1 to 4 and 7
 // fields.  Each output is compared with the separable transfer and the
 // source product summed directly in long double, and must be written.  Built
 // with AddressSanitizer: an index outside a field, a table, the output or the
@@ -39,7 +40,7 @@ inline void wave_sync() { tl_bar->arrive_and_wait(); }  // not used by the sourc
 using namespace nvp;
 using cld = std::complex<long double>;
 
-constexpr int TY = 8, TZ = 32, PRE = 2, CXM = 16;
+constexpr int TY = 8, TZ = 32, CXM = 16;  // threads along y and z; the largest x chunk
 
 #define CHECK(c, ...)                          \
     do {                                       \
@@ -77,7 +78,8 @@ std::vector<int> monotone_table(std::mt19937_64 &g, int n_t, int n_s, int K, dou
     return b;
 }
 
-template <typename R, int K, int NF> struct Case {
+template <typename R, int K, int NF, int RY, int PRE> struct Case {
+    static constexpr int TYT = RY * TY;  // target rows of a tile
     int N[3];
     std::vector<int> identity;
     std::vector<std::array<int, 3>> ns;
@@ -142,18 +144,18 @@ template <typename R, int K, int NF> struct Case {
         for (int i = 0; i < NF; ++i) {
             if (identity[i]) continue;
             int sy = 0, sz = 0;
-            for (int i0 = 0; i0 < N[1]; i0 += TY) sy = std::max(sy, b[i][1][std::min(i0 + TY, N[1]) - 1] + K - b[i][1][i0]);
+            for (int i0 = 0; i0 < N[1]; i0 += TYT) sy = std::max(sy, b[i][1][std::min(i0 + TYT, N[1]) - 1] + K - b[i][1][i0]);
             for (int i0 = 0; i0 < N[2]; i0 += TZ) sz = std::max(sz, b[i][2][std::min(i0 + TZ, N[2]) - 1] + K - b[i][2][i0]);
             msy = std::max(msy, sy);
             mblk = std::max(mblk, sy * sz);
         }
-        if (msy > 2 * TY || mblk > PRE * TY * TZ) return false;  // the host takes the fused path
+        if (msy > 2 * TYT || mblk > PRE * TY * TZ) return false;  // the host takes the fused path
         CHECK(cx_len <= CXM, "chunk %d beyond %d", cx_len, CXM);
         Buf<cx<R>> out((size_t)N[0] * N[1] * N[2]);
         const R nan = std::numeric_limits<R>::quiet_NaN();
         for (size_t e = 0; e < out.n; ++e) out[e].x = out[e].y = nan;
-        const int gz = (N[2] + TZ - 1) / TZ, gy = (N[1] + TY - 1) / TY, gx = (N[0] + cx_len - 1) / cx_len;
-        using Lay = SrcLds<R, K, NF, TY, TZ, PRE, CXM>;
+        const int gz = (N[2] + TZ - 1) / TZ, gy = (N[1] + TYT - 1) / TYT, gx = (N[0] + cx_len - 1) / cx_len;
+        using Lay = SrcLds<R, K, NF, TY, TZ, RY, PRE, CXM>;
         const size_t lds_n = Lay::BYTES;
         for (int bx = 0; bx < gx; ++bx)
             for (int by = 0; by < gy; ++by)
@@ -166,7 +168,7 @@ template <typename R, int K, int NF> struct Case {
                     for (int t = 0; t < TY * TZ; ++t)
                         th.emplace_back([&, t] {
                             tl_bar = &bar;
-                            source_tile<R, K, NF, TY, TZ, PRE, CXM>(src, out.p, N[1], cx_len, lds.p, t, bz, by, bx);
+                            source_tile<R, K, NF, TY, TZ, RY, PRE, CXM>(src, out.p, N[1], cx_len, lds.p, t, bz, by, bx);
                         });
                     for (auto &x : th) x.join();
                 }
@@ -213,7 +215,7 @@ template <typename R, int K, int NF> struct Case {
     }
 };
 
-template <typename R, int K, int NF> int cases(unsigned seed) {
+template <typename R, int K, int NF, int RY = 1, int PRE = 2> int cases(unsigned seed) {
     std::mt19937_64 g(seed);
     const long double tol = sizeof(R) == 8 ? 1e-12L : 1e-5L;
     // (Nx, Ny, Nz, x chunk, P(no advance), P(advance by 2))
@@ -230,7 +232,7 @@ template <typename R, int K, int NF> int cases(unsigned seed) {
     };
     int ran = 0;
     for (const Shape &s : shapes) {
-        Case<R, K, NF> c;
+        Case<R, K, NF, RY, PRE> c;
         c.N[0] = s.nx;
         c.N[1] = s.ny;
         c.N[2] = s.nz;
@@ -250,7 +252,12 @@ int main() {
     n += cases<double, 4, 4>(7);
     n += cases<double, 2, 2>(8);
     n += cases<double, 4, 7>(9);
-    CHECK(n >= 40, "only %d cases fit the kernel's limits", n);
+    // two target rows per thread
+    n += cases<float, 4, 1, 2, 3>(11);
+    n += cases<float, 4, 4, 2, 3>(12);
+    n += cases<float, 2, 3, 2, 3>(13);
+    n += cases<double, 4, 3, 2, 3>(14);
+    CHECK(n >= 60, "only %d cases fit the kernel's limits", n);
     std::printf("OK %d\n", n);
     return 0;
 }

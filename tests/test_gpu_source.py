@@ -27,7 +27,7 @@ TOL = {P.NVP_C64: 1e-5, P.NVP_C128: 1e-12}
 DT = {P.NVP_C64: torch.complex64, P.NVP_C128: torch.complex128}
 E_INVALID, E_UNSUPPORTED = 1, 4  # NVP_E_INVALID, NVP_E_UNSUPPORTED
 FOCUS = (15e-3, 0.0, 0.0)
-TARGET = (23, 19, 70)  # 3 x 3 tiles of 8 x 32 (y, z), ragged in both
+TARGET = (23, 19, 70)  # 3 x 3 tiles of 8 x 32 (y, z) columns, ragged in both
 
 
 def say(*a):
