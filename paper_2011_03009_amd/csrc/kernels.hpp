@@ -14,6 +14,7 @@
 
 #include "fft_core.hpp"
 #include "field_dev.hpp"
+#include "kz_tasks.hpp"
 #include "launch.hpp"
 
 namespace nvp {
@@ -400,7 +401,7 @@ k_zconv_multi(const ZconvTaskArgs *__restrict__ tasks, int ntasks, const cx<R> *
 template <int L, int PW, bool TWL>
 __global__ void __launch_bounds__(PW *kz_threads(L))
 k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, int64_t Nz,
-     const double2 *__restrict__ ktab, const double2 *__restrict__ tw) {
+     const double2 *__restrict__ ktab, const double2 *__restrict__ tw, int64_t ntasks) {
     constexpr bool WL = wave_local_p(kz_threads(L));
     using F = Fft<double, L, false, WL, kz_threads(L)>;
     constexpr int HZ = L / 2 + 1;
@@ -408,15 +409,12 @@ k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, 
     constexpr int NT = plan_tw_len(L, false);
     cx<double> *lds = reinterpret_cast<cx<double> *>(nvp_smem);
     const int tid = threadIdx.x, t = tid % F::P, c = tid / F::P;
-    const int64_t row = (int64_t)blockIdx.x * PW + c;
-    const bool act = row < Hx * Hy;
-    // (i, j) of the row: the workgroup's first row is split with one 32-bit
-    // division on uniform values (the host keeps Hx Hy below 2^31), then
-    // carried forward by c
-    const uint32_t hy = (uint32_t)Hy, r0 = blockIdx.x * (uint32_t)PW, i0 = r0 / hy;
-    uint32_t ui = i0, uj = r0 - i0 * hy + (uint32_t)c;
-    while (uj >= hy) uj -= hy, ++ui;
-    const int64_t i = act ? ui : 0, jj = act ? uj : 0;
+    // the slot's task: one octant row, or the rows (i, j) and (j, i) of the
+    // square of nonzero rows, which hold the same values
+    const int64_t q = (int64_t)blockIdx.x * PW + c;
+    const bool act = q < ntasks;
+    const KzTask tk = kz_task(act ? q : 0, Hx, Hy, Nx < Ny ? Nx : Ny);
+    const int64_t i = tk.i, jj = tk.j;
     cx<double> *my = lds + c * SL;
     cx<double> *twl = lds + PW * SL;  // the twiddle table, staged when it fits (TWL)
     if constexpr (TWL) {
@@ -443,7 +441,10 @@ k_kz(double2 *__restrict__ out, int64_t Hx, int64_t Hy, int64_t Nx, int64_t Ny, 
     F::template run<-1, true>(
         t, twf, [&](int m) { return my[padded<double>(m <= L / 2 ? m : L - m)]; },
         [&](int m, cx<double> v) {
-            if (act && m < HZ) out[row * octant_row(L) + m] = v;
+            if (act && m < HZ) {
+                out[tk.r0 * octant_row(L) + m] = v;
+                if (tk.r1 != tk.r0) out[tk.r1 * octant_row(L) + m] = v;
+            }
         },
         PencilSlot<double>{my});
 }

@@ -202,10 +202,11 @@ hipError_t kz_impl(double2 *out, const int64_t H[3], const int64_t N[3], const d
     static_assert(lds <= 163840 && PW * kz_threads(L) <= 1024, "kernel-spectrum workgroup too large");
     static const hipError_t attr = allow_lds(kern, lds);
     if (attr != hipSuccess) return attr;
-    const int64_t rows = H[0] * H[1];
-    if (rows > 0x7fffffff - PW) return hipErrorInvalidValue;  // row indices are 32-bit in the kernel
-    hipLaunchKernelGGL(kern, dim3((unsigned)((rows + PW - 1) / PW)), dim3(PW * kz_threads(L)), lds, s, out, H[0],
-                       H[1], N[0], N[1], N[2], ktab, static_cast<const double2 *>(tw));
+    // one task per octant row, except the mirror pairs (i, j), (j, i) of the nonzero square
+    const int64_t ntasks = kz_task_count(H[0], H[1], N[0] < N[1] ? N[0] : N[1]);
+    if (ntasks > 0x7fffffff - PW || N[0] > H[0] || N[1] > H[1]) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kern, dim3((unsigned)((ntasks + PW - 1) / PW)), dim3(PW * kz_threads(L)), lds, s, out, H[0],
+                       H[1], N[0], N[1], N[2], ktab, static_cast<const double2 *>(tw), ntasks);
     return hipGetLastError();
 }
 

@@ -92,3 +92,22 @@ def test_source_kernel_on_host_threads():
         os.replace(exe + ".tmp", exe)
     r = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=600)
     assert r.returncode == 0 and r.stdout.startswith("OK"), r.stdout[-3000:]
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_kernel_tabulation_tasks_cover_every_row_once():
+    """The tasks of the kernel-tabulation pass (csrc/kz_tasks.hpp) on octant shapes of the paper's
+    workloads and small edge cases: every row written once, indices in the octant, mirror pairs
+    inside the square of nonzero rows (tests/fft_host/kz_tasks_check.cpp)."""
+    os.makedirs(BUILD, exist_ok=True)
+    exe = os.path.join(BUILD, "kz_tasks_check")
+    srcs = [os.path.join(HERE, "kz_tasks_check.cpp"), os.path.join(CSRC, "kz_tasks.hpp"),
+            os.path.join(CSRC, "fft_core.hpp"), os.path.join(HERE, "hip", "hip_runtime.h")]
+    if not os.path.exists(exe) or any(os.path.getmtime(s) > os.path.getmtime(exe) for s in srcs):
+        cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer",
+               "-I" + HERE, "-I" + CSRC, srcs[0], "-o", exe + ".tmp"]
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+        assert r.returncode == 0, "compile failed:\n" + r.stdout[-3000:]
+        os.replace(exe + ".tmp", exe)
+    r = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.startswith("OK"), r.stdout[-3000:]
