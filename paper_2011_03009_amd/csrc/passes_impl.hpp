@@ -17,9 +17,10 @@ template <typename R> constexpr int strided_cols(int L) {
 }
 
 // Whether the contiguous FP64 kernel stages its twiddle table in LDS: when
-// the table and one pencil fit 128 KiB.
+// the table and one pencil fit 128 KiB, up to 1024 points.  (Beyond, the
+// staged table leaves room for only one workgroup of four rows per CU.)
 template <typename R> constexpr bool contig_tw_lds(int L) {
-    return (size_t)(twiddle_table_len(L) + slot_len<R>(L)) * sizeof(cx<R>) <= 131072;
+    return L <= 1024 && (size_t)(twiddle_table_len(L) + slot_len<R>(L)) * sizeof(cx<R>) <= 131072;
 }
 
 // Pencils per workgroup of the contiguous FP64 kernel: about 256 threads,
