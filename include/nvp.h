@@ -27,6 +27,9 @@
  *     asynchronous faults surface at nvp_ctx_sync().
  *   - Contexts and plans are owned by the library and released only by their
  *     _destroy call.  A plan is bound to its context's device and stream.
+ *   - A context outlives the plans, batches and networks made with it:
+ *     nvp_ctx_destroy fails with NVP_E_STATE, and frees nothing, while any
+ *     of them has not been destroyed.
  */
 #ifndef NVP_H
 #define NVP_H

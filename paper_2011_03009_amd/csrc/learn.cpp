@@ -16,6 +16,8 @@ static_assert(NVP_QBOX_MAX_COUNT == NVP_QBOX_MAX, "box count limit");
 
 namespace nvp {
 int ctx_device(const nvp_ctx *c);
+void ctx_attach(nvp_ctx *c);  // a network made with the context, until its destroy call
+void ctx_detach(nvp_ctx *c);
 hipStream_t ctx_stream(const nvp_ctx *c);
 nvp_status ctx_fail(nvp_ctx *c, nvp_status s, const char *msg);
 nvp_status ctx_hip_fail(nvp_ctx *c, const char *what, hipError_t e);
@@ -179,6 +181,7 @@ nvp_status nvp_boxnet_create(nvp_ctx *ctx, int max_batch, nvp_boxnet **out) {
         delete bn;
         return ctx_hip_fail(ctx, "nvp_boxnet_create: initialisation", e);
     }
+    nvp::ctx_attach(ctx);
     *out = bn;
     return NVP_OK;
 }
@@ -277,6 +280,7 @@ nvp_status nvp_boxnet_destroy(nvp_boxnet *bn) {
     (void)hipSetDevice(nvp::ctx_device(bn->ctx));
     (void)hipStreamSynchronize(nvp::ctx_stream(bn->ctx));
     if (bn->blob) (void)hipFree(bn->blob);
+    nvp::ctx_detach(bn->ctx);
     delete bn;
     return NVP_OK;
 }

@@ -62,6 +62,7 @@ struct nvp_ctx {
     VpCache vp;
     size_t max_lds = 0;
     int quad = NVP_QUAD_BALL;  // quadrature rule of plans and potentials created from now on
+    int users = 0;             // live plans, batches and networks made with this context
 };
 
 namespace {
@@ -678,6 +679,8 @@ nvp_status noalloc_setup(nvp_ctx *ctx);
 
 // Context access for the other translation units behind the C ABI.
 int ctx_device(const nvp_ctx *c) { return c->device; }
+void ctx_attach(nvp_ctx *c) { ++c->users; }
+void ctx_detach(nvp_ctx *c) { --c->users; }
 hipStream_t ctx_stream(const nvp_ctx *c) { return c->stream; }
 nvp_status ctx_fail(nvp_ctx *c, nvp_status s, const char *msg) { return fail(c, s, msg); }
 nvp_status ctx_hip_fail(nvp_ctx *c, const char *what, hipError_t e) { return hip_fail(c, what, e); }
@@ -776,6 +779,9 @@ nvp_status nvp_quadrature_weights(int rule, double k_re, double k_im, double h, 
 
 nvp_status nvp_ctx_destroy(nvp_ctx *ctx) {
     if (!ctx) return NVP_E_INVALID;
+    if (ctx->users > 0)  // their destroy calls still reach the context
+        return fail(ctx, NVP_E_STATE,
+                    "nvp_ctx_destroy: " + std::to_string(ctx->users) + " plans, batches or networks still use this context");
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->tw_blob) (void)hipFree(ctx->tw_blob);
@@ -1120,6 +1126,7 @@ nvp_status nvp_plan_cascade(nvp_ctx *ctx, const nvp_medium *med, double f0, int 
     p->bytes_A = maxA;
     p->bytes_B = maxB;
     p->bytes_tables = tbytes;
+    ++ctx->users;
     *out = p;
     return NVP_OK;
 }
@@ -1419,6 +1426,7 @@ nvp_status nvp_plan_destroy(nvp_plan *plan) {
     (void)hipSetDevice(plan->ctx->device);
     (void)hipStreamSynchronize(plan->ctx->stream);
     free_plan_memory(plan);
+    --plan->ctx->users;
     delete plan;
     return NVP_OK;
 }
@@ -2009,6 +2017,7 @@ nvp_status nvp_batch_create(nvp_ctx *ctx, int count, const nvp_problem *problems
         b->off.push_back(b->n_out);
         b->n_out += pr.n_harm - 1;
     }
+    ++ctx->users;
     *out = b;
     return NVP_OK;
 }
@@ -2087,6 +2096,7 @@ nvp_status nvp_batch_destroy(nvp_batch *b) {
     (void)hipSetDevice(b->ctx->device);
     (void)hipStreamSynchronize(b->ctx->stream);
     free_batch(b);
+    --b->ctx->users;
     delete b;
     return NVP_OK;
 }

@@ -7,6 +7,7 @@ library every call raises.
 """
 
 import ctypes
+import weakref
 
 import torch
 
@@ -160,12 +161,16 @@ class Context:
         h = ctypes.c_void_p()
         _check(_native.lib().nvp_ctx_create(dev.index or 0, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
         self.handle = h
+        self._users = weakref.WeakSet()  # plans, batches and networks made with this context
 
     def sync(self):
         _check(_native.lib().nvp_ctx_sync(self.handle), self.handle)
 
     def close(self):
+        """Destroys the context after every plan, batch and network still made with it."""
         if self.handle:
+            for u in list(self._users):
+                u.close()
             _native.lib().nvp_ctx_destroy(self.handle)
             self.handle = None
 
@@ -361,6 +366,7 @@ class CascadePlan:
         _check(_native.lib().nvp_plan_cascade(ctx.handle, ctypes.byref(medium(med)), f0, self.n_harm,
                                               ctypes.byref(self.g1), arr, prec, order, ctypes.byref(h)), ctx.handle)
         self.handle = h
+        ctx._users.add(self)
 
     def shape(self, n):
         g = self.g1 if n == 1 else self.grids[n - 2]
@@ -503,6 +509,7 @@ class Batch:
         _check(_native.lib().nvp_batch_create(ctx.handle, len(problems), arr, prec, order, ctypes.byref(h)),
                ctx.handle)
         self.handle = h
+        ctx._users.add(self)
 
     def set_graph(self, enable, branches=4):
         _check(_native.lib().nvp_batch_set_graph(self.handle, int(bool(enable)), branches), self.ctx.handle)
@@ -592,6 +599,7 @@ class BoxNet:
         h = ctypes.c_void_p()
         _check(_native.lib().nvp_boxnet_create(ctx.handle, self.max_batch, ctypes.byref(h)), ctx.handle)
         self.handle = h
+        ctx._users.add(self)
 
     def set_params(self, params):
         import numpy as np

@@ -460,3 +460,20 @@ def test_regrid_equals_a_fresh_plan(ctx, prec):
         assert oracle.rel_l2(host(got[n - 2]), ref[n]) < TOL[prec], n
     plan.close()
     fresh.close()
+
+
+def test_context_outlives_its_plans():
+    """The C ABI refuses to destroy a context a plan still uses (the plan's destroy call reaches
+    it); the binding's Context.close() destroys the context's plans first."""
+    c = P.Context(0)
+    h = oracle.spacing(2, F0, WATER["c0"])
+    g1 = oracle.grid_from_counts((15e-3, 0.0, 0.0), 2 * h, (10, 9, 8), (5, 4, 4))
+    g2 = oracle.grid_from_counts((15e-3, 0.0, 0.0), h, (12, 11, 10), (6, 5, 5))
+    plan = P.CascadePlan(c, WATER, F0, g1, [g2], prec=P.NVP_C64, order=3)
+    assert P._native.lib().nvp_ctx_destroy(c.handle) == 5  # NVP_E_STATE, nothing freed
+    p2 = plan.execute(torch.ones(tuple(g1.n), dtype=torch.complex64, device="cuda"))[0]
+    torch.cuda.synchronize()
+    assert torch.isfinite(torch.view_as_real(p2)).all()
+    c.close()
+    assert plan.handle is None and c.handle is None
+    plan.close()  # a no-op now
