@@ -4,6 +4,7 @@
 
 #include "passes_impl.hpp"
 #include "source.hpp"
+#include "source_wf.hpp"
 
 namespace nvp {
 
@@ -36,6 +37,17 @@ hipError_t launch_kradial(double2 *ktab, int64_t n, double h, double kr, double 
 
 template <typename R, int K, int NF>
 static hipError_t source_nf(const LdSource<R, K> &ld, const SourceArgs &a, void *out, int Ny, int cxl, hipStream_t s) {
+    if constexpr (source_wf(sizeof(R))) {
+        auto kern = k_source_wf<R, K, NF, NVP_SRC_PREW, NVP_SRC_CXM>;
+        constexpr size_t lds = SrcWfLds<R, K, NF, NVP_SRC_PREW, NVP_SRC_CXM>::BYTES;
+        if (lds != source_lds_bytes(NF, K, sizeof(R)) || cxl < 1 || cxl > NVP_SRC_CXM) return hipErrorInvalidValue;
+        if (lds > 98304) return hipErrorInvalidValue;
+        static const hipError_t attr = allow_lds(kern, lds);
+        if (attr != hipSuccess) return attr;
+        dim3 grid((unsigned)((a.Nz + 31) / 32), (unsigned)((Ny + 7) / 8), (unsigned)((a.Nx + cxl - 1) / cxl));
+        hipLaunchKernelGGL(kern, grid, dim3(NF * 64), lds, s, ld, static_cast<cx<R> *>(out), Ny, cxl);
+        return hipGetLastError();
+    }
     constexpr int RY = source_rows(sizeof(R)), PRE = source_pre(sizeof(R));
     auto kern = k_source<R, K, NF, NVP_SRC_TY, NVP_SRC_TZ, RY, PRE, NVP_SRC_CXM>;
     constexpr size_t lds = SrcLds<R, K, NF, NVP_SRC_TY, NVP_SRC_TZ, RY, PRE, NVP_SRC_CXM>::BYTES;

@@ -103,9 +103,20 @@ hipError_t launch_xsrc_c128(int L, const SourceArgs &a, const void *tw, hipStrea
 // Target rows per thread and block entries per thread, for reals of rsize bytes.
 constexpr int source_rows(size_t rsize) { return rsize == 4 ? NVP_SRC_RY32 : 1; }
 constexpr int source_pre(size_t rsize) { return source_rows(rsize) == 2 ? 3 : 2; }
+// 1: the source kernel with one wavefront per field (k_source_wf): tiles of
+// 8 x 32 columns, blocks of up to 64 NVP_SRC_PREW entries and 16 rows.
+#ifndef NVP_SRC_WF
+#define NVP_SRC_WF 1
+#endif
+#define NVP_SRC_PREW 7
+// Whether the source kernel of reals of rsize bytes is k_source_wf (complex64).
+constexpr bool source_wf(size_t rsize) { return NVP_SRC_WF && rsize == 4; }
 // LDS bytes of a launch for nf fields, K-point stencils and reals of rsize
 // bytes (4 or 8): the kernel's fixed layout.
 inline size_t source_lds_bytes(int nf, int K, size_t rsize) {
+    if (source_wf(rsize))
+        return (size_t)nf * (((size_t)NVP_SRC_PREW * 64 + 16 * 32 + 2 * 256) * 2 * rsize +
+                             (size_t)NVP_SRC_CXM * K * rsize + (size_t)NVP_SRC_CXM * sizeof(int));
     const size_t nt = (size_t)NVP_SRC_TY * NVP_SRC_TZ, ry = (size_t)source_rows(rsize);
     return (size_t)nf * (((size_t)source_pre(rsize) * nt + 2 * ry * nt) * 2 * rsize +
                          ((size_t)(NVP_SRC_TZ + ry * NVP_SRC_TY) * K + (size_t)NVP_SRC_CXM * K) * rsize +

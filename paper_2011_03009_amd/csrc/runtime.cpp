@@ -934,13 +934,13 @@ nvp_status nvp_volume_potential_box(nvp_ctx *ctx, double k_re, double k_im, cons
 // Target x planes per source-kernel workgroup: enough x chunks for about
 // `want` workgroups per launch (0: 2048, or the environment variable
 // NVP_SRC_WGS, read once), and at most SRC_CXM planes.
-int source_chunk(const int64_t n[3], size_t rsize, int64_t want = 0) {
+int source_chunk(const int64_t n[3], size_t rsize, int64_t want = 0, int nf = 4) {
     static const int64_t dflt = [] {
         const char *e = getenv("NVP_SRC_WGS");
         const long v = e ? atol(e) : 0;
         return v > 0 ? (int64_t)v : (int64_t)2048;
     }();
-    if (want <= 0) want = dflt;
+    if (want <= 0) want = nvp::source_wf(rsize) ? dflt * 4 / std::max(1, nf) : dflt;  // about 8192 wavefronts
     const int64_t ty = (int64_t)NVP_SRC_TY * nvp::source_rows(rsize);
     const int64_t tiles = ((n[1] + ty - 1) / ty) * ((n[2] + NVP_SRC_TZ - 1) / NVP_SRC_TZ);
     int64_t chunks = std::max<int64_t>(1, std::min<int64_t>((want + tiles - 1) / tiles, n[0]));
@@ -1057,10 +1057,10 @@ nvp_status plan_layout(nvp_ctx *ctx, nvp_plan *p, const nvp_grid *gn, std::vecto
             mblk = std::max(mblk, span[1] * span[2]);
         }
         const size_t lds = nvp::source_lds_bytes(h.n - 1, K, rsize);
-        h.src_cx = source_chunk(h.g.n, rsize);
-        h.src_lds = small && msy <= 2 * TY && mblk <= nvp::source_pre(rsize) * NVP_SRC_TY * TZ && lds <= 98304
-                        ? (int64_t)lds
-                        : 0;
+        h.src_cx = source_chunk(h.g.n, rsize, 0, h.n - 1);
+        const bool fits = nvp::source_wf(rsize) ? msy <= 16 && mblk <= 64 * NVP_SRC_PREW
+                                     : msy <= 2 * TY && mblk <= nvp::source_pre(rsize) * NVP_SRC_TY * TZ;
+        h.src_lds = small && fits && lds <= 98304 ? (int64_t)lds : 0;
     }
     *tbytes_out = tbytes;
     *maxA_out = maxA;
@@ -1605,7 +1605,9 @@ nvp_status autotune_plan(nvp_plan *plan, std::map<std::string, Tune> &cache, int
             const Tune base = best_t;
             for (int64_t want : {(int64_t)1024, (int64_t)4096}) {
                 Tune t = base;
-                t.src_cx = source_chunk(h.g.n, csize(plan->prec) / 2, want);
+                const size_t rs = csize(plan->prec) / 2;
+                t.src_cx = source_chunk(h.g.n, rs, nvp::source_wf(rs) ? want * 4 / std::max(1, h.n - 1) : want,
+                                        h.n - 1);
                 if (t.src_cx != h.src_cx && st == NVP_OK) try_choice(t);
             }
         }

@@ -1,13 +1,17 @@
-// Host emulation of the source kernel (paper_2011_03009_amd/csrc/source.hpp).
+// Host emulation of the source kernels: the streamed one
+// (paper_2011_03009_amd/csrc/source.hpp) and the one with a wavefront per
+// field (source_wf.hpp).
 //
 // The kernel body is compiled for the host: every workgroup of the launch
-// grid runs as TY x TZ host threads sharing a barrier (for __syncthreads) and
+// grid runs as host threads, one per work item, sharing a barrier (for
+// __syncthreads), one barrier per 64 of them (for wave_sync) and
 // an LDS array of exactly the size the launch gives it, filled with NaN so
 // that a read of an entry not written before it is seen.  Random monotone axis
 // tables (source planes advancing by 0, 1 or 2 per target voxel, clamped at
 // both ends, as interpolation onto finer, equal or coarser grids makes them),
 // random weights, fields on the target grid among them, ragged tiles in y and
-// z and ragged x chunks, one or two target rows per thread, in FP32 and FP64,
+// z and ragged x chunks, one or two target rows per thread of the streamed
+// kernel, in FP32 and FP64,
 // for K = 2 and 4 and 1 to 4 and 7
 // fields.  Each output is compared with the separable transfer and the
 // source product summed directly in long double, and must be written.  Built
@@ -23,19 +27,22 @@
 #include <cstdlib>
 #include <functional>
 #include <limits>
+#include <memory>
 #include <random>
 #include <thread>
 #include <vector>
 
 #include "hip/hip_runtime.h"
 
-static thread_local std::barrier<> *tl_bar = nullptr;
+static thread_local std::barrier<> *tl_bar = nullptr;       // the workgroup's threads
+static thread_local std::barrier<> *tl_wave_bar = nullptr;  // the wavefront's 64 threads
 void __syncthreads() { tl_bar->arrive_and_wait(); }
 namespace nvp {
-inline void wave_sync() { tl_bar->arrive_and_wait(); }  // not used by the source kernel
+inline void wave_sync() { tl_wave_bar->arrive_and_wait(); }
 }  // namespace nvp
 
 #include "source.hpp"
+#include "source_wf.hpp"
 
 using namespace nvp;
 using cld = std::complex<long double>;
@@ -78,8 +85,11 @@ std::vector<int> monotone_table(std::mt19937_64 &g, int n_t, int n_s, int K, dou
     return b;
 }
 
-template <typename R, int K, int NF, int RY, int PRE> struct Case {
-    static constexpr int TYT = RY * TY;  // target rows of a tile
+// WF: the kernel with one wavefront per field (k_source_wf; PRE is its block
+// entries per lane over 64 lanes); else the streamed kernel with RY rows per thread.
+template <typename R, int K, int NF, int RY, int PRE, bool WF = false> struct Case {
+    static constexpr int TYT = WF ? 8 : RY * TY;  // target rows of a tile
+    static constexpr int NTH = WF ? NF * 64 : TY * TZ;  // threads of a workgroup
     int N[3];
     std::vector<int> identity;
     std::vector<std::array<int, 3>> ns;
@@ -149,26 +159,33 @@ template <typename R, int K, int NF, int RY, int PRE> struct Case {
             msy = std::max(msy, sy);
             mblk = std::max(mblk, sy * sz);
         }
-        if (msy > 2 * TYT || mblk > PRE * TY * TZ) return false;  // the host takes the fused path
+        // beyond the kernel's limits the host takes the fused path
+        if (WF ? (msy > 16 || mblk > 64 * PRE) : (msy > 2 * TYT || mblk > PRE * TY * TZ)) return false;
         CHECK(cx_len <= CXM, "chunk %d beyond %d", cx_len, CXM);
         Buf<cx<R>> out((size_t)N[0] * N[1] * N[2]);
         const R nan = std::numeric_limits<R>::quiet_NaN();
         for (size_t e = 0; e < out.n; ++e) out[e].x = out[e].y = nan;
         const int gz = (N[2] + TZ - 1) / TZ, gy = (N[1] + TYT - 1) / TYT, gx = (N[0] + cx_len - 1) / cx_len;
-        using Lay = SrcLds<R, K, NF, TY, TZ, RY, PRE, CXM>;
-        const size_t lds_n = Lay::BYTES;
+        const size_t lds_n = WF ? SrcWfLds<R, K, NF, PRE, CXM>::BYTES : SrcLds<R, K, NF, TY, TZ, RY, PRE, CXM>::BYTES;
         for (int bx = 0; bx < gx; ++bx)
             for (int by = 0; by < gy; ++by)
                 for (int bz = 0; bz < gz; ++bz) {
                     // NaN in every real and int of the LDS: a read before its write shows
                     Buf<unsigned char> lds(lds_n);
                     for (size_t e = 0; e < lds_n; ++e) lds[e] = 0xff;
-                    std::barrier<> bar(TY * TZ);
+                    std::barrier<> bar(NTH);
+                    std::vector<std::unique_ptr<std::barrier<>>> wbar;
+                    for (int v = 0; v < (NTH + 63) / 64; ++v) wbar.emplace_back(new std::barrier<>(64));
                     std::vector<std::thread> th;
-                    for (int t = 0; t < TY * TZ; ++t)
+                    for (int t = 0; t < NTH; ++t)
                         th.emplace_back([&, t] {
                             tl_bar = &bar;
-                            source_tile<R, K, NF, TY, TZ, RY, PRE, CXM>(src, out.p, N[1], cx_len, lds.p, t, bz, by, bx);
+                            tl_wave_bar = wbar[t / 64].get();
+                            if constexpr (WF)
+                                source_tile_wf<R, K, NF, PRE, CXM>(src, out.p, N[1], cx_len, lds.p, t, bz, by, bx);
+                            else
+                                source_tile<R, K, NF, TY, TZ, RY, PRE, CXM>(src, out.p, N[1], cx_len, lds.p, t, bz,
+                                                                            by, bx);
                         });
                     for (auto &x : th) x.join();
                 }
@@ -215,7 +232,7 @@ template <typename R, int K, int NF, int RY, int PRE> struct Case {
     }
 };
 
-template <typename R, int K, int NF, int RY = 1, int PRE = 2> int cases(unsigned seed) {
+template <typename R, int K, int NF, int RY = 1, int PRE = 2, bool WF = false> int cases(unsigned seed) {
     std::mt19937_64 g(seed);
     const long double tol = sizeof(R) == 8 ? 1e-12L : 1e-5L;
     // (Nx, Ny, Nz, x chunk, P(no advance), P(advance by 2))
@@ -232,7 +249,7 @@ template <typename R, int K, int NF, int RY = 1, int PRE = 2> int cases(unsigned
     };
     int ran = 0;
     for (const Shape &s : shapes) {
-        Case<R, K, NF, RY, PRE> c;
+        Case<R, K, NF, RY, PRE, WF> c;
         c.N[0] = s.nx;
         c.N[1] = s.ny;
         c.N[2] = s.nz;
@@ -257,7 +274,16 @@ int main() {
     n += cases<float, 4, 4, 2, 3>(12);
     n += cases<float, 2, 3, 2, 3>(13);
     n += cases<double, 4, 3, 2, 3>(14);
-    CHECK(n >= 60, "only %d cases fit the kernel's limits", n);
+    // one wavefront per field
+    n += cases<float, 4, 1, 1, 7, true>(21);
+    n += cases<float, 4, 2, 1, 7, true>(22);
+    n += cases<float, 4, 3, 1, 7, true>(23);
+    n += cases<float, 4, 4, 1, 7, true>(24);
+    n += cases<float, 4, 7, 1, 7, true>(25);
+    n += cases<float, 2, 3, 1, 7, true>(26);
+    n += cases<double, 4, 4, 1, 7, true>(27);
+    n += cases<double, 2, 2, 1, 7, true>(28);
+    CHECK(n >= 100, "only %d cases fit the kernel's limits", n);
     std::printf("OK %d\n", n);
     return 0;
 }
