@@ -40,25 +40,29 @@ static hipError_t source_nf(const LdSource<R, K> &ld, const SourceArgs &a, void 
     if constexpr (source_wf(sizeof(R))) {
         auto kern = k_source_wf<R, K, NF, NVP_SRC_PREW, NVP_SRC_CXM>;
         constexpr size_t lds = SrcWfLds<R, K, NF, NVP_SRC_PREW, NVP_SRC_CXM>::BYTES;
-        if (lds != source_lds_bytes(NF, K, sizeof(R)) || cxl < 1 || cxl > NVP_SRC_CXM) return hipErrorInvalidValue;
+        static_assert(lds == source_lds_bytes(NF, K, sizeof(R)), "the host sizes this kernel's LDS layout");
+        if (cxl < 1 || cxl > NVP_SRC_CXM) return hipErrorInvalidValue;
         if (lds > 98304) return hipErrorInvalidValue;
         static const hipError_t attr = allow_lds(kern, lds);
         if (attr != hipSuccess) return attr;
         dim3 grid((unsigned)((a.Nz + 31) / 32), (unsigned)((Ny + 7) / 8), (unsigned)((a.Nx + cxl - 1) / cxl));
         hipLaunchKernelGGL(kern, grid, dim3(NF * 64), lds, s, ld, static_cast<cx<R> *>(out), Ny, cxl);
         return hipGetLastError();
+    } else {
+        constexpr int RY = source_rows(sizeof(R)), PRE = source_pre(sizeof(R));
+        auto kern = k_source<R, K, NF, NVP_SRC_TY, NVP_SRC_TZ, RY, PRE, NVP_SRC_CXM>;
+        constexpr size_t lds = SrcLds<R, K, NF, NVP_SRC_TY, NVP_SRC_TZ, RY, PRE, NVP_SRC_CXM>::BYTES;
+        static_assert(lds == source_lds_bytes(NF, K, sizeof(R)), "the host sizes this kernel's LDS layout");
+        if (cxl < 1 || cxl > NVP_SRC_CXM) return hipErrorInvalidValue;
+        if (lds > 98304) return hipErrorInvalidValue;
+        static const hipError_t attr = allow_lds(kern, lds);
+        if (attr != hipSuccess) return attr;
+        dim3 grid((unsigned)((a.Nz + NVP_SRC_TZ - 1) / NVP_SRC_TZ),
+                  (unsigned)((Ny + RY * NVP_SRC_TY - 1) / (RY * NVP_SRC_TY)), (unsigned)((a.Nx + cxl - 1) / cxl));
+        hipLaunchKernelGGL(kern, grid, dim3(NVP_SRC_TY * NVP_SRC_TZ), lds, s, ld, static_cast<cx<R> *>(out), Ny,
+                           cxl);
+        return hipGetLastError();
     }
-    constexpr int RY = source_rows(sizeof(R)), PRE = source_pre(sizeof(R));
-    auto kern = k_source<R, K, NF, NVP_SRC_TY, NVP_SRC_TZ, RY, PRE, NVP_SRC_CXM>;
-    constexpr size_t lds = SrcLds<R, K, NF, NVP_SRC_TY, NVP_SRC_TZ, RY, PRE, NVP_SRC_CXM>::BYTES;
-    if (lds != source_lds_bytes(NF, K, sizeof(R)) || cxl < 1 || cxl > NVP_SRC_CXM) return hipErrorInvalidValue;
-    if (lds > 98304) return hipErrorInvalidValue;
-    static const hipError_t attr = allow_lds(kern, lds);
-    if (attr != hipSuccess) return attr;
-    dim3 grid((unsigned)((a.Nz + NVP_SRC_TZ - 1) / NVP_SRC_TZ),
-              (unsigned)((Ny + RY * NVP_SRC_TY - 1) / (RY * NVP_SRC_TY)), (unsigned)((a.Nx + cxl - 1) / cxl));
-    hipLaunchKernelGGL(kern, grid, dim3(NVP_SRC_TY * NVP_SRC_TZ), lds, s, ld, static_cast<cx<R> *>(out), Ny, cxl);
-    return hipGetLastError();
 }
 
 template <typename R, int K>

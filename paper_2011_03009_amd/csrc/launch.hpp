@@ -113,7 +113,7 @@ constexpr int source_pre(size_t rsize) { return source_rows(rsize) == 2 ? 3 : 2;
 constexpr bool source_wf(size_t rsize) { return NVP_SRC_WF && rsize == 4; }
 // LDS bytes of a launch for nf fields, K-point stencils and reals of rsize
 // bytes (4 or 8): the kernel's fixed layout.
-inline size_t source_lds_bytes(int nf, int K, size_t rsize) {
+constexpr size_t source_lds_bytes(int nf, int K, size_t rsize) {
     if (source_wf(rsize))
         return (size_t)nf * (((size_t)NVP_SRC_PREW * 64 + 16 * 32 + 2 * 256) * 2 * rsize +
                              (size_t)NVP_SRC_CXM * K * rsize + (size_t)NVP_SRC_CXM * sizeof(int));
