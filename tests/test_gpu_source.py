@@ -114,3 +114,40 @@ def test_set_tuning_rejects_bad_choices(ctx):
         assert plan.tuning(2)["src"] == 0
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("prec", [P.NVP_C64, P.NVP_C128])
+def test_source_kernel_up_to_seven_fields(ctx, prec):
+    """Harmonics 6..8, the source term of five to seven lower fields (the most the library takes),
+    each p_m on its own coarser grid at lambda_m / 6.  In complex64 the kernel with a wavefront per
+    field runs them; in complex128 a field's LDS share of the streamed kernel allows at most four
+    fields, so these grids take the fused path and the source-term call reports it."""
+    h8 = oracle.spacing(8, F0, WATER["c0"])
+    n8 = (21, 17, 45)
+    tgt = oracle.grid_from_counts(FOCUS, h8, n8, tuple(v // 2 for v in n8))
+    g = []
+    for m in range(1, 8):
+        cnt = tuple(-(-v * m // 8) + 4 for v in n8)
+        g.append(oracle.grid_from_counts(FOCUS, h8 * 8 / m, cnt, tuple(v // 2 for v in cnt)))
+    g.append(tgt)
+    flds = [fields.smooth_field(gm.n, 60 + m) * 10 ** (3 - 0.5 * m) + 1e-3 * fields.random_field(gm.n, 70 + m)
+            for m, gm in enumerate(g, start=1)]
+    plan = P.CascadePlan(ctx, WATER, F0, g[0], g[1:], prec=prec, order=3)
+    try:
+        for n in (6, 7, 8):
+            args = [dev(flds[m - 1], prec) for m in range(1, n)]
+            if prec == P.NVP_C128:
+                say("case source many-fields n=%d prec=%d expect unsupported" % (n, prec))
+                with pytest.raises(P.NvpError) as e:
+                    plan.source_term(n, args)
+                assert e.value.status == E_UNSUPPORTED
+                continue
+            v = {m: oracle.transfer(flds[m - 1], g[m - 1], g[n - 1], 3) for m in range(1, n)}
+            ref = oracle.source_term(n, v)
+            for cx in (0, 1):
+                say("case source many-fields n=%d prec=%d cx=%d" % (n, prec, cx))
+                plan.set_tuning(n, src=1, src_cx=cx)
+                f = host(plan.source_term(n, args))
+                assert oracle.rel_l2(f, ref) < TOL[prec], (n, cx)
+    finally:
+        plan.close()
