@@ -477,3 +477,28 @@ def test_context_outlives_its_plans():
     c.close()
     assert plan.handle is None and c.handle is None
     plan.close()  # a no-op now
+
+
+@pytest.mark.parametrize("prec", [P.NVP_C128, P.NVP_C64])
+def test_eight_harmonic_cascade_matches_oracle(ctx, prec):
+    """The longest cascade the library takes, p2..p8 (up to seven lower fields per source term), each
+    harmonic from the plan's own chained outputs, against the oracle's direct-sum cascade at every
+    voxel.  In complex64 the source terms of p6..p8 run in the kernel with a wavefront per field; in
+    complex128 they take the fused path."""
+    focus = (15e-3, 0.0, 0.0)
+    c0 = WATER["c0"]
+    g1 = oracle.grid_from_counts(focus, oracle.spacing(1, F0, c0), (10, 9, 8), (5, 4, 4))
+    gn = {n: oracle.grid_from_counts(focus, oracle.spacing(n, F0, c0), (8 + 2 * n, 12, 16), (4 + n, 6, 8))
+          for n in range(2, 9)}
+    say("case eight-harmonic cascade prec=%d" % prec)
+    k1 = oracle.wavenumber(1, F0, WATER)
+    pts = bowl.bowl_points(7.5e-3, 15e-3, 128, 1)
+    p1 = bowl.incident_field(pts, 7.5e-3, 15e-3, k1, 1e6, g1.coords(0), g1.coords(1), g1.coords(2)).numpy()
+    plan = P.CascadePlan(ctx, WATER, F0, g1, [gn[n] for n in range(2, 9)], prec=prec, order=3)
+    try:
+        outs = plan.execute(dev(p1, prec))
+        ref = oracle.cascade(p1, g1, gn, F0, WATER, 3, method="direct")
+        for n in range(2, 9):
+            assert oracle.rel_l2(host(outs[n - 2]), ref[n]) < TOL[prec], n
+    finally:
+        plan.close()
