@@ -146,8 +146,14 @@ __device__ __forceinline__ void strided_tile(Ld ld, St st, const cx<R> *__restri
     }
 }
 
+// Waves per SIMD the FP64 mirror passes are compiled for, where their LDS
+// allows more workgroups per CU than their registers otherwise would.
+template <typename R, int L, bool MIRROR> constexpr int strided_min_waves() {
+    return (sizeof(R) == 8 && MIRROR) ? (L == 512 ? 4 : (L == 768 ? 3 : 1)) : 1;
+}
+
 template <typename R, int L, int T, int SG, bool MIRROR, class Ld, class St>
-__global__ void __launch_bounds__(T *col_threads<R>(L))
+__global__ void __launch_bounds__(T *col_threads<R>(L), (strided_min_waves<R, L, MIRROR>()))
 k_strided(Ld ld, St st, const cx<R> *__restrict__ tw, int64_t inner) {
     strided_tile<R, L, T, SG, MIRROR>(ld, st, tw, inner, blockIdx.x, blockIdx.y);
 }
