@@ -530,7 +530,7 @@ def main():
                     help="only copy 1 GiB device-to-device 3 times (a known-size reference for HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; every configuration fits one MI355X "
+        print("bench.py: measures one GPU only; every configuration fits one MI355X "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 

@@ -46,7 +46,7 @@ typedef int32_t nvp_status;
 #define NVP_E_INVALID 1     /* bad argument: null pointer, h <= 0, n < 1, bad precision, ... */
 #define NVP_E_NOMEM 2       /* device or host allocation failed; no partial state kept */
 #define NVP_E_HIP 3         /* a HIP runtime call or kernel launch failed */
-#define NVP_E_UNSUPPORTED 4 /* valid request outside what this build handles: an axis beyond 4096 voxels, a grid beyond a fixed scratch, a transfer order other than 1 or 3, the source kernel for grids only the fused path takes */
+#define NVP_E_UNSUPPORTED 4 /* valid request outside what the library handles: an axis beyond 4096 voxels, a grid beyond a fixed scratch, a transfer order other than 1 or 3, the source kernel for grids only the fused path takes */
 #define NVP_E_STATE 5       /* call out of order (e.g. timing read while disabled) */
 /* Fault injection for tests: with the environment variable
  * NVP_DEVICE_ALLOC_LIMIT set to a byte count, every device allocation of the
